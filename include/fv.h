@@ -1,0 +1,147 @@
+/*
+ * fv.h -- C ABI of the MI355X (gfx950) visibility simulator.
+ *
+ * The library evaluates, for every frequency nu_f and antenna pair i <= j,
+ *
+ *     V_f(i,j) = sum_s beam[f][s] * flux[f][s]
+ *                      * exp(-2 pi i (nu_f / c) (x_i - x_j) . s_hat_s)
+ *
+ * (paper section 2.2: the point-source form of the measurement equation,
+ * rewritten as a type-3 non-uniform FFT from sources s_j to target modes
+ * x_k = -2 pi nu b_k / c; the pair orientation b_ij = x_i - x_j follows the
+ * per-antenna phasor factorisation of section 5.1), either with the type-3
+ * NUFFT (spread with the ES kernel, oversampled FFT, deconvolve and
+ * interpolate; section 2.2 steps 1-3) or with a direct sum.
+ *
+ * Conventions for every entry point
+ *   ant_enu  [n_ant][3]  antenna positions, metres, East/North/Up, FP64.
+ *   src_lmn  [n_src][3]  unit direction vectors (l=East, m=North, n=Up), FP64;
+ *                        |s| must be 1 within 1e-9.  No horizon cut is made.
+ *   freq_hz  [n_freq]    frequencies, Hz, > 0.
+ *   flux     [n_freq][n_src]  Stokes-I flux (any sign), FP64.
+ *   beam     [n_freq][n_src]  real beam weight applied as-is (the source
+ *                        strength is beam*flux); NULL means 1.
+ *   vis      [n_freq][n_ant*(n_ant+1)/2] complex128 (interleaved re, im),
+ *                        pairs (i <= j) in row-major order (autos included).
+ *   eps      requested relative l2 error of the whole output of the call
+ *            (all frequencies, all pairs) against the exact sum;
+ *            1e-14 <= eps <= 1e-1.
+ *
+ * Ownership: the caller owns every input and output buffer; the context owns
+ * every device buffer it allocates.  On any non-OK status the output is left
+ * untouched.  Status codes are returned; nothing aborts across the ABI.
+ * A context serves one host thread, except the server entry points, which
+ * are thread-safe.
+ */
+#ifndef FV_H
+#define FV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FV_OK = 0,
+    FV_EINVAL = -1,        /* bad size, pointer, non-finite value, eps out of range */
+    FV_ENOMEM = -2,        /* footprint above the context's HBM budget or allocation failed */
+    FV_EDEVICE = -3,       /* a HIP call failed; the context stays usable */
+    FV_EUNSUPPORTED = -4,  /* e.g. FP32 forced with eps < 1e-6 */
+    FV_EBUSY = -5,         /* server not running / already running / queue full */
+    FV_ECANCELLED = -6,    /* request dropped by fv_server_stop */
+    FV_ETIMEOUT = -7       /* fv_wait timed out; the ticket stays valid */
+} fv_status;
+
+/* flags (bitwise or) */
+#define FV_DIM_AUTO        0x0u   /* 2-D if the array is flat within the eps tolerance, else 3-D */
+#define FV_DIM_2D          0x1u   /* force u*l + v*m (the Up terms are dropped) */
+#define FV_DIM_3D          0x2u   /* force u*l + v*m + w*n */
+#define FV_DIM_MASK        0x3u
+#define FV_PREC_AUTO       0x0u   /* FP32 grids if eps >= 1e-6, else FP64 */
+#define FV_PREC_FP32       0x4u
+#define FV_PREC_FP64       0x8u
+#define FV_PREC_MASK       0xCu
+#define FV_METHOD_NUFFT    0x00u  /* type-3 NUFFT (default) */
+#define FV_METHOD_DIRECT   0x10u  /* direct sum, one thread per pair (vector ALU) */
+#define FV_METHOD_MFMA     0x20u  /* direct sum as V = Z diag(c) Z^H on matrix cores */
+#define FV_METHOD_MASK     0x30u
+#define FV_NO_FOLD         0x100u /* do not reflect targets into a half-space */
+
+typedef struct fv_ctx fv_ctx;
+
+typedef struct {
+    int n_ant;  const double *ant_enu;
+    int n_src;  const double *src_lmn;
+    int n_freq; const double *freq_hz;
+    const double *flux;
+    const double *beam;     /* NULL => 1 */
+    double eps;
+    unsigned flags;
+} fv_problem;
+
+typedef struct {
+    int dim;              /* 2 or 3 */
+    int prec_bits;        /* 32 or 64 (grid arithmetic) */
+    int method;           /* FV_METHOD_* */
+    int w;                /* kernel points per dimension */
+    int fold_axis;        /* -1 when targets are not reflected */
+    int n1[3], n2[3];     /* spreading / FFT grid of the highest frequency */
+    double t_total_ms;    /* wall time of the call (host clock, includes sync) */
+    double model_bytes;   /* algorithmic HBM bytes of the grid stages (all frequencies) */
+    double src_pairs;     /* n_src * n_pairs * n_freq */
+} fv_report;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes = 0 means 90%
+ * of the device's free memory.  Returns FV_EDEVICE if the device is absent. */
+fv_status fv_create(int device, size_t hbm_budget_bytes, fv_ctx **out);
+void fv_destroy(fv_ctx *ctx);
+/* Message for the last non-OK status returned on the calling thread. */
+const char *fv_last_error(void);
+
+/* Host buffers in, host buffer out (blocking).  rep may be NULL. */
+fv_status fv_simulate(fv_ctx *ctx, const fv_problem *p, double *vis, fv_report *rep);
+
+/* Device buffers in and out: every array pointer in *p and vis are device
+ * pointers on the context's device.  The work is enqueued on `stream`
+ * (a hipStream_t; NULL = the null stream).  The call blocks only for the few
+ * scalars planning needs (antenna positions, frequencies, the source box);
+ * the buffers must stay alive until the stream has completed the work. */
+fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *stream, fv_report *rep);
+
+/* Many snapshots (each a problem with its own sources, frequencies and
+ * array) in one batched launch sequence; host buffers; vis[i] is the output
+ * of snaps[i].  rep (nullable) receives the report of the whole batch. */
+fv_status fv_simulate_batch(fv_ctx *ctx, int n_snap, const fv_problem *snaps, double *const *vis,
+                            fv_report *rep);
+
+/* Serving loop: a worker thread admits submitted requests while HBM (the
+ * context budget) and one of max_slots slots are free, and runs admitted
+ * requests concurrently on per-slot streams.  Host buffers, which must stay
+ * alive until fv_wait returns FV_OK / FV_ECANCELLED / an error for the
+ * ticket. */
+fv_status fv_server_start(fv_ctx *ctx, int max_slots);
+fv_status fv_submit(fv_ctx *ctx, const fv_problem *p, double *vis, uint64_t *ticket);
+/* timeout_s < 0 waits forever.  rep (nullable) receives the request's report
+ * with t_total_ms = submit -> completion latency. */
+fv_status fv_wait(fv_ctx *ctx, uint64_t ticket, double timeout_s, fv_report *rep);
+fv_status fv_server_stop(fv_ctx *ctx);
+
+/* Diagnostic entry point for stage-by-stage checks of the NUFFT path
+ * (section 2.2 steps 1-3) on one frequency `f` of a host problem.
+ * Writes the plan scalars and, when the buffers are non-NULL and large
+ * enough, copies out (as complex128):
+ *   spread:  the deconvolved spreading grid b~, [n1z][n1y][n1x];
+ *   fftout:  the pruned FFT output, [Mz][My][Mx], element (o) holding
+ *            grid index p = o - P (mod n2) along each axis.
+ * plan_out[0..]: dim, w, fold_axis, n1[3], n2[3], M[3], P[3] as doubles,
+ *   then s_c[3], S[3], b_c[3], B[3]  (31 doubles).
+ * Returns FV_EINVAL if the buffers are too small (sizes are in plan_out). */
+fv_status fv_debug_stages(fv_ctx *ctx, const fv_problem *p, int f, double *plan_out,
+                          double *spread, size_t spread_cap, double *fftout, size_t fftout_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FV_H */

@@ -1,0 +1,234 @@
+"""Python binding of libfv.so, the MI355X type-3 NUFFT visibility simulator.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/fv.h``.  There is no CPU
+fallback; importing this package raises if the library has not been built.
+
+    import paper_2506_02130_amd as fv
+    ctx = fv.Context()
+    vis = ctx.simulate(ant_enu, src_lmn, freq_hz, flux, beam, eps=1e-6)   # [n_freq, n_pairs] complex128
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfv.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY, ECANCELLED, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "EBUSY",
+                -6: "ECANCELLED", -7: "ETIMEOUT"}
+
+DIM_AUTO, DIM_2D, DIM_3D = 0x0, 0x1, 0x2
+PREC_AUTO, PREC_FP32, PREC_FP64 = 0x0, 0x4, 0x8
+METHOD_NUFFT, METHOD_DIRECT, METHOD_MFMA = 0x00, 0x10, 0x20
+NO_FOLD = 0x100
+
+ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
+               "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_debug_stages")
+
+
+class FvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_ant", ctypes.c_int), ("ant_enu", ctypes.c_void_p),
+                ("n_src", ctypes.c_int), ("src_lmn", ctypes.c_void_p),
+                ("n_freq", ctypes.c_int), ("freq_hz", ctypes.c_void_p),
+                ("flux", ctypes.c_void_p), ("beam", ctypes.c_void_p),
+                ("eps", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("prec_bits", ctypes.c_int), ("method", ctypes.c_int), ("w", ctypes.c_int),
+                ("fold_axis", ctypes.c_int), ("n1", ctypes.c_int * 3), ("n2", ctypes.c_int * 3),
+                ("t_total_ms", ctypes.c_double), ("model_bytes", ctypes.c_double), ("src_pairs", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"dim": self.dim, "prec_bits": self.prec_bits, "method": self.method, "w": self.w,
+                "fold_axis": self.fold_axis, "n1": list(self.n1), "n2": list(self.n2),
+                "t_total_ms": self.t_total_ms, "model_bytes": self.model_bytes, "src_pairs": self.src_pairs}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                          "(hipcc for gfx950); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp, dp = ctypes.c_void_p, P(ctypes.c_double)
+    lib.fv_create.argtypes = [ctypes.c_int, ctypes.c_size_t, P(vp)]
+    lib.fv_destroy.argtypes = [vp]
+    lib.fv_destroy.restype = None
+    lib.fv_last_error.restype = ctypes.c_char_p
+    lib.fv_last_error.argtypes = []
+    lib.fv_simulate.argtypes = [vp, P(Problem), vp, P(Report)]
+    lib.fv_simulate_dev.argtypes = [vp, P(Problem), vp, vp, P(Report)]
+    lib.fv_simulate_batch.argtypes = [vp, ctypes.c_int, P(Problem), P(vp), P(Report)]
+    lib.fv_server_start.argtypes = [vp, ctypes.c_int]
+    lib.fv_submit.argtypes = [vp, P(Problem), vp, P(ctypes.c_uint64)]
+    lib.fv_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, P(Report)]
+    lib.fv_server_stop.argtypes = [vp]
+    lib.fv_debug_stages.argtypes = [vp, P(Problem), ctypes.c_int, dp, vp, ctypes.c_size_t, vp, ctypes.c_size_t]
+    for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
+                 "fv_submit", "fv_wait", "fv_server_stop", "fv_debug_stages"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(status: int):
+    if status != OK:
+        raise FvError(status, (_lib.fv_last_error() or b"").decode())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class HostProblem:
+    """Keeps the contiguous FP64 copies alive while the C struct points at them."""
+
+    def __init__(self, ant_enu, src_lmn, freq_hz, flux, beam=None, eps: float = 1e-6, flags: int = 0):
+        self.ant = _f64(ant_enu).reshape(-1, 3)
+        self.src = _f64(src_lmn).reshape(-1, 3)
+        self.freq = _f64(freq_hz).reshape(-1)
+        n_freq, n_src = self.freq.shape[0], self.src.shape[0]
+        self.flux = _f64(flux).reshape(n_freq, n_src)
+        self.beam = None if beam is None else _f64(beam).reshape(n_freq, n_src)
+        self.n_pairs = self.ant.shape[0] * (self.ant.shape[0] + 1) // 2
+        ptr = lambda a: None if a is None or a.size == 0 else a.ctypes.data
+        self.c = Problem(self.ant.shape[0], ptr(self.ant), n_src, ptr(self.src), n_freq, ptr(self.freq),
+                         ptr(self.flux), ptr(self.beam), float(eps), int(flags))
+
+    @classmethod
+    def of(cls, p, eps: Optional[float] = None, flags: int = 0) -> "HostProblem":
+        """From any object with ant_enu, src_lmn, freq_hz, flux, beam, eps attributes."""
+        return cls(p.ant_enu, p.src_lmn, p.freq_hz, p.flux, p.beam, p.eps if eps is None else eps, flags)
+
+
+class Context:
+    """One fv_ctx on a HIP device; owns its device memory and caches."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.fv_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.last_report: Optional[dict] = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------ host API
+    def simulate(self, ant_enu, src_lmn, freq_hz, flux, beam=None, eps: float = 1e-6, flags: int = 0) -> np.ndarray:
+        hp = HostProblem(ant_enu, src_lmn, freq_hz, flux, beam, eps, flags)
+        return self.simulate_problem(hp)
+
+    def simulate_problem(self, hp: HostProblem) -> np.ndarray:
+        out = np.empty((hp.freq.shape[0], hp.n_pairs, 2), dtype=np.float64)
+        rep = Report()
+        _check(_lib.fv_simulate(self._h, ctypes.byref(hp.c), out.ctypes.data, ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return out[..., 0] + 1j * out[..., 1]
+
+    # ------------------------------------------------------------------ device API
+    def simulate_dev(self, ant_enu, src_lmn, freq_hz, flux, beam, vis, eps: float = 1e-6, flags: int = 0,
+                     stream=None) -> dict:
+        """All arguments are torch tensors on this context's device (float64,
+        contiguous); ``vis`` is float64 [n_freq, n_pairs, 2].  The work is
+        enqueued on ``stream`` (a torch.cuda.Stream, default: torch's current
+        stream); returns the report."""
+        import torch
+        for name, t in (("ant_enu", ant_enu), ("src_lmn", src_lmn), ("freq_hz", freq_hz), ("flux", flux),
+                        ("vis", vis)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
+        if beam is not None and not (beam.is_cuda and beam.dtype == torch.float64 and beam.is_contiguous()):
+            raise ValueError("beam must be a contiguous float64 device tensor")
+        n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
+        if vis.numel() != 2 * n_freq * n_ant * (n_ant + 1) // 2:
+            raise ValueError("vis has the wrong size")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        c = Problem(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
+                    freq_hz.data_ptr(), flux.data_ptr() if n_src else None,
+                    None if beam is None else beam.data_ptr(), float(eps), int(flags))
+        rep = Report()
+        _check(_lib.fv_simulate_dev(self._h, ctypes.byref(c), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
+                                    ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return self.last_report
+
+    # ------------------------------------------------------------------ batch API
+    def simulate_batch(self, problems: Sequence[HostProblem]) -> list:
+        n = len(problems)
+        arr = (Problem * n)(*[p.c for p in problems])
+        outs = [np.empty((p.freq.shape[0], p.n_pairs, 2), dtype=np.float64) for p in problems]
+        ptrs = (ctypes.c_void_p * n)(*[o.ctypes.data for o in outs])
+        rep = Report()
+        _check(_lib.fv_simulate_batch(self._h, n, arr, ptrs, ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return [o[..., 0] + 1j * o[..., 1] for o in outs]
+
+    # ------------------------------------------------------------------ serving
+    def server_start(self, max_slots: int = 4):
+        _check(_lib.fv_server_start(self._h, int(max_slots)))
+
+    def submit(self, hp: HostProblem, out: np.ndarray) -> int:
+        t = ctypes.c_uint64()
+        _check(_lib.fv_submit(self._h, ctypes.byref(hp.c), out.ctypes.data, ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        rep = Report()
+        st = _lib.fv_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(rep))
+        return st, rep.as_dict()
+
+    def server_stop(self):
+        _check(_lib.fv_server_stop(self._h))
+
+    # ------------------------------------------------------------------ diagnostics
+    def debug_stages(self, hp: HostProblem, f: int = 0):
+        """Plan scalars, the deconvolved spreading grid and the pruned FFT
+        output of frequency ``f`` (complex128, axes ordered z, y, x)."""
+        plan = np.zeros(31, dtype=np.float64)
+        _check(_lib.fv_debug_stages(self._h, ctypes.byref(hp.c), int(f),
+                                    plan.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0, None, 0))
+        n1 = plan[3:6].astype(int)
+        M = plan[9:12].astype(int)
+        spread = np.empty((int(np.prod(n1)), 2))
+        fft = np.empty((int(np.prod(M)), 2))
+        _check(_lib.fv_debug_stages(self._h, ctypes.byref(hp.c), int(f),
+                                    plan.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), spread.ctypes.data,
+                                    spread.shape[0], fft.ctypes.data, fft.shape[0]))
+        dim = int(plan[0])
+        info = {"dim": dim, "w": int(plan[1]), "fold_axis": int(plan[2]), "n1": n1[:dim].tolist(),
+                "n2": plan[6:9].astype(int)[:dim].tolist(), "M": M[:dim].tolist(),
+                "P": plan[12:15].astype(int)[:dim].tolist(), "s_c": plan[15:18][:dim].copy(),
+                "S": plan[18:21][:dim].copy(), "b_c": plan[21:24][:dim].copy(), "B": plan[24:27][:dim].copy(),
+                "prec_bits": int(plan[27]), "X": plan[28:31][:dim].copy()}
+        shape1 = tuple(int(v) for v in n1[:dim][::-1])
+        shapeM = tuple(int(v) for v in M[:dim][::-1])
+        return info, (spread[:, 0] + 1j * spread[:, 1]).reshape(shape1), (fft[:, 0] + 1j * fft[:, 1]).reshape(shapeM)

@@ -1,0 +1,75 @@
+// The context object behind the opaque fv_ctx handle.
+#pragma once
+
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "fv_internal.h"
+
+namespace fv {
+
+// Device pointers of one problem's inputs plus the host-side source box.
+struct DevInputs {
+    const double *ant = nullptr, *src = nullptr, *flux = nullptr, *beam = nullptr;
+    double *vis = nullptr;
+    double s_c[3] = {0, 0, 0}, S[3] = {0, 0, 0};
+};
+
+// A stream with its own workspace and input arenas.
+struct Slot {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Arena arena;   // NUFFT workspace
+    Arena inputs;  // uploaded inputs and the device output
+    ~Slot();
+};
+
+struct Server;  // serving loop state (server.cpp)
+
+}  // namespace fv
+
+struct fv_ctx {
+    int device = 0;
+    size_t budget = 0;       // HBM budget in bytes
+    size_t chunk_bytes = 0;  // NUFFT workspace cap per launch group
+    fv::Slot main;
+    fv::DevCache cache;
+    std::mutex geo_mu;
+    std::vector<std::pair<uint64_t, fv::GeomPlan>> geos;
+    std::list<std::shared_ptr<fv::TargetTable>> targets;
+    double *scalar_buf = nullptr;
+    fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
+    double *scalars(hipStream_t) {
+        if (!scalar_buf) FV_HIP(hipMalloc((void **)&scalar_buf, 8 * sizeof(double)));
+        return scalar_buf;
+    }
+    ~fv_ctx();
+};
+
+namespace fv {
+
+GeomPlan ctx_geometry(fv_ctx *ctx, const double *ant_host, int n_ant, int dim, double eps, const double *s_c,
+                      const double *S, bool fold);
+std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, const double *ant_dev,
+                                         const GeomPlan &g, hipStream_t st);
+void validate_host(const fv_problem *p);
+DevInputs upload(Slot &slot, const fv_problem *p, double *s_c, double *S);
+void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevInputs &in, double *vis_dev,
+                fv_report *rep);
+void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv_report *rep);
+const char *last_error_cstr();
+void set_last_error(const std::string &msg);
+
+// Stage outputs of a single snapshot for the diagnostic entry point
+// (complex128, host): the deconvolved spreading grid and the pruned FFT output.
+void nufft_debug(const SnapJob &job, int dim, int prec_bits, int w, Arena &arena, DevCache &cache, double *spread,
+                 double *fftout, hipStream_t s);
+
+}  // namespace fv

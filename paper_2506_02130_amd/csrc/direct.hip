@@ -1,0 +1,164 @@
+// Direct evaluation of the point-source sum (paper section 2.2, the sum the
+// type-3 transform replaces): one thread per (frequency, pair), sources
+// staged through LDS in chunks of 256.  The phase of every term is formed in
+// FP64 in turns, reduced exactly to [-1/2, 1/2], then passed to sin/cos; in
+// FP32 mode the terms of one chunk are summed in FP32 and the chunk sums in
+// FP64.  Plus small utility kernels (input checks, zero fill).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dev_common.h"
+#include "fv_internal.h"
+
+namespace fv {
+namespace {
+
+template <int D, typename ACC>
+__global__ __launch_bounds__(256) void k_direct(const double *ant, int n_ant, long long n_pairs, const double *src,
+                                                int n_src, const double *flux, const double *beam, double kturn,
+                                                double *out) {
+    __shared__ double sl[256], sm[256], sn[256], sc[256];
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    double u = 0, v = 0, w = 0;
+    if (p < n_pairs) {
+        int i, j;
+        pair_decode(p, n_ant, &i, &j);
+        // phase turns of source s: -(nu/c) (x_i - x_j) . s
+        u = -kturn * (ant[3 * (size_t)i + 0] - ant[3 * (size_t)j + 0]);
+        v = -kturn * (ant[3 * (size_t)i + 1] - ant[3 * (size_t)j + 1]);
+        w = D == 3 ? -kturn * (ant[3 * (size_t)i + 2] - ant[3 * (size_t)j + 2]) : 0.0;
+    }
+    double accr = 0.0, acci = 0.0;
+    for (int s0 = 0; s0 < n_src; s0 += 256) {
+        const int s = s0 + threadIdx.x;
+        if (s < n_src) {
+            sl[threadIdx.x] = src[3 * (size_t)s + 0];
+            sm[threadIdx.x] = src[3 * (size_t)s + 1];
+            sn[threadIdx.x] = src[3 * (size_t)s + 2];
+            sc[threadIdx.x] = beam ? flux[s] * beam[s] : flux[s];
+        }
+        __syncthreads();
+        const int cnt = min(256, n_src - s0);
+        ACC pr = 0, pi = 0;
+        for (int k = 0; k < cnt; ++k) {
+            double t = u * sl[k] + v * sm[k];
+            if (D == 3) t += w * sn[k];
+            ACC sn_, cs_;
+            sincos_turns(t, &sn_, &cs_);
+            const ACC c = (ACC)sc[k];
+            pr += c * cs_;
+            pi += c * sn_;
+        }
+        accr += (double)pr;
+        acci += (double)pi;
+        __syncthreads();
+    }
+    if (p < n_pairs) {
+        out[2 * p] = accr;
+        out[2 * p + 1] = acci;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_src_check(const double *src, int n_src, double *out) {
+    __shared__ double red[6][1024];
+    __shared__ int badsh[1024];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int j = threadIdx.x; j < n_src; j += 1024) {
+        const double a = src[3 * (size_t)j], b = src[3 * (size_t)j + 1], c = src[3 * (size_t)j + 2];
+        if (!(isfinite(a) && isfinite(b) && isfinite(c)) || fabs(sqrt(a * a + b * b + c * c) - 1.0) > 1e-9) ++bad;
+        lo[0] = fmin(lo[0], a);
+        hi[0] = fmax(hi[0], a);
+        lo[1] = fmin(lo[1], b);
+        hi[1] = fmax(hi[1], b);
+        lo[2] = fmin(lo[2], c);
+        hi[2] = fmax(hi[2], c);
+    }
+    for (int a = 0; a < 3; ++a) {
+        red[2 * a][threadIdx.x] = lo[a];
+        red[2 * a + 1][threadIdx.x] = hi[a];
+    }
+    badsh[threadIdx.x] = bad;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            for (int a = 0; a < 3; ++a) {
+                red[2 * a][threadIdx.x] = fmin(red[2 * a][threadIdx.x], red[2 * a][threadIdx.x + off]);
+                red[2 * a + 1][threadIdx.x] = fmax(red[2 * a + 1][threadIdx.x], red[2 * a + 1][threadIdx.x + off]);
+            }
+            badsh[threadIdx.x] += badsh[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 6; ++k) out[k] = red[k][0];
+        out[6] = (double)badsh[0];
+        int *cnt = (int *)(out + 7);
+        cnt[0] = 0;
+        cnt[1] = 0;
+    }
+}
+
+__global__ void k_count_nonfinite(const double *x, long long n, int *out) {
+    int bad = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        if (!isfinite(x[i])) ++bad;
+    if (bad) atomicAdd(out, bad);
+}
+
+__global__ void k_zero_f64(double *p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+}  // namespace
+
+void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
+                   int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits, double *vis_dev,
+                   hipStream_t st) {
+    const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
+    const unsigned nb = (unsigned)((n_pairs + 255) / 256);
+    for (int f = 0; f < n_freq; ++f) {
+        const double kturn = freq_host[f] / kCLight;
+        const double *fl = flux_dev + (size_t)f * n_src;
+        const double *bm = beam_dev ? beam_dev + (size_t)f * n_src : nullptr;
+        double *o = vis_dev + 2 * (size_t)f * n_pairs;
+        if (dim == 2) {
+            if (prec_bits == 32)
+                hipLaunchKernelGGL((k_direct<2, float>), dim3(nb), dim3(256), 0, st, ant_dev, n_ant, n_pairs, src_dev,
+                                   n_src, fl, bm, kturn, o);
+            else
+                hipLaunchKernelGGL((k_direct<2, double>), dim3(nb), dim3(256), 0, st, ant_dev, n_ant, n_pairs, src_dev,
+                                   n_src, fl, bm, kturn, o);
+        } else {
+            if (prec_bits == 32)
+                hipLaunchKernelGGL((k_direct<3, float>), dim3(nb), dim3(256), 0, st, ant_dev, n_ant, n_pairs, src_dev,
+                                   n_src, fl, bm, kturn, o);
+            else
+                hipLaunchKernelGGL((k_direct<3, double>), dim3(nb), dim3(256), 0, st, ant_dev, n_ant, n_pairs, src_dev,
+                                   n_src, fl, bm, kturn, o);
+        }
+    }
+    FV_HIP(hipGetLastError());
+}
+
+void launch_src_check(const double *src, int n_src, double *out8, hipStream_t st) {
+    hipLaunchKernelGGL(k_src_check, dim3(1), dim3(1024), 0, st, src, n_src, out8);
+    FV_HIP(hipGetLastError());
+}
+
+void launch_count_nonfinite(const double *x, long long n, int *out, hipStream_t st) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(std::max(1u, nb)), dim3(256), 0, st, x, n, out);
+    FV_HIP(hipGetLastError());
+}
+
+void launch_zero_c128(double *out, long long n_complex, hipStream_t st) {
+    const long long n = 2 * n_complex;
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero_f64, dim3(std::max(1u, nb)), dim3(256), 0, st, out, n);
+    FV_HIP(hipGetLastError());
+}
+
+}  // namespace fv

@@ -1,0 +1,179 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fv.h"
+
+namespace fv {
+
+constexpr double kCLight = 299792458.0;
+constexpr double kSigma = 2.0;   // upsampling factor of the FFT grid
+constexpr int kMaxW = 16;        // largest kernel width handled
+constexpr int kMinW = 3;
+constexpr int kQuadHalf = 32;    // positive nodes of the 64-node Gauss-Legendre rule
+constexpr int kSubBin = 8;       // sub-bin edge (cells) of the source sort along x and y
+constexpr int kSubBinZ = 4;      // sub-bin edge along z
+constexpr int kFftSlots = 30;    // complex values per thread per LDS FFT stage (lines * N <= kFftSlots * threads)
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws fv::Error; every ABI entry converts it to a
+// status code and records the message for fv_last_error().
+struct Error {
+    fv_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(fv_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define FV_HIP(call) ::fv::hip_check((call), #call)
+
+// ---------------------------------------------------------------------------
+// Per-snapshot parameters read by every stage kernel (plain data, in device
+// memory as an array indexed by snapshot).  A snapshot is one (problem,
+// frequency) pair.
+struct SnapDev {
+    int n1[3], n2[3], M[3], P[3];    // spreading grid, FFT grid, pruned output M = 2P+1
+    int ntile[3];                    // spread tiles per axis
+    int nsb[3];                      // sort sub-bins per axis
+    int cx[3];                       // lines per workgroup of each FFT pass
+    int dim, w, n_src, n_tgt;
+    int degenerate;                  // bit a: X_a was clamped to 1 rad
+    int pad0;
+    long long tile_base;             // first global spread tile of this snapshot
+    long long src_base;              // offset in the rank / record arrays
+    long long bin_base;              // offset in the sub-bin array (nbins + 1 entries)
+    long long bufA, bufB;            // element offsets of the two grid regions
+    long long ipsi_base;             // offset of the 1/psi2hat tables (n1[0] | n1[1] | n1[2])
+    long long wg_base[3];            // first workgroup of each FFT pass
+    const double *src;               // [n_src][3]
+    const double *flux;              // [n_src] this frequency
+    const double *beam;              // [n_src] this frequency, or nullptr
+    double *out;                     // [n_pairs] complex128 of this frequency
+    const double *tb;                // folded target baselines, [dim][n_tgt]
+    const int *tidx;                 // pair index | (reflected << 31)
+    const double *tphi;              // phihat at each target, [dim][n_tgt]
+    const double *qn;                // quadrature table of this w
+    const void *tw[3];               // twiddle table of n2[a]
+    double gscale[3];                // grid cells per unit of s: sigma X / pi
+    double s_c[3];
+    double qscale[3];                // target grid coordinate q = qscale (b - b_c)
+    double b_c[3];
+    double xi_deg[3];                // clamped axes: xi = xi_deg (b - b_c)
+    double pre_turn[3];              // pre-phase turns = pre_turn . (s - s_c)
+    double post_turn;                // post-phase turns = post_turn (b . s_c)
+    double post_norm;                // prod_a 4 pi / (n2_a w)
+    double beta;
+};
+
+// Host plan of one snapshot.
+struct SnapPlan {
+    int dim = 2, w = 8, fold_axis = -1;
+    int n1[3] = {1, 1, 1}, n2[3] = {1, 1, 1}, M[3] = {1, 1, 1}, P[3] = {0, 0, 0};
+    double X[3] = {1, 1, 1};
+    double S[3] = {0, 0, 0}, s_c[3] = {0, 0, 0}, b_c[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+    double k = 0;  // 2 pi nu / c
+    double nu = 0;
+    int degenerate = 0;
+    long long cells1() const { return (long long)n1[0] * n1[1] * n1[2]; }
+    long long cellsM() const { return (long long)M[0] * M[1] * M[2]; }
+};
+
+// Geometry-level plan shared by all frequencies of one problem.
+struct GeomPlan {
+    int dim = 2, w = 8, fold_axis = -1, n_ant = 0;
+    long long n_pairs = 0;
+    double S[3] = {0, 0, 0}, s_c[3] = {0, 0, 0};
+    double b_c[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+};
+
+int kernel_width(double eps);
+int next_smooth_even(long long n);
+void src_box(const double *src, int n_src, int dim, double *s_c, double *S);
+GeomPlan plan_geometry(const double *ant, int n_ant, int dim, double eps, const double *s_c, const double *S,
+                       bool fold);
+SnapPlan plan_snapshot(const GeomPlan &g, double nu);
+void fold_baseline(const double *b, int dim, int axis, double *out, bool *flipped);
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+int choose_dim(const double *ant, int n_ant, double eps, const double *freq, int n_freq, unsigned flags);
+int choose_prec(double eps, unsigned flags);
+void quad_table(int w, double *out64);  // host: the 2*kQuadHalf quadrature table of width w
+
+// ---------------------------------------------------------------------------
+// Device memory: a growable bump arena (one allocation).  Callers make sure
+// no in-flight work uses the arena before `ensure` reallocates it.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    void ensure(size_t bytes);          // reallocate (contents lost) if smaller
+    void reset() { used = 0; }
+    void *take(size_t bytes, size_t align = 256);
+    void release();
+};
+
+// Device tables reused across calls: twiddles per (n, precision), quadrature
+// tables per w.
+struct DevCache {
+    std::map<std::pair<int, int>, void *> twiddles;
+    std::map<int, double *> qnodes;
+    const void *twiddle(int n, int prec_bits, hipStream_t s);
+    const double *quad(int w, hipStream_t s);
+    void release();
+};
+
+// Target table of one (array, dim, fold axis, w): folded baselines, pair
+// indices and phihat at the normalised target positions.
+struct TargetTable {
+    uint64_t key = 0;
+    int dim = 0, w = 0, fold_axis = -1, n_ant = 0;
+    long long n_tgt = 0;
+    double *tb = nullptr;
+    int *tidx = nullptr;
+    double *tphi = nullptr;
+    void release();
+};
+
+// One (problem, frequency) snapshot of a NUFFT launch group.
+struct SnapJob {
+    SnapPlan plan;
+    const double *src = nullptr;   // device [n_src][3]
+    int n_src = 0;
+    const double *flux = nullptr;  // device row of this frequency
+    const double *beam = nullptr;  // device row or nullptr
+    double *out = nullptr;         // device [n_pairs] complex128
+    const TargetTable *tt = nullptr;
+};
+
+// Enqueue the whole type-3 pipeline for jobs that share (dim, precision, w).
+// Allocates its workspace from `arena` (which must be idle); returns the
+// algorithmic HBM bytes of the grid stages.
+double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena,
+                     DevCache &cache, hipStream_t s);
+// Workspace bytes nufft_execute would take for these jobs.
+size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w);
+
+void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B,
+                   int w, const double *qn_dev, TargetTable &tt, hipStream_t s);
+// Device reduction over sources: out[0..5] = min/max of l, m, n; out[6] =
+// count of non-unit or non-finite directions.  out must be device memory.
+void launch_src_check(const double *src, int n_src, double *out7, hipStream_t s);
+// Device count of non-finite values in x[n] added to *out (device int).
+void launch_count_nonfinite(const double *x, long long n, int *out, hipStream_t s);
+void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
+
+// Direct sums.
+void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
+                   int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits,
+                   double *vis_dev, hipStream_t s);
+size_t zz_work_bytes(int n_ant, int n_src);
+void launch_zz(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
+               int n_freq, const double *flux_dev, const double *beam_dev, int dim, double *vis_dev, void *work,
+               hipStream_t s);
+
+}  // namespace fv

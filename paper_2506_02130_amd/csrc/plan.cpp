@@ -1,0 +1,219 @@
+// Host-side planning of the type-3 transform (paper section 2.2: kernel width
+// from eps, the grid-size equation, centring of both point sets) and the
+// choice of dimension and precision.
+//
+// Host code here is compiled with -ffp-contract=off so that every grid size is
+// the exact IEEE result of the documented expression.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "fv_internal.h"
+
+namespace fv {
+
+int kernel_width(double eps) {
+    // paper rule ceil(log10(1/eps)) + 1, plus one point (the rule alone lands
+    // at about eps, not below it)
+    int w = (int)std::ceil(-std::log10(eps) - 1e-9) + 2;
+    return std::max(2, std::min(kMaxW, w));
+}
+
+int next_smooth_even(long long n) {
+    if (n < 2) n = 2;
+    if (n % 2) ++n;
+    for (;; n += 2) {
+        long long m = n;
+        for (int p : {2, 3, 5})
+            while (m % p == 0) m /= p;
+        if (m == 1) return (int)n;
+    }
+}
+
+void src_box(const double *src, int n_src, int dim, double *s_c, double *S) {
+    for (int a = 0; a < 3; ++a) { s_c[a] = 0; S[a] = 0; }
+    if (n_src <= 0) return;
+    for (int a = 0; a < dim; ++a) {
+        double lo = src[a], hi = src[a];
+        for (int j = 1; j < n_src; ++j) {
+            double v = src[3 * (size_t)j + a];
+            lo = std::min(lo, v);
+            hi = std::max(hi, v);
+        }
+        s_c[a] = 0.5 * (lo + hi);
+        S[a] = 0.5 * (hi - lo);
+    }
+}
+
+// Reflect b into the half-space b[axis] >= 0, zeros decided by the remaining
+// axes in increasing order.  Real strengths give V(-b) = conj V(b).
+void fold_baseline(const double *b, int dim, int axis, double *out, bool *flipped) {
+    bool flip = false;
+    if (axis >= 0) {
+        int order[3] = {axis, 0, 0};
+        int k = 1;
+        for (int a = 0; a < dim; ++a)
+            if (a != axis) order[k++] = a;
+        for (int t = 0; t < dim; ++t) {
+            double v = b[order[t]];
+            if (v < 0) { flip = true; break; }
+            if (v > 0) break;
+        }
+    }
+    for (int a = 0; a < dim; ++a) out[a] = flip ? -b[a] : b[a];
+    for (int a = dim; a < 3; ++a) out[a] = 0.0;
+    *flipped = flip;
+}
+
+GeomPlan plan_geometry(const double *ant, int n_ant, int dim, double eps, const double *s_c, const double *S,
+                       bool fold) {
+    GeomPlan g;
+    g.dim = dim;
+    g.w = kernel_width(eps);
+    g.n_ant = n_ant;
+    g.n_pairs = (long long)n_ant * (n_ant + 1) / 2;
+    for (int a = 0; a < 3; ++a) { g.s_c[a] = s_c[a]; g.S[a] = S[a]; }
+    // unfolded extents pick the reflection axis (largest extent times S)
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = std::numeric_limits<double>::infinity(); hi[a] = -lo[a]; }
+    for (int i = 0; i < n_ant; ++i)
+        for (int j = i; j < n_ant; ++j)
+            for (int a = 0; a < dim; ++a) {
+                double b = ant[3 * (size_t)i + a] - ant[3 * (size_t)j + a];
+                lo[a] = std::min(lo[a], b);
+                hi[a] = std::max(hi[a], b);
+            }
+    g.fold_axis = -1;
+    if (fold) {
+        double best = -1.0;
+        for (int a = 0; a < dim; ++a) {
+            double v = (hi[a] - lo[a]) * std::max(S[a], 1e-300);
+            if (v > best) { best = v; g.fold_axis = a; }
+        }
+        for (int a = 0; a < 3; ++a) { lo[a] = std::numeric_limits<double>::infinity(); hi[a] = -lo[a]; }
+        for (int i = 0; i < n_ant; ++i)
+            for (int j = i; j < n_ant; ++j) {
+                double b[3], f[3];
+                bool fl;
+                for (int a = 0; a < 3; ++a) b[a] = ant[3 * (size_t)i + a] - ant[3 * (size_t)j + a];
+                fold_baseline(b, dim, g.fold_axis, f, &fl);
+                for (int a = 0; a < dim; ++a) { lo[a] = std::min(lo[a], f[a]); hi[a] = std::max(hi[a], f[a]); }
+            }
+    }
+    for (int a = 0; a < dim; ++a) {
+        g.b_c[a] = 0.5 * (lo[a] + hi[a]);
+        g.B[a] = 0.5 * (hi[a] - lo[a]);
+    }
+    return g;
+}
+
+SnapPlan plan_snapshot(const GeomPlan &g, double nu) {
+    SnapPlan p;
+    p.dim = g.dim;
+    p.w = g.w;
+    p.fold_axis = g.fold_axis;
+    p.nu = nu;
+    p.k = 2.0 * M_PI * nu / kCLight;
+    for (int a = 0; a < 3; ++a) {
+        p.s_c[a] = g.s_c[a];
+        p.S[a] = g.S[a];
+        p.b_c[a] = g.b_c[a];
+        p.B[a] = g.B[a];
+    }
+    const int P0 = g.w / 2 + 1;
+    for (int a = 0; a < g.dim; ++a) {
+        double kB = p.k * g.B[a];
+        double X = std::max(kB, 1.0);
+        if (!(kB >= 1.0)) p.degenerate |= 1 << a;
+        double Se = std::max(g.S[a], 1.0 / X);
+        double v = 2.0 * kSigma / M_PI * X * Se + (double)g.w;
+        p.X[a] = X;
+        p.n1[a] = next_smooth_even((long long)std::ceil(v));
+        p.n2[a] = (int)(kSigma * p.n1[a]);
+        p.P[a] = p.n1[a] / 2 + P0;
+        p.M[a] = 2 * p.P[a] + 1;
+    }
+    return p;
+}
+
+// Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n from the
+// Chebyshev-like initial guesses (textbook construction).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                // one more evaluation of the derivative at the converged node
+                p0 = 1.0; p1 = z;
+                for (int k = 2; k <= n; ++k) {
+                    double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = n * (z * p1 - p0) / (z * z - 1.0);
+                break;
+            }
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+int choose_dim(const double *ant, int n_ant, double eps, const double *freq, int n_freq, unsigned flags) {
+    unsigned d = flags & FV_DIM_MASK;
+    if (d == FV_DIM_2D) return 2;
+    if (d == FV_DIM_3D) return 3;
+    double zlo = ant[2], zhi = ant[2];
+    for (int i = 1; i < n_ant; ++i) {
+        zlo = std::min(zlo, ant[3 * (size_t)i + 2]);
+        zhi = std::max(zhi, ant[3 * (size_t)i + 2]);
+    }
+    double numax = 0.0;
+    for (int f = 0; f < n_freq; ++f) numax = std::max(numax, freq[f]);
+    // dropped phase 2 pi nu dz n / c must stay below eps / 10
+    double tol = eps * kCLight / (20.0 * M_PI * numax);
+    return (zhi - zlo) <= tol ? 2 : 3;
+}
+
+int choose_prec(double eps, unsigned flags) {
+    unsigned p = flags & FV_PREC_MASK;
+    if (p == FV_PREC_FP32) return 32;
+    if (p == FV_PREC_FP64) return 64;
+    return eps >= 1e-6 ? 32 : 64;
+}
+
+}  // namespace fv
+
+namespace fv {
+
+// Quadrature table for phihat with kernel width w (beta = 2.3 w):
+// out[q] = sin(theta_q), out[kQuadHalf + q] = 2 * (pi/2) wgl_q exp(beta (cos theta_q - 1)) cos theta_q
+// over the positive nodes theta_q = (pi/2) x_q of the 64-point rule (the
+// integrand is even in theta, so each positive node stands for its mirror).
+void quad_table(int w, double *out) {
+    std::vector<double> x, wt;
+    gauss_legendre(2 * kQuadHalf, x, wt);
+    const double beta = 2.3 * w;
+    for (int q = 0; q < kQuadHalf; ++q) {
+        double xq = x[kQuadHalf + q];
+        double t = 0.5 * M_PI * xq;
+        out[q] = std::sin(t);
+        out[kQuadHalf + q] = 2.0 * 0.5 * M_PI * wt[kQuadHalf + q] * std::exp(beta * (std::cos(t) - 1.0)) * std::cos(t);
+    }
+}
+
+}  // namespace fv

@@ -1,0 +1,513 @@
+// Context, device memory, validation and the C ABI entry points (the serving
+// entry points live in server.cpp, the batch entry point in batch.cpp).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+#include "fv_internal.h"
+
+namespace fv {
+
+static thread_local std::string g_last_error;
+
+[[noreturn]] void fail(fv_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // clear the sticky per-thread error where possible
+        fail(FV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+void *Arena::take(size_t bytes, size_t align) {
+    size_t off = (used + align - 1) / align * align;
+    if (off + bytes > cap) fail(FV_ENOMEM, "workspace arena overflow");
+    used = off + bytes;
+    return base + off;
+}
+
+void Arena::ensure(size_t bytes) {
+    if (bytes <= cap) return;
+    release();
+    size_t want = std::max(bytes, cap + cap / 2);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        e = hipMalloc(&p, bytes);
+        want = bytes;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(FV_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    base = (char *)p;
+    cap = want;
+    used = 0;
+}
+
+void Arena::release() {
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    cap = used = 0;
+}
+
+void TargetTable::release() {
+    if (tb) (void)hipFree(tb);
+    if (tidx) (void)hipFree(tidx);
+    if (tphi) (void)hipFree(tphi);
+    tb = tphi = nullptr;
+    tidx = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+Slot::~Slot() {
+    arena.release();
+    inputs.release();
+    if (stream && own_stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace fv
+
+using namespace fv;
+
+fv_ctx::~fv_ctx() {
+    targets.clear();
+    cache.release();
+    if (scalar_buf) (void)hipFree(scalar_buf);
+}
+
+namespace fv {
+
+static size_t device_free_bytes() {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return fr;
+}
+
+// Geometry plan with a cache of the pair extents per (array bytes, dim).
+GeomPlan ctx_geometry(fv_ctx *ctx, const double *ant_host, int n_ant, int dim, double eps, const double *s_c,
+                      const double *S, bool fold) {
+    std::lock_guard<std::mutex> lk(ctx->geo_mu);
+    uint64_t key = fnv1a(ant_host, sizeof(double) * 3 * (size_t)n_ant);
+    key = fnv1a(&dim, sizeof(dim), key);
+    key = fnv1a(&fold, sizeof(fold), key);
+    key = fnv1a(S, sizeof(double) * 3, key);
+    int w = kernel_width(eps);
+    key = fnv1a(&w, sizeof(w), key);
+    for (auto &e : ctx->geos)
+        if (e.first == key) {
+            GeomPlan g = e.second;
+            for (int a = 0; a < 3; ++a) { g.s_c[a] = s_c[a]; g.S[a] = S[a]; }
+            return g;
+        }
+    GeomPlan g = plan_geometry(ant_host, n_ant, dim, eps, s_c, S, fold);
+    ctx->geos.push_back({key, g});
+    if (ctx->geos.size() > 64) ctx->geos.erase(ctx->geos.begin());
+    return g;
+}
+
+// Target table for (array, dim, fold axis, w), built on the device and cached.
+std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, const double *ant_dev,
+                                         const GeomPlan &g, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(ctx->geo_mu);
+    uint64_t key = fnv1a(ant_host, sizeof(double) * 3 * (size_t)g.n_ant);
+    key = fnv1a(&g.dim, sizeof(int), key);
+    key = fnv1a(&g.fold_axis, sizeof(int), key);
+    key = fnv1a(&g.w, sizeof(int), key);
+    key = fnv1a(g.b_c, sizeof(double) * 3, key);
+    key = fnv1a(g.B, sizeof(double) * 3, key);
+    for (auto it = ctx->targets.begin(); it != ctx->targets.end(); ++it)
+        if ((*it)->key == key) {
+            auto t = *it;
+            ctx->targets.erase(it);
+            ctx->targets.push_back(t);  // most recently used at the back
+            return t;
+        }
+    if (ctx->targets.size() >= 64) ctx->targets.pop_front();  // freed when its last user drops it
+    std::shared_ptr<TargetTable> t(new TargetTable, [](TargetTable *x) {
+        x->release();
+        delete x;
+    });
+    t->key = key;
+    t->dim = g.dim;
+    t->w = g.w;
+    t->fold_axis = g.fold_axis;
+    t->n_ant = g.n_ant;
+    t->n_tgt = g.n_pairs;
+    const size_t n = (size_t)std::max<long long>(g.n_pairs, 1);
+    FV_HIP(hipMalloc((void **)&t->tb, n * g.dim * sizeof(double)));
+    FV_HIP(hipMalloc((void **)&t->tidx, n * sizeof(int)));
+    FV_HIP(hipMalloc((void **)&t->tphi, n * g.dim * sizeof(double)));
+    const double *qn = ctx->cache.quad(g.w, st);
+    build_targets(ant_dev, g.n_ant, g.dim, g.fold_axis, g.b_c, g.B, g.w, qn, *t, st);
+    ctx->targets.push_back(t);
+    return t;
+}
+
+// Host-side validation of a problem whose arrays are host memory.
+void validate_host(const fv_problem *p) {
+    if (!p) fail(FV_EINVAL, "null problem");
+    if (p->n_ant < 1 || p->n_src < 0 || p->n_freq < 1) fail(FV_EINVAL, "bad sizes");
+    if (!p->ant_enu || !p->freq_hz) fail(FV_EINVAL, "null antenna or frequency array");
+    if (p->n_src > 0 && (!p->src_lmn || !p->flux)) fail(FV_EINVAL, "null source or flux array");
+    if (!(p->eps >= 1e-14 && p->eps <= 1e-1)) fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
+    for (long long i = 0; i < 3LL * p->n_ant; ++i)
+        if (!std::isfinite(p->ant_enu[i])) fail(FV_EINVAL, "non-finite antenna position");
+    for (int f = 0; f < p->n_freq; ++f)
+        if (!(std::isfinite(p->freq_hz[f]) && p->freq_hz[f] > 0)) fail(FV_EINVAL, "frequency must be finite and > 0");
+    for (int j = 0; j < p->n_src; ++j) {
+        const double *s = p->src_lmn + 3 * (size_t)j;
+        if (!(std::isfinite(s[0]) && std::isfinite(s[1]) && std::isfinite(s[2])))
+            fail(FV_EINVAL, "non-finite source direction");
+        double r = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        if (std::fabs(r - 1.0) > 1e-9) fail(FV_EINVAL, "source direction is not a unit vector");
+    }
+    const long long nfs = (long long)p->n_freq * p->n_src;
+    for (long long i = 0; i < nfs; ++i)
+        if (!std::isfinite(p->flux[i])) fail(FV_EINVAL, "non-finite flux");
+    if (p->beam)
+        for (long long i = 0; i < nfs; ++i)
+            if (!std::isfinite(p->beam[i])) fail(FV_EINVAL, "non-finite beam");
+    unsigned m = p->flags & FV_METHOD_MASK;
+    if (m != FV_METHOD_NUFFT && m != FV_METHOD_DIRECT && m != FV_METHOD_MFMA) fail(FV_EINVAL, "unknown method");
+    if ((p->flags & FV_DIM_MASK) == FV_DIM_MASK) fail(FV_EINVAL, "both 2-D and 3-D forced");
+    if ((p->flags & FV_PREC_MASK) == FV_PREC_MASK) fail(FV_EINVAL, "both FP32 and FP64 forced");
+    if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6) fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
+}
+
+// Everything the device path needs once the inputs are on the device and the
+// planning scalars (antenna positions, frequencies, source box) on the host.
+void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevInputs &in, double *vis_dev,
+                fv_report *rep) {
+    const fv_problem *p = &host_meta;
+    const int n_ant = p->n_ant, n_freq = p->n_freq, n_src = p->n_src;
+    const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
+    hipStream_t st = slot.stream;
+    const unsigned method = p->flags & FV_METHOD_MASK;
+    const int dim = choose_dim(p->ant_enu, n_ant, p->eps, p->freq_hz, n_freq, p->flags);
+    const int prec = choose_prec(p->eps, p->flags);
+    fv_report r;
+    std::memset(&r, 0, sizeof(r));
+    r.dim = dim;
+    r.prec_bits = prec;
+    r.method = (int)method;
+    r.fold_axis = -1;
+    r.src_pairs = (double)n_src * (double)n_pairs * (double)n_freq;
+    if (n_src == 0) {
+        launch_zero_c128(vis_dev, n_pairs * n_freq, st);
+    } else if (method == FV_METHOD_DIRECT) {
+        launch_direct(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, prec, vis_dev, st);
+    } else if (method == FV_METHOD_MFMA) {
+        slot.arena.ensure(zz_work_bytes(n_ant, n_src));
+        slot.arena.reset();
+        void *work = slot.arena.take(zz_work_bytes(n_ant, n_src));
+        launch_zz(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, vis_dev, work, st);
+    } else {
+        const bool fold = !(p->flags & FV_NO_FOLD);
+        GeomPlan g = ctx_geometry(ctx, p->ant_enu, n_ant, dim, p->eps, in.s_c, in.S, fold);
+        std::shared_ptr<TargetTable> tt_hold = ctx_targets(ctx, p->ant_enu, in.ant, g, st);
+        const TargetTable *tt = tt_hold.get();
+        std::vector<SnapJob> jobs;
+        jobs.reserve(n_freq);
+        for (int f = 0; f < n_freq; ++f) {
+            SnapJob j;
+            j.plan = plan_snapshot(g, p->freq_hz[f]);
+            j.src = in.src;
+            j.n_src = n_src;
+            j.flux = in.flux + (size_t)f * n_src;
+            j.beam = in.beam ? in.beam + (size_t)f * n_src : nullptr;
+            j.out = vis_dev + 2 * (size_t)f * n_pairs;
+            j.tt = tt;
+            jobs.push_back(j);
+        }
+        // run in chunks of frequencies whose workspace fits the budget share
+        const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
+        std::vector<size_t> each(jobs.size());
+        for (size_t i = 0; i < jobs.size(); ++i)
+            each[i] = nufft_workspace_bytes(std::vector<SnapJob>{jobs[i]}, dim, prec, g.w);
+        size_t i0 = 0;
+        int best_f = 0;
+        for (int f = 1; f < n_freq; ++f)
+            if (p->freq_hz[f] > p->freq_hz[best_f]) best_f = f;
+        while (i0 < jobs.size()) {
+            size_t i1 = i0 + 1, tot = each[i0];
+            while (i1 < jobs.size() && tot + each[i1] <= cap) tot += each[i1++];
+            std::vector<SnapJob> part(jobs.begin() + i0, jobs.begin() + i1);
+            if (i0 > 0) FV_HIP(hipStreamSynchronize(st));  // the arena is reused
+            r.model_bytes += nufft_execute(part, dim, prec, g.w, slot.arena, ctx->cache, st);
+            i0 = i1;
+        }
+        const SnapPlan top = jobs.empty() ? SnapPlan() : jobs[best_f].plan;
+        r.w = g.w;
+        r.fold_axis = g.fold_axis;
+        for (int a = 0; a < 3; ++a) {
+            r.n1[a] = top.n1[a];
+            r.n2[a] = top.n2[a];
+        }
+    }
+    FV_HIP(hipGetLastError());
+    if (rep) *rep = r;
+}
+
+// Upload a host problem into the slot's input arena.
+DevInputs upload(Slot &slot, const fv_problem *p, double *s_c, double *S) {
+    const int n_ant = p->n_ant, n_src = p->n_src, n_freq = p->n_freq;
+    const size_t b_ant = sizeof(double) * 3 * n_ant, b_src = sizeof(double) * 3 * (size_t)n_src;
+    const size_t b_fs = sizeof(double) * (size_t)n_freq * n_src;
+    const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
+    const size_t b_vis = sizeof(double) * 2 * (size_t)n_pairs * n_freq;
+    slot.inputs.ensure(b_ant + b_src + 2 * b_fs + b_vis + 8 * 256);
+    slot.inputs.reset();
+    DevInputs in;
+    in.ant = (double *)slot.inputs.take(b_ant);
+    in.src = n_src ? (double *)slot.inputs.take(b_src) : nullptr;
+    in.flux = n_src ? (double *)slot.inputs.take(b_fs) : nullptr;
+    in.beam = (n_src && p->beam) ? (double *)slot.inputs.take(b_fs) : nullptr;
+    in.vis = (double *)slot.inputs.take(b_vis);
+    hipStream_t st = slot.stream;
+    FV_HIP(hipMemcpyAsync((void *)in.ant, p->ant_enu, b_ant, hipMemcpyHostToDevice, st));
+    if (n_src) {
+        FV_HIP(hipMemcpyAsync((void *)in.src, p->src_lmn, b_src, hipMemcpyHostToDevice, st));
+        FV_HIP(hipMemcpyAsync((void *)in.flux, p->flux, b_fs, hipMemcpyHostToDevice, st));
+        if (p->beam) FV_HIP(hipMemcpyAsync((void *)in.beam, p->beam, b_fs, hipMemcpyHostToDevice, st));
+    }
+    const int dim = choose_dim(p->ant_enu, n_ant, p->eps, p->freq_hz, n_freq, p->flags);
+    src_box(p->src_lmn, n_src, dim, s_c, S);
+    for (int a = 0; a < 3; ++a) {
+        in.s_c[a] = s_c[a];
+        in.S[a] = S[a];
+    }
+    return in;
+}
+
+void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv_report *rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    validate_host(p);
+    FV_HIP(hipSetDevice(ctx->device));
+    double s_c[3], S[3];
+    DevInputs in = upload(slot, p, s_c, S);
+    fv_report r;
+    run_device(ctx, slot, *p, in, in.vis, &r);
+    const long long n_pairs = (long long)p->n_ant * (p->n_ant + 1) / 2;
+    FV_HIP(hipMemcpyAsync(vis, in.vis, sizeof(double) * 2 * (size_t)n_pairs * p->n_freq, hipMemcpyDeviceToHost,
+                          slot.stream));
+    FV_HIP(hipStreamSynchronize(slot.stream));
+    r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+}
+
+}  // namespace fv
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+#define FV_GUARD_BEGIN try {
+#define FV_GUARD_END                                   \
+    }                                                  \
+    catch (const fv::Error &e) {                       \
+        fv::set_last_error(e.msg);                     \
+        return e.code;                                 \
+    }                                                  \
+    catch (const std::bad_alloc &) {                   \
+        fv::set_last_error("host allocation failed");  \
+        return FV_ENOMEM;                              \
+    }                                                  \
+    catch (const std::exception &e) {                  \
+        fv::set_last_error(e.what());                  \
+        return FV_EDEVICE;                             \
+    }                                                  \
+    catch (...) {                                      \
+        fv::set_last_error("unknown failure");         \
+        return FV_EDEVICE;                             \
+    }
+
+extern "C" {
+
+fv_status fv_create(int device, size_t hbm_budget_bytes, fv_ctx **out) {
+    FV_GUARD_BEGIN
+    if (!out) fv::fail(FV_EINVAL, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        fv::fail(FV_EDEVICE, "no HIP device");
+    }
+    if (device < 0 || device >= n) fv::fail(FV_EINVAL, "device index out of range");
+    FV_HIP(hipSetDevice(device));
+    fv_ctx *c = new fv_ctx();
+    c->device = device;
+    size_t fr = fv::device_free_bytes();
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * fr);
+    c->chunk_bytes = std::max<size_t>(c->budget / 4, 256u << 20);
+    hipError_t e = hipStreamCreateWithFlags(&c->main.stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        FV_HIP(e);
+    }
+    c->main.own_stream = true;
+    *out = c;
+    return FV_OK;
+    FV_GUARD_END
+}
+
+void fv_destroy(fv_ctx *ctx) {
+    if (!ctx) return;
+    try {
+        fv_server_stop(ctx);
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+    } catch (...) {
+    }
+    delete ctx;
+}
+
+const char *fv_last_error(void) { return fv::last_error_cstr(); }
+
+fv_status fv_simulate(fv_ctx *ctx, const fv_problem *p, double *vis, fv_report *rep) {
+    FV_GUARD_BEGIN
+    if (!ctx || !vis) fv::fail(FV_EINVAL, "null context or output");
+    fv::simulate_host(ctx, ctx->main, p, vis, rep);
+    return FV_OK;
+    FV_GUARD_END
+}
+
+fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *stream, fv_report *rep) {
+    FV_GUARD_BEGIN
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx || !p || !vis) fv::fail(FV_EINVAL, "null argument");
+    if (p->n_ant < 1 || p->n_src < 0 || p->n_freq < 1) fv::fail(FV_EINVAL, "bad sizes");
+    if (!p->ant_enu || !p->freq_hz || (p->n_src > 0 && (!p->src_lmn || !p->flux)))
+        fv::fail(FV_EINVAL, "null device array");
+    if (!(p->eps >= 1e-14 && p->eps <= 1e-1)) fv::fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
+    FV_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    // planning scalars to the host
+    std::vector<double> ant(3 * (size_t)p->n_ant), freq(p->n_freq);
+    FV_HIP(hipMemcpyAsync(ant.data(), p->ant_enu, ant.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    FV_HIP(hipMemcpyAsync(freq.data(), p->freq_hz, freq.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    double *chk = ctx->scalars(st);  // device: 7 doubles + 1 int
+    double host_chk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (p->n_src > 0) {
+        fv::launch_src_check(p->src_lmn, p->n_src, chk, st);
+        int *bad = (int *)(chk + 7);
+        fv::launch_count_nonfinite(p->flux, (long long)p->n_src * p->n_freq, bad, st);
+        if (p->beam) fv::launch_count_nonfinite(p->beam, (long long)p->n_src * p->n_freq, bad, st);
+        FV_HIP(hipMemcpyAsync(host_chk, chk, sizeof(host_chk), hipMemcpyDeviceToHost, st));
+    }
+    FV_HIP(hipStreamSynchronize(st));
+    fv_problem meta = *p;
+    meta.ant_enu = ant.data();
+    meta.freq_hz = freq.data();
+    for (double a : ant)
+        if (!std::isfinite(a)) fv::fail(FV_EINVAL, "non-finite antenna position");
+    for (double f : freq)
+        if (!(std::isfinite(f) && f > 0)) fv::fail(FV_EINVAL, "frequency must be finite and > 0");
+    int badcount = 0;
+    std::memcpy(&badcount, host_chk + 7, sizeof(int));
+    if (p->n_src > 0 && (host_chk[6] != 0.0 || badcount != 0)) fv::fail(FV_EINVAL, "invalid source directions or strengths");
+    if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6) fv::fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
+    fv::DevInputs in;
+    in.ant = nullptr;
+    in.src = p->src_lmn;
+    in.flux = p->flux;
+    in.beam = p->beam;
+    in.vis = vis;
+    const int dim = fv::choose_dim(ant.data(), p->n_ant, p->eps, freq.data(), p->n_freq, p->flags);
+    for (int a = 0; a < 3; ++a) {
+        in.s_c[a] = 0;
+        in.S[a] = 0;
+    }
+    if (p->n_src > 0)
+        for (int a = 0; a < dim; ++a) {
+            in.s_c[a] = 0.5 * (host_chk[2 * a] + host_chk[2 * a + 1]);
+            in.S[a] = 0.5 * (host_chk[2 * a + 1] - host_chk[2 * a]);
+        }
+    in.ant = p->ant_enu;
+    fv::Slot &slot = ctx->main;
+    hipStream_t keep = slot.stream;
+    slot.stream = st;
+    try {
+        fv::run_device(ctx, slot, meta, in, vis, rep);
+    } catch (...) {
+        slot.stream = keep;
+        throw;
+    }
+    slot.stream = keep;
+    if (rep) rep->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return FV_OK;
+    FV_GUARD_END
+}
+
+fv_status fv_debug_stages(fv_ctx *ctx, const fv_problem *p, int f, double *plan_out, double *spread, size_t spread_cap,
+                          double *fftout, size_t fftout_cap) {
+    FV_GUARD_BEGIN
+    if (!ctx || !p || !plan_out) fv::fail(FV_EINVAL, "null argument");
+    fv::validate_host(p);
+    if (f < 0 || f >= p->n_freq) fv::fail(FV_EINVAL, "frequency index out of range");
+    if ((p->flags & FV_METHOD_MASK) != FV_METHOD_NUFFT) fv::fail(FV_EINVAL, "stages exist for the NUFFT only");
+    if (p->n_src == 0) fv::fail(FV_EINVAL, "stages need at least one source");
+    FV_HIP(hipSetDevice(ctx->device));
+    fv::Slot &slot = ctx->main;
+    double s_c[3], S[3];
+    fv::DevInputs in = fv::upload(slot, p, s_c, S);
+    const int dim = fv::choose_dim(p->ant_enu, p->n_ant, p->eps, p->freq_hz, p->n_freq, p->flags);
+    const int prec = fv::choose_prec(p->eps, p->flags);
+    const bool fold = !(p->flags & FV_NO_FOLD);
+    fv::GeomPlan g = fv::ctx_geometry(ctx, p->ant_enu, p->n_ant, dim, p->eps, s_c, S, fold);
+    std::shared_ptr<fv::TargetTable> tt = fv::ctx_targets(ctx, p->ant_enu, in.ant, g, slot.stream);
+    fv::SnapJob j;
+    j.plan = fv::plan_snapshot(g, p->freq_hz[f]);
+    j.src = in.src;
+    j.n_src = p->n_src;
+    j.flux = in.flux + (size_t)f * p->n_src;
+    j.beam = in.beam ? in.beam + (size_t)f * p->n_src : nullptr;
+    j.out = in.vis;
+    j.tt = tt.get();
+    const fv::SnapPlan &sp = j.plan;
+    double *po = plan_out;
+    po[0] = dim;
+    po[1] = g.w;
+    po[2] = g.fold_axis;
+    for (int a = 0; a < 3; ++a) {
+        po[3 + a] = sp.n1[a];
+        po[6 + a] = sp.n2[a];
+        po[9 + a] = sp.M[a];
+        po[12 + a] = sp.P[a];
+        po[15 + a] = g.s_c[a];
+        po[18 + a] = g.S[a];
+        po[21 + a] = g.b_c[a];
+        po[24 + a] = g.B[a];
+    }
+    po[27] = prec;
+    po[28] = sp.X[0];
+    po[29] = sp.X[1];
+    po[30] = sp.X[2];
+    const size_t n1c = (size_t)sp.cells1(), nMc = (size_t)sp.cellsM();
+    if ((spread && spread_cap < n1c) || (fftout && fftout_cap < nMc)) fv::fail(FV_EINVAL, "output buffers too small");
+    fv::nufft_debug(j, dim, prec, g.w, slot.arena, ctx->cache, spread, fftout, slot.stream);
+    return FV_OK;
+    FV_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import type3
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(fv, ctx, p, eps=None, flags=0):
+    hp = fv.HostProblem.of(p, eps=eps, flags=flags)
+    return ctx.simulate_problem(hp), ctx.last_report
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0)
+    yield c
+    c.close()
+
+
+# ---------------------------------------------------------------- end to end
+def test_config1_full_output_fp64(gpu_lib, ctx):
+    p = synth.config1()
+    v, rep = _run(gpu_lib, ctx, p)
+    ref = oracle.direct_problem(p)
+    assert rep["prec_bits"] == 64 and rep["dim"] == 2
+    assert oracle.rel_l2(v, ref) <= p.eps
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-5, 1e-6, 1e-8, 1e-10, 1e-12])
+def test_small_2d_eps_sweep(gpu_lib, ctx, eps):
+    p = synth.small_problem(31, n_ant=40, n_src=700, n_freq=3, hex_layout=True)
+    v, rep = _run(gpu_lib, ctx, p, eps=eps)
+    ref = oracle.direct_problem(p)
+    assert oracle.rel_l2(v, ref) <= eps
+
+
+def test_eps_sweep_error_is_monotone(gpu_lib, ctx):
+    p = synth.small_problem(32, n_ant=30, n_src=500, n_freq=2, hex_layout=True)
+    ref = oracle.direct_problem(p)
+    errs = [oracle.rel_l2(_run(gpu_lib, ctx, p, eps=e)[0], ref) for e in (1e-3, 1e-5, 1e-7, 1e-9, 1e-11)]
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-10])
+def test_small_3d(gpu_lib, ctx, eps):
+    p = synth.small_problem(33, n_ant=30, n_src=600, n_freq=2, three_d=True, radius=120.0, zhalf=3.0)
+    v, rep = _run(gpu_lib, ctx, p, eps=eps)
+    assert rep["dim"] == 3
+    ref = oracle.direct_problem(p)
+    assert oracle.rel_l2(v, ref) <= eps
+
+
+def test_2d_and_3d_agree_on_flat_array(gpu_lib, ctx):
+    p = synth.small_problem(34, n_ant=25, n_src=400, n_freq=2)
+    v2, r2 = _run(gpu_lib, ctx, p, eps=1e-8, flags=gpu_lib.DIM_2D)
+    v3, r3 = _run(gpu_lib, ctx, p, eps=1e-8, flags=gpu_lib.DIM_3D)
+    assert r2["dim"] == 2 and r3["dim"] == 3
+    assert oracle.rel_l2(v3, v2) <= 2e-8
+
+
+def test_unfolded_equals_folded(gpu_lib, ctx):
+    p = synth.small_problem(35, n_ant=20, n_src=300, n_freq=2)
+    a, ra = _run(gpu_lib, ctx, p, eps=1e-9)
+    b, rb = _run(gpu_lib, ctx, p, eps=1e-9, flags=gpu_lib.NO_FOLD)
+    assert ra["fold_axis"] >= 0 and rb["fold_axis"] == -1
+    ref = oracle.direct_problem(p)
+    assert oracle.rel_l2(a, ref) <= 1e-9 and oracle.rel_l2(b, ref) <= 1e-9
+
+
+def test_ragged_sizes_and_beamless(gpu_lib, ctx):
+    # odd counts, no beam, sources not multiples of any tile or wave size
+    p = synth.small_problem(36, n_ant=17, n_src=131, n_freq=5, beam=False, sky="disk")
+    v, _ = _run(gpu_lib, ctx, p, eps=1e-6)
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= 1e-6
+
+
+# ---------------------------------------------------------------- stages
+@pytest.mark.parametrize("eps,dim", [(1e-6, 2), (1e-10, 2), (1e-6, 3)])
+def test_stage_parity_against_type3_steps(gpu_lib, ctx, eps, dim):
+    p = synth.small_problem(37, n_ant=14, n_src=90, n_freq=2, three_d=(dim == 3), radius=70.0, zhalf=2.0)
+    flags = gpu_lib.DIM_3D if dim == 3 else gpu_lib.DIM_2D
+    hp = gpu_lib.HostProblem.of(p, eps=eps, flags=flags)
+    info, spread, fft = ctx.debug_stages(hp, f=1)
+    pl = type3.make_plan(p.ant_enu, p.src_lmn, p.freq_hz, eps, dim)
+    # plan: integers bit-exact
+    assert info["w"] == pl.w and info["fold_axis"] == pl.fold_axis
+    assert info["n1"] == [int(v) for v in pl.n1[1]]
+    assert info["n2"] == [int(v) for v in pl.n2(1)]
+    assert np.allclose(info["s_c"], pl.s_c, rtol=0, atol=1e-15)
+    assert np.allclose(info["B"], pl.B, rtol=1e-15, atol=1e-12)
+    tol = 2e-6 if info["prec_bits"] == 32 else 1e-12
+    # step 1 + first deconvolution
+    bt = type3.spread(pl, 1, p.src_lmn, p.strengths()[1])
+    assert spread.shape == bt.shape
+    assert oracle.rel_l2(spread, bt) <= tol
+    # step 2 on the pruned output window p in [-P, P]
+    g = type3.fft_upsampled(pl, 1, bt)
+    n2 = pl.n2(1)
+    idx = [np.mod(np.arange(info["M"][a]) - info["P"][a], n2[a]) for a in range(dim)]
+    ref = g[np.ix_(*[idx[a] for a in reversed(range(dim))])]
+    assert fft.shape == ref.shape
+    assert oracle.rel_l2(fft, ref) <= 4 * tol
+
+
+# ---------------------------------------------------------------- direct kernel
+@pytest.mark.parametrize("eps,tol", [(1e-6, 1e-6), (1e-10, 1e-12)])
+def test_direct_kernel(gpu_lib, ctx, eps, tol):
+    p = synth.small_problem(38, n_ant=21, n_src=1500, n_freq=2, three_d=True, radius=200.0)
+    v, rep = _run(gpu_lib, ctx, p, eps=eps, flags=gpu_lib.METHOD_DIRECT)
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= tol
+
+
+# ---------------------------------------------------------------- edges
+def test_empty_sky_gives_exact_zero(gpu_lib, ctx):
+    p = synth.small_problem(39, n_ant=6, n_src=0, n_freq=2)
+    v, _ = _run(gpu_lib, ctx, p)
+    assert v.shape == (2, 21) and np.all(v == 0)
+
+
+def test_single_antenna_autos(gpu_lib, ctx):
+    p = synth.small_problem(40, n_ant=1, n_src=50, n_freq=2)
+    v, _ = _run(gpu_lib, ctx, p, eps=1e-8)
+    assert np.allclose(v[:, 0], p.strengths().sum(1), rtol=1e-8)
+
+
+def test_single_source_zenith(gpu_lib, ctx):
+    ant = synth.hex_array(19)
+    src = np.array([[0.0, 0.0, 1.0]])
+    V = gpu_lib.Context.simulate(ctx, ant, src, np.array([150e6]), np.array([[2.5]]), None, eps=1e-10)
+    assert np.allclose(V, 2.5, rtol=1e-10)
+
+
+def test_invalid_inputs_are_rejected(gpu_lib, ctx):
+    p = synth.small_problem(41, n_ant=5, n_src=10, n_freq=1)
+    bad = p.flux.copy()
+    bad[0, 3] = np.nan
+    with pytest.raises(gpu_lib.FvError) as e:
+        ctx.simulate(p.ant_enu, p.src_lmn, p.freq_hz, bad, p.beam, eps=1e-6)
+    assert e.value.status == gpu_lib.EINVAL
+    src = p.src_lmn.copy()
+    src[2] *= 1.01
+    with pytest.raises(gpu_lib.FvError) as e:
+        ctx.simulate(p.ant_enu, src, p.freq_hz, p.flux, p.beam, eps=1e-6)
+    assert e.value.status == gpu_lib.EINVAL
+    with pytest.raises(gpu_lib.FvError) as e:
+        ctx.simulate(p.ant_enu, p.src_lmn, p.freq_hz, p.flux, p.beam, eps=1e-8, flags=gpu_lib.PREC_FP32)
+    assert e.value.status == gpu_lib.EUNSUPPORTED
+    with pytest.raises(gpu_lib.FvError) as e:
+        ctx.simulate(p.ant_enu, p.src_lmn, p.freq_hz, p.flux, p.beam, eps=0.5)
+    assert e.value.status == gpu_lib.EINVAL
+    # the context is still usable
+    v = ctx.simulate(p.ant_enu, p.src_lmn, p.freq_hz, p.flux, p.beam, eps=1e-6)
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= 1e-6
+
+
+# ---------------------------------------------------------------- device API
+def test_device_pointer_path_matches_host_path(gpu_lib, ctx):
+    import torch
+    p = synth.small_problem(42, n_ant=30, n_src=800, n_freq=3, hex_layout=True)
+    host, _ = _run(gpu_lib, ctx, p, eps=1e-6)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    vis = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device="cuda")
+    ctx.simulate_dev(d(p.ant_enu), d(p.src_lmn), d(p.freq_hz), d(p.flux), d(p.beam), vis, eps=1e-6)
+    torch.cuda.synchronize()
+    v = vis.cpu().numpy()
+    v = v[..., 0] + 1j * v[..., 1]
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= 1e-6
+    assert oracle.rel_l2(v, host) <= 1e-6
+
+
+def test_fp32_single_frequency(gpu_lib, ctx):
+    p = synth.small_problem(31, n_ant=40, n_src=700, n_freq=1, hex_layout=True)
+    v, rep = _run(gpu_lib, ctx, p, eps=1e-4)
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= 1e-4
+
+
+def test_fp64_multi_frequency(gpu_lib, ctx):
+    p = synth.small_problem(31, n_ant=40, n_src=700, n_freq=3, hex_layout=True)
+    v, rep = _run(gpu_lib, ctx, p, eps=1e-10)
+    errs = [oracle.rel_l2(v[f], oracle.direct_problem(p)[f]) for f in range(3)]
+    assert max(errs) <= 1e-10, errs
