@@ -1,0 +1,232 @@
+"""Benchmark: source x baseline pairs per second of the type-3 NUFFT visibility
+simulator on one MI355X, on the HERA-350 workload (350-antenna hexagonal array,
+1e5 power-law point sources, Gaussian beam, 64 frequencies in 100-200 MHz,
+eps = 1e-6, FP32 grids), inputs resident in HBM.
+
+One step = one call of the whole pipeline (tables, sort, spread, FFT passes,
+interpolation) over all 64 frequencies through the C ABI (fv_simulate_dev).
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(algorithmic bytes / HIP-event time of that kernel), the direct-sum kernels'
+rates on the same workload, the per-step latency percentiles, a parity check
+against the FP64 oracle on a seeded subset, and the oracle's own CPU rate.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (packed)
+METRIC = "src×baseline pairs/s at 1e-6 rel err, NUFFT vs direct DFT; p99 latency"
+KERNEL_OF_STAGE = {"spread": "k_spread", "fft_x": "k_fft", "fft_y": "k_fft", "fft_z": "k_fft", "interp": "k_interp",
+                   "sort": "k_bin/k_scan/k_scatter", "direct": "k_direct", "other": "k_ipsi"}
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def _kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_02130_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, fn), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profiles(kernel: str, units: float):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc summary
+    (profiles/traffic_*.json), only if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != _kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-src", type=int, default=100_000)
+    ap.add_argument("--n-freq", type=int, default=64)
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct-sum comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline and parity sample")
+    ap.add_argument("--profile", action="store_true", help="short run for a profiler: no direct, no CPU leg")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the steps, one device copy of this many MiB (reference for byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py: this build measures one GPU; the multi-GPU sharding (snapshots across GPUs, or "
+              "slab-decomposed FFT with one all-to-all) is a design only.  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.profile:
+        args.no_direct = True
+        args.no_cpu = True
+
+    import numpy as np
+    import torch
+    import paper_2506_02130_amd as fv
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    p = synth.config2(n_src=args.n_src, n_freq=args.n_freq)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    ant, src, freq, flux, beam = d(p.ant_enu), d(p.src_lmn), d(p.freq_hz), d(p.flux), d(p.beam)
+    vis = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    ctx = fv.Context(0)
+    pairs_per_step = float(p.n_src) * p.n_pairs * p.n_freq
+    flags = fv.TIMING
+
+    def step(fl=flags):
+        return ctx.simulate_dev(ant, src, freq, flux, beam, vis, eps=p.eps, flags=fl, stream=stream)
+
+    print(f"bench: workload {p.name}, pairs/step {pairs_per_step:.3e}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------------- timed region
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        reps.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = pairs_per_step / ((t1 - t0) / args.steps)
+    lat = [r["t_total_ms"] for r in reps]
+    print(f"bench: {ms_per_step:.3f} ms/step, {value:.3e} pairs/s", file=sys.stderr, flush=True)
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        xa = torch.ones(n, dtype=torch.float32, device=dev)
+        xb = torch.empty_like(xa)
+        torch.cuda.synchronize()
+        xb.copy_(xa)
+        torch.cuda.synchronize()
+        del xa, xb
+
+    # per-stage HIP-event times of the timed steps
+    names = fv.STAGES
+    stage_ms = {n: sum(r["t_stage_ms"][i] for r in reps) / args.steps for i, n in enumerate(names)}
+    stage_launch = {n: reps[0]["stage_launches"][i] for i, n in enumerate(names)}
+    stage_bytes = {n: reps[0]["stage_bytes"][i] for i, n in enumerate(names)}
+    dom = max((n for n in names if stage_launch[n] > 0), key=lambda n: stage_ms[n])
+    per_launch_ms = stage_ms[dom] / max(stage_launch[dom], 1)
+    per_launch_bytes = stage_bytes[dom] / max(stage_launch[dom], 1)
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": KERNEL_OF_STAGE.get(dom, dom), "stage": dom, "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": _traffic_from_profiles(KERNEL_OF_STAGE.get(dom, dom), 1.0),
+                "avg_launch_ms": per_launch_ms, "bytes_per_launch": per_launch_bytes}
+    stages = {n: {"ms": round(stage_ms[n], 4), "launches": stage_launch[n],
+                  "GBps": (stage_bytes[n] / max(stage_launch[n], 1)) / (stage_ms[n] / max(stage_launch[n], 1) * 1e-3)
+                  / 1e9 if stage_ms[n] > 0 else None}
+              for n in names if stage_launch[n] > 0}
+
+    # ---------------------------------------------------------------- parity + CPU baseline
+    rel_err = None
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        sub = synth.subset_pairs(p.n_ant, 2048, 7)
+        fsel = np.linspace(0, p.n_freq - 1, min(8, p.n_freq)).round().astype(int)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        tc0 = time.perf_counter()
+        ref = oracle.direct_vis(p.ant_enu, p.src_lmn, p.freq_hz[fsel], p.flux[fsel], p.beam[fsel], pairs=sub,
+                                threads=threads)
+        tc1 = time.perf_counter()
+        cpu_pairs = float(p.n_src) * len(sub) * len(fsel)
+        cpu = {"value": cpu_pairs / (tc1 - tc0), "unit": "src×baseline pairs/s", "cores": threads,
+               "kind": "oracle", "sample": f"{len(sub)} seeded pairs x {p.n_src} sources x {len(fsel)} of "
+                                           f"{p.n_freq} frequencies ({cpu_pairs:.2e} pairs, {tc1 - tc0:.1f} s)"}
+        out = vis.cpu().numpy()
+        got = out[fsel][:, sub, 0] + 1j * out[fsel][:, sub, 1]
+        rel_err = oracle.rel_l2(got, ref)
+        print(f"bench: rel l2 vs oracle on the sample {rel_err:.3e}; oracle {cpu['value']:.3e} pairs/s",
+              file=sys.stderr, flush=True)
+
+    # ---------------------------------------------------------------- direct-sum kernels
+    direct = {}
+    if not args.no_direct:
+        for name, method, fl in (("direct_valu", fv.METHOD_DIRECT, fv.TIMING | fv.METHOD_DIRECT),):
+            vis_d = torch.empty_like(vis)
+            r = ctx.simulate_dev(ant, src, freq, flux, beam, vis_d, eps=p.eps, flags=fl, stream=stream)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(2):
+                ta = time.perf_counter()
+                ctx.simulate_dev(ant, src, freq, flux, beam, vis_d, eps=p.eps, flags=fl, stream=stream)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - ta)
+            t = min(ts)
+            a = vis.cpu().numpy()
+            b = vis_d.cpu().numpy()
+            import oracle as _o
+            diff = _o.rel_l2(a[..., 0] + 1j * a[..., 1], b[..., 0] + 1j * b[..., 1])
+            direct[name] = {"pairs_per_s": pairs_per_step / t, "ms": t * 1e3, "nufft_vs_direct_rel_l2": diff}
+            del vis_d
+        best = max(v["pairs_per_s"] for v in direct.values())
+        direct["nufft_speedup_over_best_direct"] = value / best
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "src×baseline pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"hex{p.n_ant} 14.6 m, {p.n_src} power-law sources, Gaussian beam, {p.n_freq} freqs "
+                               f"100-200 MHz, eps 1e-6, 2-D, FP32 grids, inputs in HBM",
+                   "n_ant": p.n_ant, "n_pairs": p.n_pairs, "n_src": p.n_src, "n_freq": p.n_freq, "eps": p.eps,
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rel_l2_vs_oracle": rel_err,
+        "latency_ms": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99), "kind": "per call, host clock"},
+        "stages": stages,
+        "direct": direct or None,
+        "report": {k: reps[-1][k] for k in ("dim", "prec_bits", "w", "fold_axis", "n1", "n2", "model_bytes")},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

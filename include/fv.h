@@ -68,6 +68,19 @@ typedef enum {
 #define FV_METHOD_MFMA     0x20u  /* direct sum as V = Z diag(c) Z^H on matrix cores */
 #define FV_METHOD_MASK     0x30u
 #define FV_NO_FOLD         0x100u /* do not reflect targets into a half-space */
+#define FV_TIMING          0x200u /* record HIP events around every stage launch (the call then
+                                     waits for its own work and fills the t_stage_ms fields) */
+
+/* stage indices of fv_report.t_stage_ms / stage_bytes / stage_launches */
+#define FV_STAGE_SORT      0      /* key, count, scan and scatter of the source records */
+#define FV_STAGE_SPREAD    1      /* ES spreading into LDS tiles, first deconvolution */
+#define FV_STAGE_FFT_X     2
+#define FV_STAGE_FFT_Y     3
+#define FV_STAGE_FFT_Z     4
+#define FV_STAGE_INTERP    5      /* interpolation, second deconvolution, phases */
+#define FV_STAGE_DIRECT    6      /* direct-sum kernels */
+#define FV_STAGE_OTHER     7      /* tables (1/psi2hat, targets) */
+#define FV_NSTAGE          8
 
 typedef struct fv_ctx fv_ctx;
 
@@ -91,6 +104,9 @@ typedef struct {
     double t_total_ms;    /* wall time of the call (host clock, includes sync) */
     double model_bytes;   /* algorithmic HBM bytes of the grid stages (all frequencies) */
     double src_pairs;     /* n_src * n_pairs * n_freq */
+    double t_stage_ms[FV_NSTAGE];     /* FV_TIMING: summed event time of each stage's launches */
+    double stage_bytes[FV_NSTAGE];    /* algorithmic HBM bytes of each stage (all launches) */
+    int stage_launches[FV_NSTAGE];    /* kernel launches per stage */
 } fv_report;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes = 0 means 90%

@@ -27,6 +27,8 @@ DIM_AUTO, DIM_2D, DIM_3D = 0x0, 0x1, 0x2
 PREC_AUTO, PREC_FP32, PREC_FP64 = 0x0, 0x4, 0x8
 METHOD_NUFFT, METHOD_DIRECT, METHOD_MFMA = 0x00, 0x10, 0x20
 NO_FOLD = 0x100
+TIMING = 0x200
+STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_debug_stages")
@@ -49,12 +51,16 @@ class Problem(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("prec_bits", ctypes.c_int), ("method", ctypes.c_int), ("w", ctypes.c_int),
                 ("fold_axis", ctypes.c_int), ("n1", ctypes.c_int * 3), ("n2", ctypes.c_int * 3),
-                ("t_total_ms", ctypes.c_double), ("model_bytes", ctypes.c_double), ("src_pairs", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("model_bytes", ctypes.c_double), ("src_pairs", ctypes.c_double),
+                ("t_stage_ms", ctypes.c_double * 8), ("stage_bytes", ctypes.c_double * 8),
+                ("stage_launches", ctypes.c_int * 8)]
 
     def as_dict(self) -> dict:
         return {"dim": self.dim, "prec_bits": self.prec_bits, "method": self.method, "w": self.w,
                 "fold_axis": self.fold_axis, "n1": list(self.n1), "n2": list(self.n2),
-                "t_total_ms": self.t_total_ms, "model_bytes": self.model_bytes, "src_pairs": self.src_pairs}
+                "t_total_ms": self.t_total_ms, "model_bytes": self.model_bytes, "src_pairs": self.src_pairs,
+                "t_stage_ms": list(self.t_stage_ms), "stage_bytes": list(self.stage_bytes),
+                "stage_launches": list(self.stage_launches)}
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -28,6 +28,7 @@ struct Slot {
     bool own_stream = false;
     Arena arena;   // NUFFT workspace
     Arena inputs;  // uploaded inputs and the device output
+    StageTimer timer;
     ~Slot();
 };
 
@@ -47,7 +48,7 @@ struct fv_ctx {
     double *scalar_buf = nullptr;
     fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
     double *scalars(hipStream_t) {
-        if (!scalar_buf) FV_HIP(hipMalloc((void **)&scalar_buf, 8 * sizeof(double)));
+        if (!scalar_buf) FV_HIP(hipMalloc((void **)&scalar_buf, (8 + 7 * fv::kSrcCheckBlocks) * sizeof(double)));
         return scalar_buf;
     }
     ~fv_ctx();

@@ -60,12 +60,14 @@ __global__ __launch_bounds__(256) void k_direct(const double *ant, int n_ant, lo
     }
 }
 
-__global__ __launch_bounds__(1024) void k_src_check(const double *src, int n_src, double *out) {
-    __shared__ double red[6][1024];
-    __shared__ int badsh[1024];
+// Partial min/max of each direction component and count of invalid
+// directions per block; k_src_reduce folds the partials.
+__global__ __launch_bounds__(256) void k_src_check(const double *src, int n_src, double *part) {
+    __shared__ double red[6][256];
+    __shared__ int badsh[256];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
-    for (int j = threadIdx.x; j < n_src; j += 1024) {
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < n_src; j += gridDim.x * 256) {
         const double a = src[3 * (size_t)j], b = src[3 * (size_t)j + 1], c = src[3 * (size_t)j + 2];
         if (!(isfinite(a) && isfinite(b) && isfinite(c)) || fabs(sqrt(a * a + b * b + c * c) - 1.0) > 1e-9) ++bad;
         lo[0] = fmin(lo[0], a);
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(1024) void k_src_check(const double *src, int n_src
     }
     badsh[threadIdx.x] = bad;
     __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off) {
             for (int a = 0; a < 3; ++a) {
                 red[2 * a][threadIdx.x] = fmin(red[2 * a][threadIdx.x], red[2 * a][threadIdx.x + off]);
@@ -92,12 +94,25 @@ __global__ __launch_bounds__(1024) void k_src_check(const double *src, int n_src
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 6; ++k) out[k] = red[k][0];
-        out[6] = (double)badsh[0];
-        int *cnt = (int *)(out + 7);
-        cnt[0] = 0;
-        cnt[1] = 0;
+        for (int k = 0; k < 6; ++k) part[7 * blockIdx.x + k] = red[k][0];
+        part[7 * blockIdx.x + 6] = (double)badsh[0];
     }
+}
+
+__global__ __launch_bounds__(64) void k_src_reduce(const double *part, int nblk, double *out) {
+    if (threadIdx.x != 0) return;
+    double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    for (int b = 0; b < nblk; ++b) {
+        for (int k = 0; k < 6; k += 2) {
+            v[k] = fmin(v[k], part[7 * b + k]);
+            v[k + 1] = fmax(v[k + 1], part[7 * b + k + 1]);
+        }
+        v[6] += part[7 * b + 6];
+    }
+    for (int k = 0; k < 7; ++k) out[k] = v[k];
+    int *cnt = (int *)(out + 7);
+    cnt[0] = 0;
+    cnt[1] = 0;
 }
 
 __global__ void k_count_nonfinite(const double *x, long long n, int *out) {
@@ -116,9 +131,12 @@ __global__ void k_zero_f64(double *p, long long n) {
 
 void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
                    int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits, double *vis_dev,
-                   hipStream_t st) {
+                   hipStream_t st, StageTimer *tm) {
     const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
     const unsigned nb = (unsigned)((n_pairs + 255) / 256);
+    StageTimer dummy;
+    if (!tm) tm = &dummy;
+    tm->begin(FV_STAGE_DIRECT, st);
     for (int f = 0; f < n_freq; ++f) {
         const double kturn = freq_host[f] / kCLight;
         const double *fl = flux_dev + (size_t)f * n_src;
@@ -140,11 +158,19 @@ void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int 
                                    n_src, fl, bm, kturn, o);
         }
     }
+    tm->end(st);
+    // inputs read once per frequency (directions, strengths), outputs written once
+    tm->add(FV_STAGE_DIRECT, (double)n_freq * ((double)n_src * (24.0 + (beam_dev ? 16.0 : 8.0)) + 16.0 * n_pairs),
+            n_freq);
     FV_HIP(hipGetLastError());
 }
 
 void launch_src_check(const double *src, int n_src, double *out8, hipStream_t st) {
-    hipLaunchKernelGGL(k_src_check, dim3(1), dim3(1024), 0, st, src, n_src, out8);
+    // out8 is followed by room for kSrcCheckBlocks * 7 partial values
+    const int nblk = kSrcCheckBlocks;
+    double *part = out8 + 8;
+    hipLaunchKernelGGL(k_src_check, dim3(nblk), dim3(256), 0, st, src, n_src, part);
+    hipLaunchKernelGGL(k_src_reduce, dim3(1), dim3(64), 0, st, (const double *)part, nblk, out8);
     FV_HIP(hipGetLastError());
 }
 

@@ -21,6 +21,7 @@ constexpr int kMinW = 3;
 constexpr int kQuadHalf = 32;    // positive nodes of the 64-node Gauss-Legendre rule
 constexpr int kSubBin = 8;       // sub-bin edge (cells) of the source sort along x and y
 constexpr int kSubBinZ = 4;      // sub-bin edge along z
+constexpr int kSrcCheckBlocks = 128;  // blocks of the source-direction check reduction
 constexpr int kFftSlots = 30;    // complex values per thread per LDS FFT stage (lines * N <= kFftSlots * threads)
 
 // ---------------------------------------------------------------------------
@@ -139,6 +140,32 @@ struct TargetTable {
     void release();
 };
 
+// Per-stage accounting of one call: algorithmic bytes and launch counts
+// always; HIP event times around every stage when `on`.
+struct StageTimer {
+    bool on = false;
+    double ms[FV_NSTAGE] = {0}, bytes[FV_NSTAGE] = {0};
+    int launches[FV_NSTAGE] = {0};
+    struct Mark {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    int cur = -1;
+    hipEvent_t cur_a = nullptr;
+    void reset(bool enable);
+    void begin(int stage, hipStream_t s);
+    void end(hipStream_t s);
+    void add(int stage, double b, int n_launch) {
+        bytes[stage] += b;
+        launches[stage] += n_launch;
+    }
+    void collect();  // waits for the last recorded event, sums the stage times
+    ~StageTimer();
+};
+
 // One (problem, frequency) snapshot of a NUFFT launch group.
 struct SnapJob {
     SnapPlan plan;
@@ -154,7 +181,7 @@ struct SnapJob {
 // Allocates its workspace from `arena` (which must be idle); returns the
 // algorithmic HBM bytes of the grid stages.
 double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena,
-                     DevCache &cache, hipStream_t s);
+                     DevCache &cache, hipStream_t s, StageTimer *timer = nullptr);
 // Workspace bytes nufft_execute would take for these jobs.
 size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w);
 
@@ -170,10 +197,10 @@ void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
 // Direct sums.
 void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
                    int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits,
-                   double *vis_dev, hipStream_t s);
+                   double *vis_dev, hipStream_t s, StageTimer *timer = nullptr);
 size_t zz_work_bytes(int n_ant, int n_src);
 void launch_zz(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
                int n_freq, const double *flux_dev, const double *beam_dev, int dim, double *vis_dev, void *work,
-               hipStream_t s);
+               hipStream_t s, StageTimer *timer = nullptr);
 
 }  // namespace fv

@@ -71,10 +71,10 @@ void fetch_c128(const void *dev, long long n, int prec_bits, double *host, hipSt
 }  // namespace
 
 double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
-                     hipStream_t st) {
+                     hipStream_t st, StageTimer *timer) {
     if (jobs.empty()) return 0.0;
     Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st);
-    P.fn(P.L, P.snaps_dev, (int)jobs.size(), P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 7);
+    P.fn(P.L, P.snaps_dev, (int)jobs.size(), P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 7, timer);
     return P.L.model_bytes;
 }
 
@@ -84,12 +84,12 @@ void nufft_debug(const SnapJob &job, int dim, int prec_bits, int w, Arena &arena
     Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st);
     const SnapDev &d = P.L.snaps[0];
     const size_t csz = prec_bits == 32 ? 8 : 16;
-    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 1);
+    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 1, nullptr);
     if (spread) fetch_c128((char *)P.grid + d.bufA * csz, job.plan.cells1(), prec_bits, spread, st);
-    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 2);
+    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 2, nullptr);
     const long long fin = dim == 2 ? d.bufA : d.bufB;
     if (fftout) fetch_c128((char *)P.grid + fin * csz, job.plan.cellsM(), prec_bits, fftout, st);
-    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 4);
+    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 4, nullptr);
     FV_HIP(hipStreamSynchronize(st));
 }
 

@@ -48,13 +48,16 @@ struct Rec {
 
 template <int D>
 struct TileShape;
+// Spread tiles: a block of 4 wavefronts covers X x Y x Z cells; each
+// wavefront owns an 8-column slice and walks it in 8 x 8 (x TZ) sub-tiles, one
+// cell (x TZ slices) per lane.
 template <>
 struct TileShape<2> {
     static constexpr int X = 32, Y = 32, Z = 1;
 };
 template <>
 struct TileShape<3> {
-    static constexpr int X = 16, Y = 16, Z = 8;
+    static constexpr int X = 32, Y = 8, Z = 8;
 };
 
 __host__ __device__ inline int sub_bin_edge(int a) { return a < 2 ? kSubBin : kSubBinZ; }
@@ -201,125 +204,157 @@ __global__ __launch_bounds__(256) void k_ipsi(const SnapDev *snaps, R *ipsi) {
 
 template <typename R, int D, int W>
 struct SpreadCfg {
-    static constexpr int TX = TileShape<D>::X, TY = TileShape<D>::Y, TZ = TileShape<D>::Z;
-    static constexpr int CELLS = TX * TY * TZ;
-    static constexpr int WAVE_BYTES = CELLS * (int)sizeof(cplx<R>) + 64 * D * W * (int)sizeof(R);
-    static constexpr int WPB0 = 98304 / WAVE_BYTES;
-    static constexpr int WPB = WPB0 >= 4 ? 4 : (WPB0 >= 2 ? 2 : 1);
-    static constexpr int WD = D == 2 ? W * W : W * W * W;
+    static constexpr int BX = TileShape<D>::X, BY = TileShape<D>::Y, BZ = TileShape<D>::Z;
+    static constexpr int WPB = BX / 8;      // wavefronts per block, one 8-column slice each
+    static constexpr int NT = BY / 8;       // 8 x 8 sub-tiles per slice (along y)
+    static constexpr int TZ = BZ;           // z slices per sub-tile (registers per lane)
+    static constexpr int MAXROWS = 64;      // sub-bin rows of one sub-tile (bounded below)
+    static constexpr int WAVE_BYTES = 64 * D * W * (int)sizeof(R) + 2 * MAXROWS * (int)sizeof(int);
+    static_assert(((8 + W - 1 + kSubBin - 1) / kSubBin + 1) *
+                          (D == 3 ? ((TZ + W - 1 + kSubBinZ - 1) / kSubBinZ + 1) : 1) <= MAXROWS,
+                  "too many sub-bin rows per sub-tile");
+    static_assert(WPB * WAVE_BYTES <= 160 * 1024, "spread staging does not fit in LDS");
 };
 
+// ES kernel weights for the spread (FP32: hardware exp2 and sqrt, about 1
+// ulp; FP64: libm).
+__device__ __forceinline__ float es_phi_fast(float z, float beta) {
+    const float t = fmaxf(1.0f - z * z, 0.0f);
+    return __expf(beta * (__builtin_amdgcn_sqrtf(t) - 1.0f));
+}
+__device__ __forceinline__ double es_phi_fast(double z, double beta) { return es_phi(z, beta); }
+
+// Spreading (gather form).  Each lane owns one cell of an 8 x 8 sub-tile (and
+// TZ z slices in 3-D) and keeps its sum in registers.  The records of the
+// sub-tile's neighbourhood (a few contiguous ranges of the sorted records, one
+// per sub-bin row) are taken 64 at a time: each lane loads one record and
+// writes that record's w kernel weights per axis to LDS; then, record by
+// record, every lane looks up the two (three) weights of its own cell and
+// accumulates.  No atomics; each grid cell is written once, after
+// multiplication by 1/psi2hat (the first deconvolution).
 template <typename R, int D, int W>
-__global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int n_snap, long long total_tiles,
-                                                const int *bins, const Rec<R, D> *recs, const R *ipsi,
-                                                cplx<R> *grid) {
+__global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, const int *bins, const Rec<R, D> *recs,
+                                                const R *ipsi, cplx<R> *grid) {
     using Cfg = SpreadCfg<R, D, W>;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long tile = (long long)blockIdx.x * Cfg::WPB + wave;
-    if (tile >= total_tiles) return;
-    const int s = find_snap(snaps, n_snap, tile, 0);
-    const SnapDev &S = snaps[s];
-    long long t = tile - S.tile_base;
-    int org[3];
-    org[0] = (int)(t % S.ntile[0]) * Cfg::TX;
-    t /= S.ntile[0];
-    org[1] = (int)(t % S.ntile[1]) * Cfg::TY;
-    org[2] = D == 3 ? (int)(t / S.ntile[1]) * Cfg::TZ : 0;
-    const int text[3] = {Cfg::TX, Cfg::TY, Cfg::TZ};
-
-    cplx<R> *acc = (cplx<R> *)(smem + wave * Cfg::WAVE_BYTES);
-    R *kw = (R *)(acc + Cfg::CELLS);  // [64][D][W]
-    for (int c = lane; c < Cfg::CELLS; c += 64) acc[c] = cmake<R>(0, 0);
-
+    const SnapDev &S = snaps[blockIdx.y];
+    const int nbx = (S.n1[0] + Cfg::BX - 1) / Cfg::BX, nby = (S.n1[1] + Cfg::BY - 1) / Cfg::BY;
+    const int nbz = D == 3 ? (S.n1[2] + Cfg::BZ - 1) / Cfg::BZ : 1;
+    const int blk = blockIdx.x;
+    if (blk >= nbx * nby * nbz) return;
+    const int x0 = (blk % nbx) * Cfg::BX + 8 * wave;
+    if (x0 >= S.n1[0]) return;
+    const int yb = ((blk / nbx) % nby) * Cfg::BY;
+    const int z0 = D == 3 ? (blk / (nbx * nby)) * Cfg::BZ : 0;
+    R *kw = (R *)(smem + wave * Cfg::WAVE_BYTES);  // [64][D][W]
+    int *rstart = (int *)(kw + 64 * D * W);
+    int *rpre = rstart + Cfg::MAXROWS;
+    const int cx = lane & 7, cy = lane >> 3;
     const R beta = (R)S.beta;
     const R inv_hw = (R)(2.0 / W);
-    int sblo[3] = {0, 0, 0}, sbhi[3] = {0, 0, 0};
-    bool empty = false;
-    for (int a = 0; a < D; ++a) {
-        int lo = max(0, org[a] - W + 1);
-        int hi = min(S.n1[a] - W, org[a] + text[a] - 1);
-        if (lo > hi) empty = true;
-        sblo[a] = lo / sub_bin_edge(a);
-        sbhi[a] = hi / sub_bin_edge(a);
-    }
     const Rec<R, D> *rs = recs + S.src_base;
     const int *bb = bins + S.bin_base;
-    if (!empty) {
-        for (int sz = sblo[2]; sz <= (D == 3 ? sbhi[2] : 0); ++sz) {
-            for (int sy = sblo[1]; sy <= sbhi[1]; ++sy) {
-                const long long row = ((long long)sz * S.nsb[1] + sy) * S.nsb[0];
-                const int start = bb[row + sblo[0]];
-                const int end = bb[row + sbhi[0] + 1];
-                for (int b0 = start; b0 < end; b0 += 64) {
-                    const int nrec = min(64, end - b0);
-                    int ml0[D];
-                    R mcr = 0, mci = 0;
-                    bool hit = false;
-                    if (lane < nrec) {
-                        const Rec<R, D> r = rs[b0 + lane];
-                        hit = true;
-#pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            ml0[a] = r.l0[a];
-                            hit = hit && (r.l0[a] + W - 1 >= org[a]) && (r.l0[a] <= org[a] + text[a] - 1);
-#pragma unroll
-                            for (int i = 0; i < W; ++i)
-                                kw[(lane * D + a) * W + i] = es_phi((R)((R)i - r.off[a]) * inv_hw, beta);
-                        }
-                        mcr = r.cr;
-                        mci = r.ci;
-                    } else {
-#pragma unroll
-                        for (int a = 0; a < D; ++a) ml0[a] = 0;
-                    }
-                    wave_sync();
-                    unsigned long long hm = __ballot(hit);
-                    while (hm) {
-                        const int r = __ffsll((long long)hm) - 1;
-                        hm &= hm - 1;
-                        int l0[D];
-#pragma unroll
-                        for (int a = 0; a < D; ++a) l0[a] = readlane_i(ml0[a], r) - org[a];
-                        const R cr = readlane_r<R>(mcr, r), ci = readlane_r<R>(mci, r);
-                        const R *kr = kw + r * D * W;
-#pragma unroll 4
-                        for (int q = 0; q < Cfg::WD; q += 64) {
-                            const int cidx = q + lane;
-                            if (cidx < Cfg::WD) {
-                                const int ix = cidx % W;
-                                const int iy = (cidx / W) % W;
-                                const int iz = D == 3 ? cidx / (W * W) : 0;
-                                const int gx = l0[0] + ix, gy = l0[1] + iy, gz = D == 3 ? l0[D - 1] + iz : 0;
-                                if (gx >= 0 && gx < Cfg::TX && gy >= 0 && gy < Cfg::TY && gz >= 0 && gz < Cfg::TZ) {
-                                    R wt = kr[ix] * kr[W + iy];
-                                    if (D == 3) wt *= kr[2 * W + iz];
-                                    cplx<R> &cell = acc[(gz * Cfg::TY + gy) * Cfg::TX + gx];
-                                    cell.x += wt * cr;
-                                    cell.y += wt * ci;
-                                }
-                            }
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                    wave_sync();
-                }
-            }
-        }
-    }
-    wave_sync();
-    // flush: divide by psi2hat at the modes and store each owned cell once
     const R *ix_t = ipsi + S.ipsi_base;
     const R *iy_t = ix_t + S.n1[0];
     const R *iz_t = iy_t + S.n1[1];
     cplx<R> *dst = grid + S.bufA;
-    for (int c = lane; c < Cfg::CELLS; c += 64) {
-        const int lx = c % Cfg::TX, ly = (c / Cfg::TX) % Cfg::TY, lz = c / (Cfg::TX * Cfg::TY);
-        const int gx = org[0] + lx, gy = org[1] + ly, gz = org[2] + lz;
-        if (gx < S.n1[0] && gy < S.n1[1] && (D == 2 || gz < S.n1[2])) {
-            R f = ix_t[gx] * iy_t[gy];
-            if (D == 3) f *= iz_t[gz];
-            dst[((long long)gz * S.n1[1] + gy) * S.n1[0] + gx] = cscale<R>(acc[c], f);
+    const int sx_lo = max(0, x0 - W + 1) / kSubBin, sx_hi = min(S.n1[0] - W, x0 + 7) / kSubBin;
+    int sz_lo = 0, sz_hi = 0;
+    if (D == 3) {
+        sz_lo = max(0, z0 - W + 1) / kSubBinZ;
+        sz_hi = min(S.n1[2] - W, z0 + Cfg::TZ - 1) / kSubBinZ;
+    }
+    for (int t = 0; t < Cfg::NT; ++t) {
+        const int y0 = yb + 8 * t;
+        if (y0 >= S.n1[1]) break;
+        const int sy_lo = max(0, y0 - W + 1) / kSubBin, sy_hi = min(S.n1[1] - W, y0 + 7) / kSubBin;
+        const int ny = sy_hi - sy_lo + 1;
+        const int nrows = ny * (sz_hi - sz_lo + 1);
+        int cnt = 0, st = 0;
+        if (lane < nrows) {
+            const int sy = sy_lo + lane % ny, sz = sz_lo + lane / ny;
+            const long long row = ((long long)sz * S.nsb[1] + sy) * S.nsb[0];
+            st = bb[row + sx_lo];
+            cnt = bb[row + sx_hi + 1] - st;
+        }
+        int inc = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
+        }
+        const int total = __shfl(inc, 63, 64);
+        wave_sync();
+        if (lane < nrows) {
+            rstart[lane] = st;
+            rpre[lane] = inc - cnt;
+        }
+        wave_sync();
+        R accr[Cfg::TZ], acci[Cfg::TZ];
+#pragma unroll
+        for (int k = 0; k < Cfg::TZ; ++k) accr[k] = acci[k] = 0;
+        for (int b0 = 0; b0 < total; b0 += 64) {
+            const int e = b0 + lane;
+            int ml0x = -1000000, ml0y = -1000000, ml0z = -1000000;
+            R mcr = 0, mci = 0;
+            bool hit = false;
+            if (e < total) {
+                int row = 0;
+                while (row + 1 < nrows && rpre[row + 1] <= e) ++row;
+                const Rec<R, D> r = rs[rstart[row] + (e - rpre[row])];
+                ml0x = r.l0[0] - x0;
+                ml0y = r.l0[1] - y0;
+                if constexpr (D == 3) ml0z = r.l0[2] - z0;
+                hit = ml0x > -W && ml0x < 8 && ml0y > -W && ml0y < 8 &&
+                      (D == 2 || (ml0z > -W && ml0z < Cfg::TZ));
+                mcr = r.cr;
+                mci = r.ci;
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int i = 0; i < W; ++i)
+                        kw[(lane * D + a) * W + i] = es_phi_fast((R)((R)i - r.off[a]) * inv_hw, beta);
+            }
+            wave_sync();
+            unsigned long long hm = __ballot(hit);
+            while (hm) {
+                const int r = __ffsll((long long)hm) - 1;
+                hm &= hm - 1;
+                const int dx = cx - readlane_i(ml0x, r), dy = cy - readlane_i(ml0y, r);
+                const R cr = readlane_r<R>(mcr, r), ci = readlane_r<R>(mci, r);
+                const R *kr = kw + r * D * W;
+                const bool in = (unsigned)dx < (unsigned)W && (unsigned)dy < (unsigned)W;
+                const R wxy = in ? kr[dx] * kr[W + dy] : (R)0;
+                if constexpr (D == 2) {
+                    accr[0] += wxy * cr;
+                    acci[0] += wxy * ci;
+                } else {
+                    const int l0z = readlane_i(ml0z, r);
+#pragma unroll
+                    for (int k = 0; k < Cfg::TZ; ++k) {
+                        const int dz = k - l0z;
+                        if ((unsigned)dz < (unsigned)W) {  // uniform across the wave
+                            const R wz = kr[2 * W + dz];
+                            accr[k] += wxy * wz * cr;
+                            acci[k] += wxy * wz * ci;
+                        }
+                    }
+                }
+            }
+            wave_sync();
+        }
+        // flush: divide by psi2hat at the modes and store each owned cell once
+        const int gx = x0 + cx, gy = y0 + cy;
+        if (gx < S.n1[0] && gy < S.n1[1]) {
+            const R fxy = ix_t[gx] * iy_t[gy];
+#pragma unroll
+            for (int k = 0; k < Cfg::TZ; ++k) {
+                const int gz = z0 + k;
+                if (D == 3 && gz >= S.n1[2]) break;
+                const R f = D == 3 ? fxy * iz_t[gz] : fxy;
+                dst[((long long)gz * S.n1[1] + gy) * S.n1[0] + gx] = cmake<R>(accr[k] * f, acci[k] * f);
+            }
         }
     }
 }
@@ -328,7 +363,29 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int n_snap
 // FFT: mixed-radix Stockham (autosort) in LDS, + sign.  Butterfly b of a
 // radix-r stage with p = product of earlier radices reads x[i + j N/r],
 // multiplies input j by W_N^(j k N/(p r)) (k = i mod p), takes the r-point
-// DFT and writes outputs q at (i - k) r + k + q p.
+// DFT and writes outputs q at (i - k) r + k + q p.  The line lives in LDS as
+// separate real and imaginary planes with one pad word every 32 (strided
+// writes of the early stages then spread over the banks).
+__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 5); }
+
+// a / b for 0 <= a < 2^23 with a float reciprocal and one correction step.
+__device__ __forceinline__ int fdiv(int a, int b, float inv_b) {
+    int q = (int)((float)a * inv_b);
+    const int r = a - q * b;
+    q += (r >= b) - (r < 0);
+    return q;
+}
+
+template <typename R>
+__device__ __forceinline__ void dft4(cplx<R> &x0, cplx<R> &x1, cplx<R> &x2, cplx<R> &x3) {
+    const cplx<R> a = cadd<R>(x0, x2), b = csub<R>(x0, x2);
+    const cplx<R> c = cadd<R>(x1, x3), d = cmuli<R>(csub<R>(x1, x3));
+    x0 = cadd<R>(a, c);
+    x2 = csub<R>(a, c);
+    x1 = cadd<R>(b, d);
+    x3 = csub<R>(b, d);
+}
+
 template <typename R, int RAD>
 __device__ __forceinline__ void dft_small(cplx<R> *v) {
     if (RAD == 2) {
@@ -344,12 +401,7 @@ __device__ __forceinline__ void dft_small(cplx<R> *v) {
         v[1] = cadd<R>(m, it);
         v[2] = csub<R>(m, it);
     } else if (RAD == 4) {
-        cplx<R> a = cadd<R>(v[0], v[2]), b = csub<R>(v[0], v[2]);
-        cplx<R> c = cadd<R>(v[1], v[3]), d = cmuli<R>(csub<R>(v[1], v[3]));
-        v[0] = cadd<R>(a, c);
-        v[2] = csub<R>(a, c);
-        v[1] = cadd<R>(b, d);
-        v[3] = csub<R>(b, d);
+        dft4<R>(v[0], v[1], v[2], v[3]);
     } else if (RAD == 5) {
         const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
         const R s1 = (R)0.95105651629515357212, s2 = (R)0.58778525229247312917;
@@ -365,26 +417,56 @@ __device__ __forceinline__ void dft_small(cplx<R> *v) {
         v[4] = csub<R>(r1, i1);
         v[2] = cadd<R>(r2, i2);
         v[3] = csub<R>(r2, i2);
+    } else if (RAD == 8) {
+        // two 4-point DFTs of the even and odd inputs, combined with W_8^q
+        const R h = (R)0.70710678118654752440;
+        cplx<R> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        cplx<R> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<R>(e0, e1, e2, e3);
+        dft4<R>(o0, o1, o2, o3);
+        const cplx<R> t1 = cmake<R>(h * (o1.x - o1.y), h * (o1.x + o1.y));    // W8 o1
+        const cplx<R> t2 = cmuli<R>(o2);                                       // W8^2 o2
+        const cplx<R> t3 = cmake<R>(-h * (o3.x + o3.y), h * (o3.x - o3.y));   // W8^3 o3
+        v[0] = cadd<R>(e0, o0);
+        v[4] = csub<R>(e0, o0);
+        v[1] = cadd<R>(e1, t1);
+        v[5] = csub<R>(e1, t1);
+        v[2] = cadd<R>(e2, t2);
+        v[6] = csub<R>(e2, t2);
+        v[3] = cadd<R>(e3, t3);
+        v[7] = csub<R>(e3, t3);
     }
 }
 
-template <typename R, int TPB, int RAD>
-__device__ __forceinline__ void fft_stage(cplx<R> *buf, int N, int cx, int p, const cplx<R> *tw) {
+// W_N^t from the two LDS tables: coarse[t / 64] * fine[t % 64].
+template <typename R>
+__device__ __forceinline__ cplx<R> twiddle(const cplx<R> *coarse, const cplx<R> *fine, int t) {
+    return cmul<R>(coarse[t >> 6], fine[t & 63]);
+}
+
+template <typename R, int TPB, int RAD, bool MULTI>
+__device__ __forceinline__ void fft_stage(R *re, R *im, int N, int Np, int cx, int p, const cplx<R> *twc,
+                                          const cplx<R> *twf) {
     // every thread holds at most ceil(kFftSlots / RAD) butterflies; the host
     // keeps lines * N <= kFftSlots * TPB so all cx * N / RAD butterflies are covered
     constexpr int ROUNDS = (kFftSlots + RAD - 1) / RAD;
     const int T = N / RAD;
-    const int nb = cx * T;
+    const int nb = MULTI ? cx * T : T;
     const int tws = N / (p * RAD);
+    const float invT = 1.0f / (float)T, invp = 1.0f / (float)p;
     cplx<R> v[ROUNDS][RAD];
 #pragma unroll
     for (int rr = 0; rr < ROUNDS; ++rr) {
         const int b = threadIdx.x + rr * TPB;
         if (b < nb) {
-            const int c = b / T, i = b - c * T;
-            const cplx<R> *src = buf + (long long)c * N + i;
+            const int c = MULTI ? fdiv(b, T, invT) : 0;
+            const int i = b - c * T;
+            const int base = c * Np;
 #pragma unroll
-            for (int j = 0; j < RAD; ++j) v[rr][j] = src[j * T];
+            for (int j = 0; j < RAD; ++j) {
+                const int e = base + lds_pad(i + j * T);
+                v[rr][j] = cmake<R>(re[e], im[e]);
+            }
         }
     }
     __syncthreads();
@@ -392,29 +474,41 @@ __device__ __forceinline__ void fft_stage(cplx<R> *buf, int N, int cx, int p, co
     for (int rr = 0; rr < ROUNDS; ++rr) {
         const int b = threadIdx.x + rr * TPB;
         if (b < nb) {
-            const int c = b / T, i = b - c * T;
-            const int k = i % p;
+            const int c = MULTI ? fdiv(b, T, invT) : 0;
+            const int i = b - c * T;
+            const int k = p == 1 ? 0 : i - fdiv(i, p, invp) * p;
             if (k) {
 #pragma unroll
-                for (int j = 1; j < RAD; ++j) v[rr][j] = cmul<R>(v[rr][j], tw[j * k * tws]);
+                for (int j = 1; j < RAD; ++j) v[rr][j] = cmul<R>(v[rr][j], twiddle<R>(twc, twf, j * k * tws));
             }
             dft_small<R, RAD>(v[rr]);
-            cplx<R> *dst = buf + (long long)c * N + (i - k) * RAD + k;
+            const int o0 = (i - k) * RAD + k, base = c * Np;
 #pragma unroll
-            for (int q = 0; q < RAD; ++q) dst[q * p] = v[rr][q];
+            for (int q = 0; q < RAD; ++q) {
+                const int e = base + lds_pad(o0 + q * p);
+                re[e] = v[rr][q].x;
+                im[e] = v[rr][q].y;
+            }
         }
     }
     __syncthreads();
 }
 
-template <typename R, int TPB>
-__device__ void fft_lds(cplx<R> *buf, int N, int cx, const cplx<R> *tw) {
+template <typename R, int TPB, bool MULTI>
+__device__ void fft_lds(R *re, R *im, int N, int Np, int cx, const cplx<R> *twc, const cplx<R> *twf) {
     int p = 1, rem = N;
-    while (rem % 4 == 0) { fft_stage<R, TPB, 4>(buf, N, cx, p, tw); p *= 4; rem /= 4; }
-    while (rem % 2 == 0) { fft_stage<R, TPB, 2>(buf, N, cx, p, tw); p *= 2; rem /= 2; }
-    while (rem % 3 == 0) { fft_stage<R, TPB, 3>(buf, N, cx, p, tw); p *= 3; rem /= 3; }
-    while (rem % 5 == 0) { fft_stage<R, TPB, 5>(buf, N, cx, p, tw); p *= 5; rem /= 5; }
+    while (rem % 8 == 0) { fft_stage<R, TPB, 8, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 8; rem /= 8; }
+    while (rem % 4 == 0) { fft_stage<R, TPB, 4, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 4; rem /= 4; }
+    while (rem % 2 == 0) { fft_stage<R, TPB, 2, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 2; rem /= 2; }
+    while (rem % 3 == 0) { fft_stage<R, TPB, 3, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 3; rem /= 3; }
+    while (rem % 5 == 0) { fft_stage<R, TPB, 5, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 5; rem /= 5; }
 }
+
+// LDS bytes of the two twiddle tables of an N-point line.
+__host__ __device__ inline int fft_tw_entries(int N) { return (N >> 6) + 1 + 64; }
+
+// Padded LDS length of one FFT line (real or imaginary plane).
+__host__ __device__ inline int fft_line_pad(int N) { return N + (N >> 5) + 1; }
 
 // One pass along axis `a` for every snapshot: lines of n1[a] inputs (already
 // deconvolved), placed at (m mod n2), FFT of length n2, outputs p in [-P, P].
@@ -423,39 +517,79 @@ __device__ void fft_lds(cplx<R> *buf, int N, int cx, const cplx<R> *tw) {
 template <typename R, int TPB>
 __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int n_snap, int a, cplx<R> *grid) {
     extern __shared__ __align__(16) char smem[];
-    cplx<R> *buf = (cplx<R> *)smem;
-    const int s = find_snap(snaps, n_snap, blockIdx.x, a + 1);
-    const SnapDev &S = snaps[s];
+    const SnapDev &S = snaps[blockIdx.y];
     const int N = S.n2[a], n1a = S.n1[a], Ma = S.M[a], Pa = S.P[a], CX = S.cx[a];
-    long long F = 1;
+    const int Np = fft_line_pad(N);
+    long long F = 1, Sl = 1;
     for (int b = 0; b < a; ++b) F *= S.M[b];
+    for (int b = a + 1; b < S.dim; ++b) Sl *= S.n1[b];
     const long long ngrp = (F + CX - 1) / CX;
-    const long long wl = (long long)blockIdx.x - S.wg_base[a];
+    const long long wl = (long long)blockIdx.x;
+    if (wl >= Sl * ngrp) return;
     const long long o = wl / ngrp;
     const long long i0 = (wl - o * ngrp) * CX;
     const int cx = (int)min((long long)CX, F - i0);
+    cplx<R> *twc = (cplx<R> *)smem;  // [N/64 + 1] coarse, then [64] fine twiddles
+    cplx<R> *twf = twc + (N >> 6) + 1;
+    R *re = (R *)(twf + 64);
+    R *im = re + (size_t)cx * Np;
     const bool fromA = (a % 2) == 0;
     const cplx<R> *in = grid + (fromA ? S.bufA : S.bufB) + o * ((long long)n1a * F) + i0;
     cplx<R> *out = grid + (fromA ? S.bufB : S.bufA) + o * ((long long)Ma * F) + i0;
     const cplx<R> *tw = (const cplx<R> *)S.tw[a];
+    for (int t = threadIdx.x; t < (N >> 6) + 1 + 64; t += TPB) {
+        const int g = t <= (N >> 6) ? t << 6 : t - (N >> 6) - 1;
+        twc[t] = tw[g < N ? g : 0];
+    }
     const int half = n1a / 2;
-    for (int e = threadIdx.x; e < cx * N; e += TPB) {
-        const int c = e / N, l2 = e - c * N;
-        if (l2 >= half && l2 < N - half) buf[(long long)c * N + l2] = cmake<R>(0, 0);
+    if (cx == 1) {
+        for (int l2 = threadIdx.x + half; l2 < N - half; l2 += TPB) {
+            re[lds_pad(l2)] = 0;
+            im[lds_pad(l2)] = 0;
+        }
+        for (int l = threadIdx.x; l < n1a; l += TPB) {
+            int idx = l - half;
+            if (idx < 0) idx += N;
+            const cplx<R> v = in[(long long)l * F];
+            re[lds_pad(idx)] = v.x;
+            im[lds_pad(idx)] = v.y;
+        }
+        __syncthreads();
+        fft_lds<R, TPB, false>(re, im, N, Np, 1, twc, twf);
+        for (int po = threadIdx.x; po < Ma; po += TPB) {
+            int idx = po - Pa;
+            idx += idx < 0 ? N : 0;
+            idx -= idx >= N ? N : 0;
+            const int e = lds_pad(idx);
+            out[(long long)po * F] = cmake<R>(re[e], im[e]);
+        }
+        return;
+    }
+    const int zl = N - 2 * half;
+    const float invz = 1.0f / (float)zl, invcx = 1.0f / (float)cx;
+    for (int e = threadIdx.x; e < cx * zl; e += TPB) {
+        const int c = fdiv(e, zl, invz);
+        const int l2 = half + e - c * zl;
+        re[c * Np + lds_pad(l2)] = 0;
+        im[c * Np + lds_pad(l2)] = 0;
     }
     for (int e = threadIdx.x; e < cx * n1a; e += TPB) {
-        const int c = e % cx, l = e / cx;
+        const int l = fdiv(e, cx, invcx), c = e - l * cx;
         int idx = l - half;
         if (idx < 0) idx += N;
-        buf[(long long)c * N + idx] = in[(long long)l * F + c];
+        const cplx<R> v = in[(long long)l * F + c];
+        re[c * Np + lds_pad(idx)] = v.x;
+        im[c * Np + lds_pad(idx)] = v.y;
     }
     __syncthreads();
-    fft_lds<R, TPB>(buf, N, cx, tw);
+    fft_lds<R, TPB, true>(re, im, N, Np, cx, twc, twf);
     for (int e = threadIdx.x; e < cx * Ma; e += TPB) {
-        const int c = e % cx, po = e / cx;
-        int idx = (po - Pa) % N;
-        if (idx < 0) idx += N;
-        out[(long long)po * F + c] = buf[(long long)c * N + idx];
+        const int po = fdiv(e, cx, invcx), c = e - po * cx;
+        int idx = po - Pa;
+        idx += idx < 0 ? N : 0;
+        idx -= idx >= N ? N : 0;
+        const int q = c * Np + lds_pad(idx);
+        out[(long long)po * F + c] = cmake<R>(re[q], im[q]);
     }
 }
 
@@ -585,11 +719,13 @@ inline size_t spread_lds() {
 struct Layout {
     std::vector<SnapDev> snaps;
     long long total_tiles = 0, total_src = 0, total_bins = 0, total_ipsi = 0, total_grid = 0;
-    long long max_src = 0, max_tgt = 0, max_ipsi = 0;
+    long long max_src = 0, max_tgt = 0, max_ipsi = 0, max_tiles = 0;
     long long wg_total[3] = {0, 0, 0};
+    long long max_wg[3] = {0, 0, 0};
     int tpb[3] = {256, 256, 256};
     size_t fft_lds[3] = {0, 0, 0};
     double model_bytes = 0;
+    double sbytes[FV_NSTAGE] = {0, 0, 0, 0, 0, 0, 0, 0};  // algorithmic bytes per stage
 };
 
 // Upper bound on the lines one FFT workgroup transforms together (tunable
@@ -609,6 +745,11 @@ inline int fft_tpb_for(int N) {
     return 1024;
 }
 
+inline size_t rec_bytes(int dim, int prec_bits) {
+    if (prec_bits == 32) return dim == 2 ? sizeof(Rec<float, 2>) : sizeof(Rec<float, 3>);
+    return dim == 2 ? sizeof(Rec<double, 2>) : sizeof(Rec<double, 3>);
+}
+
 inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w) {
     Layout L;
     const size_t csz = prec_bits == 32 ? 8 : 16;
@@ -619,7 +760,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         int nmax = 0;
         for (auto &j : jobs) nmax = std::max(nmax, j.plan.n2[a]);
         L.tpb[a] = fft_tpb_for(nmax);
-        if ((long long)nmax > (long long)kFftSlots * 1024 || (size_t)nmax * csz > 160u * 1024)
+        if ((long long)nmax > (long long)kFftSlots * 1024 || (size_t)fft_line_pad(nmax) * csz > 160u * 1024)
             fail(FV_EUNSUPPORTED, "FFT line of " + std::to_string(nmax) + " points exceeds the LDS transform");
     }
     for (auto &j : jobs) {
@@ -647,6 +788,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         d.degenerate = p.degenerate;
         d.tile_base = L.total_tiles;
         L.total_tiles += ncell;
+        L.max_tiles = std::max(L.max_tiles, ncell);
         d.src_base = L.total_src;
         L.total_src += j.n_src;
         d.bin_base = L.total_bins;
@@ -676,13 +818,15 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
             int cx = 1;
             if (F > 1) {
                 const long long byreg = (long long)kFftSlots * L.tpb[a] / p.n2[a];
-                const long long bylds = 65536LL / ((long long)p.n2[a] * csz);
+                const long long bylds = 65536LL / ((long long)fft_line_pad(p.n2[a]) * csz);
                 cx = (int)std::max(1LL, std::min({F, byreg, bylds, (long long)fft_max_lines()}));
             }
             d.cx[a] = cx;
             d.wg_base[a] = L.wg_total[a];
             L.wg_total[a] += Sl * ((F + cx - 1) / cx);
-            L.fft_lds[a] = std::max(L.fft_lds[a], (size_t)cx * p.n2[a] * csz);
+            L.fft_lds[a] = std::max(L.fft_lds[a], (size_t)cx * fft_line_pad(p.n2[a]) * csz +
+                                                      (size_t)fft_tw_entries(p.n2[a]) * csz);
+            L.max_wg[a] = std::max(L.max_wg[a], Sl * ((F + cx - 1) / cx));
         }
         d.src = j.src;
         d.flux = j.flux;
@@ -721,15 +865,29 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         }
         b += live;
         L.model_bytes += b * csz;
+        {
+            // per stage: sort reads the directions twice, flux/beam once, writes
+            // ranks and records; spread reads the records and writes the grid;
+            // each pass reads and writes its live array; interpolation reads the
+            // final array, the target table and writes the output
+            const double rsz = (double)rec_bytes(dim, prec_bits);
+            const double ns = (double)j.n_src, nt = (double)j.tt->n_tgt;
+            L.sbytes[FV_STAGE_SORT] += ns * (2.0 * 8 * dim + 16 + 4 + 4 + 4 + rsz) + 8.0 * (double)nb;
+            L.sbytes[FV_STAGE_SPREAD] += ns * rsz + cells_in * csz;
+            double lv = cells_in;
+            for (int a = 0; a < dim; ++a) {
+                double oc = lv / p.n1[a] * p.M[a];
+                L.sbytes[FV_STAGE_FFT_X + a] += (lv + oc) * csz;
+                lv = oc;
+            }
+            L.sbytes[FV_STAGE_INTERP] += lv * csz + nt * (16.0 * dim + 4 + 16);
+            L.sbytes[FV_STAGE_OTHER] += (double)nipsi * (prec_bits == 32 ? 4 : 8);
+        }
         L.snaps.push_back(d);
     }
     return L;
 }
 
-inline size_t rec_bytes(int dim, int prec_bits) {
-    if (prec_bits == 32) return dim == 2 ? sizeof(Rec<float, 2>) : sizeof(Rec<float, 3>);
-    return dim == 2 ? sizeof(Rec<double, 2>) : sizeof(Rec<double, 3>);
-}
 
 inline size_t layout_bytes(const Layout &L, int dim, int prec_bits, int n_snap) {
     const size_t csz = prec_bits == 32 ? 8 : 16, rsz = prec_bits == 32 ? 4 : 8;
@@ -746,14 +904,20 @@ inline void ensure_lds(const void *fn, size_t bytes) {
 // stages: bit 0 sort + spread, bit 1 FFT passes, bit 2 interpolation.
 template <typename R, int D, int W>
 void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bins, int *rank, void *recs_v,
-                  R *ipsi, cplx<R> *grid, hipStream_t st, int stages) {
+                  R *ipsi, cplx<R> *grid, hipStream_t st, int stages, StageTimer *tm) {
+    StageTimer dummy;
+    if (!tm) tm = &dummy;
     auto recs = (Rec<R, D> *)recs_v;
     auto blocks = [](long long n, int b) { return (unsigned)((n + b - 1) / b); };
     if (stages & 1) {
     if (L.total_bins)
         hipLaunchKernelGGL(k_fill_int, dim3(blocks(L.total_bins, 256)), dim3(256), 0, st, bins, L.total_bins, 0);
+    tm->begin(FV_STAGE_OTHER, st);
     if (L.max_ipsi)
         hipLaunchKernelGGL(k_ipsi<R>, dim3(blocks(L.max_ipsi, 256), n_snap), dim3(256), 0, st, snaps_dev, ipsi);
+    tm->end(st);
+    tm->add(FV_STAGE_OTHER, L.sbytes[FV_STAGE_OTHER], 1);
+    tm->begin(FV_STAGE_SORT, st);
     if (L.max_src) {
         hipLaunchKernelGGL(k_bin<D>, dim3(blocks(L.max_src, 256), n_snap), dim3(256), 0, st, snaps_dev, bins, rank);
     }
@@ -762,18 +926,23 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
         hipLaunchKernelGGL((k_scatter<R, D>), dim3(blocks(L.max_src, 256), n_snap), dim3(256), 0, st, snaps_dev,
                            (const int *)bins, (const int *)rank, recs);
     }
+    tm->end(st);
+    tm->add(FV_STAGE_SORT, L.sbytes[FV_STAGE_SORT], 4);
     {
         using Cfg = SpreadCfg<R, D, W>;
+        tm->begin(FV_STAGE_SPREAD, st);
         const size_t lds = spread_lds<R, D, W>();
         ensure_lds((const void *)k_spread<R, D, W>, lds);
-        hipLaunchKernelGGL((k_spread<R, D, W>), dim3(blocks(L.total_tiles, Cfg::WPB)), dim3(64 * Cfg::WPB), lds, st,
-                           snaps_dev, n_snap, L.total_tiles, (const int *)bins, (const Rec<R, D> *)recs,
-                           (const R *)ipsi, grid);
+        hipLaunchKernelGGL((k_spread<R, D, W>), dim3((unsigned)L.max_tiles, n_snap), dim3(64 * Cfg::WPB), lds, st,
+                           snaps_dev, (const int *)bins, (const Rec<R, D> *)recs, (const R *)ipsi, grid);
+        tm->end(st);
+        tm->add(FV_STAGE_SPREAD, L.sbytes[FV_STAGE_SPREAD], 1);
     }
     }
     if (stages & 2)
     for (int a = 0; a < D; ++a) {
-        const unsigned nb = (unsigned)L.wg_total[a];
+        const dim3 nb((unsigned)L.max_wg[a], (unsigned)n_snap);
+        tm->begin(FV_STAGE_FFT_X + a, st);
         switch (L.tpb[a]) {
             case 256:
                 ensure_lds((const void *)k_fft<R, 256>, L.fft_lds[a]);
@@ -789,20 +958,26 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
                                    grid);
                 break;
         }
+        tm->end(st);
+        tm->add(FV_STAGE_FFT_X + a, L.sbytes[FV_STAGE_FFT_X + a], 1);
     }
-    if ((stages & 4) && L.max_tgt)
+    if ((stages & 4) && L.max_tgt) {
+        tm->begin(FV_STAGE_INTERP, st);
         hipLaunchKernelGGL((k_interp<R, D, W>), dim3(blocks(L.max_tgt, 256), n_snap), dim3(256), 0, st, snaps_dev,
                            (const cplx<R> *)grid);
+        tm->end(st);
+        tm->add(FV_STAGE_INTERP, L.sbytes[FV_STAGE_INTERP], 1);
+    }
     FV_HIP(hipGetLastError());
 }
 
 using PipeFn = void (*)(const Layout &, const SnapDev *, int, int *, int *, void *, void *, void *, hipStream_t,
-                        int);
+                        int, StageTimer *);
 
 template <typename R, int D, int W>
 void pipe_entry(const Layout &L, const SnapDev *sd, int n, int *bins, int *rank, void *recs, void *ipsi, void *grid,
-                hipStream_t st, int stages) {
-    run_pipeline<R, D, W>(L, sd, n, bins, rank, recs, (R *)ipsi, (cplx<R> *)grid, st, stages);
+                hipStream_t st, int stages, StageTimer *tm) {
+    run_pipeline<R, D, W>(L, sd, n, bins, rank, recs, (R *)ipsi, (cplx<R> *)grid, st, stages, tm);
 }
 
 template <typename R, int D, int... Ws>

@@ -68,6 +68,55 @@ void TargetTable::release() {
     tidx = nullptr;
 }
 
+void StageTimer::reset(bool enable) {
+    on = enable;
+    for (int i = 0; i < FV_NSTAGE; ++i) {
+        ms[i] = bytes[i] = 0;
+        launches[i] = 0;
+    }
+    marks.clear();
+    used = 0;
+    cur = -1;
+}
+
+void StageTimer::begin(int stage, hipStream_t s) {
+    if (!on) return;
+    if (used + 2 > pool.size()) {
+        for (int i = 0; i < 16; ++i) {
+            hipEvent_t e;
+            FV_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+    }
+    cur = stage;
+    cur_a = pool[used++];
+    FV_HIP(hipEventRecord(cur_a, s));
+}
+
+void StageTimer::end(hipStream_t s) {
+    if (!on || cur < 0) return;
+    hipEvent_t b = pool[used++];
+    FV_HIP(hipEventRecord(b, s));
+    marks.push_back({cur, cur_a, b});
+    cur = -1;
+}
+
+void StageTimer::collect() {
+    if (!on || marks.empty()) return;
+    FV_HIP(hipEventSynchronize(marks.back().b));
+    for (auto &m : marks) {
+        float t = 0;
+        FV_HIP(hipEventElapsedTime(&t, m.a, m.b));
+        ms[m.stage] += t;
+    }
+    marks.clear();
+    used = 0;
+}
+
+StageTimer::~StageTimer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 // ---------------------------------------------------------------------------
 static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
     const unsigned char *c = (const unsigned char *)p;
@@ -209,6 +258,8 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
     const int prec = choose_prec(p->eps, p->flags);
     fv_report r;
     std::memset(&r, 0, sizeof(r));
+    StageTimer &tm = slot.timer;
+    tm.reset((p->flags & FV_TIMING) != 0);
     r.dim = dim;
     r.prec_bits = prec;
     r.method = (int)method;
@@ -217,12 +268,13 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
     if (n_src == 0) {
         launch_zero_c128(vis_dev, n_pairs * n_freq, st);
     } else if (method == FV_METHOD_DIRECT) {
-        launch_direct(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, prec, vis_dev, st);
+        launch_direct(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, prec, vis_dev, st,
+                      &tm);
     } else if (method == FV_METHOD_MFMA) {
         slot.arena.ensure(zz_work_bytes(n_ant, n_src));
         slot.arena.reset();
         void *work = slot.arena.take(zz_work_bytes(n_ant, n_src));
-        launch_zz(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, vis_dev, work, st);
+        launch_zz(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, vis_dev, work, st, &tm);
     } else {
         const bool fold = !(p->flags & FV_NO_FOLD);
         GeomPlan g = ctx_geometry(ctx, p->ant_enu, n_ant, dim, p->eps, in.s_c, in.S, fold);
@@ -255,7 +307,7 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
             while (i1 < jobs.size() && tot + each[i1] <= cap) tot += each[i1++];
             std::vector<SnapJob> part(jobs.begin() + i0, jobs.begin() + i1);
             if (i0 > 0) FV_HIP(hipStreamSynchronize(st));  // the arena is reused
-            r.model_bytes += nufft_execute(part, dim, prec, g.w, slot.arena, ctx->cache, st);
+            r.model_bytes += nufft_execute(part, dim, prec, g.w, slot.arena, ctx->cache, st, &tm);
             i0 = i1;
         }
         const SnapPlan top = jobs.empty() ? SnapPlan() : jobs[best_f].plan;
@@ -267,6 +319,12 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
         }
     }
     FV_HIP(hipGetLastError());
+    tm.collect();
+    for (int i = 0; i < FV_NSTAGE; ++i) {
+        r.t_stage_ms[i] = tm.ms[i];
+        r.stage_bytes[i] = tm.bytes[i];
+        r.stage_launches[i] = tm.launches[i];
+    }
     if (rep) *rep = r;
 }
 

@@ -7,7 +7,7 @@ namespace fv {
 size_t zz_work_bytes(int, int) { return 256; }
 
 void launch_zz(const double *, int, const double *, int, const double *, int, const double *, const double *, int,
-               double *, void *, hipStream_t) {
+               double *, void *, hipStream_t, StageTimer *) {
     fail(FV_EUNSUPPORTED, "matrix-core direct sum not built yet");
 }
 
