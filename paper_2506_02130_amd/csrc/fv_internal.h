@@ -22,7 +22,6 @@ constexpr int kQuadHalf = 32;    // positive nodes of the 64-node Gauss-Legendre
 constexpr int kSubBin = 8;       // sub-bin edge (cells) of the source sort along x and y
 constexpr int kSubBinZ = 4;      // sub-bin edge along z
 constexpr int kSrcCheckBlocks = 128;  // blocks of the source-direction check reduction
-constexpr int kFftSlots = 30;    // complex values per thread per LDS FFT stage (lines * N <= kFftSlots * threads)
 
 // ---------------------------------------------------------------------------
 // Errors: internal code throws fv::Error; every ABI entry converts it to a

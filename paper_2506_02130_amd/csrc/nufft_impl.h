@@ -53,7 +53,7 @@ struct TileShape;
 // cell (x TZ slices) per lane.
 template <>
 struct TileShape<2> {
-    static constexpr int X = 32, Y = 32, Z = 1;
+    static constexpr int X = 64, Y = 16, Z = 1;  // 4 matrix-core tiles of 16 x 16
 };
 template <>
 struct TileShape<3> {
@@ -360,6 +360,143 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, const int 
 }
 
 // ---------------------------------------------------------------------------
+// 2-D spreading on the matrix cores.  The spread into one 16 x 16 tile is a
+// sum of outer products over the tile's records r,
+//     b[y][x] = sum_r ky_r(y) * (c'_r kx_r(x)),
+// i.e. the 16 x 16 x R product KY^T (C KX), accumulated 4 records at a time
+// by v_mfma_{f32,f64}_16x16x4 (A = y weights of 4 records, B = strength-scaled
+// x weights, real and imaginary parts in two accumulators).  Each lane builds
+// one A and one B element per step from the records staged in LDS.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+    typedef mfma_f4 T;
+    static __device__ __forceinline__ T step(float a, float b, T c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // accumulator register r of lane l holds row 4 (l / 16) + r, column l % 16
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct MfmaAcc<double> {
+    typedef mfma_d4 T;
+    static __device__ __forceinline__ T step(double a, double b, T c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // accumulator register r of lane l holds row (l / 16) + 4 r, column l % 16
+    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+template <typename R, int W>
+struct SpreadMfmaCfg {
+    static constexpr int T = 16;            // tile edge
+    static constexpr int WPB = 4;           // wavefronts (tiles) per block, along x
+    static constexpr int BX = T * WPB, BY = T;
+    static constexpr int MAXROWS = 8;       // sub-bin rows per tile
+    // staged records: l0x, l0y (int), offx, offy, cr, ci (R)
+    static constexpr int WAVE_BYTES = 64 * (2 * (int)sizeof(int) + 4 * (int)sizeof(R)) + 2 * MAXROWS * (int)sizeof(int);
+    static_assert((T + W - 1 + kSubBin - 1) / kSubBin + 1 <= MAXROWS, "too many sub-bin rows per tile");
+};
+
+template <typename R, int W>
+__global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, const int *bins, const Rec<R, 2> *recs,
+                                                     const R *ipsi, cplx<R> *grid) {
+    using Cfg = SpreadMfmaCfg<R, W>;
+    using MA = MfmaAcc<R>;
+    extern __shared__ __align__(16) char smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const SnapDev &S = snaps[blockIdx.y];
+    const int nbx = (S.n1[0] + Cfg::BX - 1) / Cfg::BX, nby = (S.n1[1] + Cfg::BY - 1) / Cfg::BY;
+    const int blk = blockIdx.x;
+    if (blk >= nbx * nby) return;
+    const int x0 = (blk % nbx) * Cfg::BX + Cfg::T * wave;
+    if (x0 >= S.n1[0]) return;
+    const int y0 = (blk / nbx) * Cfg::BY;
+    char *wbase = smem + wave * Cfg::WAVE_BYTES;
+    int *sl0x = (int *)wbase, *sl0y = sl0x + 64;
+    R *soffx = (R *)(sl0y + 64), *soffy = soffx + 64, *scr = soffy + 64, *sci = scr + 64;
+    int *rstart = (int *)(sci + 64), *rpre = rstart + Cfg::MAXROWS;
+    const R beta = (R)S.beta;
+    const R inv_hw = (R)(2.0 / W);
+    const Rec<R, 2> *rs = recs + S.src_base;
+    const int *bb = bins + S.bin_base;
+    // sub-bin rows of records whose footprint meets the tile
+    const int sx_lo = max(0, x0 - W + 1) / kSubBin, sx_hi = min(S.n1[0] - W, x0 + Cfg::T - 1) / kSubBin;
+    const int sy_lo = max(0, y0 - W + 1) / kSubBin, sy_hi = min(S.n1[1] - W, y0 + Cfg::T - 1) / kSubBin;
+    const int nrows = (sx_lo > sx_hi || sy_lo > sy_hi) ? 0 : sy_hi - sy_lo + 1;
+    int cnt = 0, st = 0;
+    if (lane < nrows) {
+        const long long row = (long long)(sy_lo + lane) * S.nsb[0];
+        st = bb[row + sx_lo];
+        cnt = bb[row + sx_hi + 1] - st;
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    const int total = __shfl(inc, 63, 64);
+    if (lane < nrows) {
+        rstart[lane] = st;
+        rpre[lane] = inc - cnt;
+    }
+    wave_sync();
+    typename MA::T accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+    const int li = lane & 15, lk = lane >> 4;  // A row / B column index, record slot of the 4
+    for (int b0 = 0; b0 < total; b0 += 64) {
+        const int e = b0 + lane;
+        if (e < total) {
+            int row = 0;
+            while (row + 1 < nrows && rpre[row + 1] <= e) ++row;
+            const Rec<R, 2> r = rs[rstart[row] + (e - rpre[row])];
+            sl0x[lane] = r.l0[0] - x0;
+            sl0y[lane] = r.l0[1] - y0;
+            soffx[lane] = r.off[0];
+            soffy[lane] = r.off[1];
+            scr[lane] = r.cr;
+            sci[lane] = r.ci;
+        }
+        wave_sync();
+        const int nb = min(64, total - b0);
+#pragma unroll 2
+        for (int g = 0; g < nb; g += 4) {
+            const int rr = g + lk;
+            R a = 0, bre = 0, bim = 0;
+            if (rr < nb) {
+                const int dy = li - sl0y[rr], dx = li - sl0x[rr];
+                if ((unsigned)dy < (unsigned)W) a = es_phi_fast((R)((R)dy - soffy[rr]) * inv_hw, beta);
+                if ((unsigned)dx < (unsigned)W) {
+                    const R kx = es_phi_fast((R)((R)dx - soffx[rr]) * inv_hw, beta);
+                    bre = scr[rr] * kx;
+                    bim = sci[rr] * kx;
+                }
+            }
+            accr = MA::step(a, bre, accr);
+            acci = MA::step(a, bim, acci);
+        }
+        wave_sync();
+    }
+    // flush: divide by psi2hat at the modes, store each owned cell once
+    const R *ix_t = ipsi + S.ipsi_base;
+    const R *iy_t = ix_t + S.n1[0];
+    cplx<R> *dst = grid + S.bufA;
+    const int gx = x0 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gy = y0 + MA::row(lane, r);
+        if (gx < S.n1[0] && gy < S.n1[1]) {
+            const R f = ix_t[gx] * iy_t[gy];
+            dst[(long long)gy * S.n1[0] + gx] = cmake<R>(accr[r] * f, acci[r] * f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FFT: mixed-radix Stockham (autosort) in LDS, + sign.  Butterfly b of a
 // radix-r stage with p = product of earlier radices reads x[i + j N/r],
 // multiplies input j by W_N^(j k N/(p r)) (k = i mod p), takes the r-point
@@ -444,82 +581,75 @@ __device__ __forceinline__ cplx<R> twiddle(const cplx<R> *coarse, const cplx<R> 
     return cmul<R>(coarse[t >> 6], fine[t & 63]);
 }
 
+// LDS index of element e of a line: one pad complex every 16.
+__device__ __forceinline__ int cpad(int e) { return e + (e >> 4); }
+__host__ __device__ inline int cline_pad(int L) { return L + (L >> 4) + 1; }
+
+// One radix-RAD Stockham stage over cx lines of L points, out of place
+// (src -> dst, interleaved complex in LDS padded by cpad).  Twiddle exponents
+// are in units of W_L = W_N^tmul.  Each thread walks its butterflies one at a
+// time, so only one butterfly is live in registers.
 template <typename R, int TPB, int RAD, bool MULTI>
-__device__ __forceinline__ void fft_stage(R *re, R *im, int N, int Np, int cx, int p, const cplx<R> *twc,
-                                          const cplx<R> *twf) {
-    // every thread holds at most ceil(kFftSlots / RAD) butterflies; the host
-    // keeps lines * N <= kFftSlots * TPB so all cx * N / RAD butterflies are covered
-    constexpr int ROUNDS = (kFftSlots + RAD - 1) / RAD;
-    const int T = N / RAD;
+__device__ __forceinline__ void fft_stage(const cplx<R> *src, cplx<R> *dst, int L, int Lp, int cx, int p, int tmul,
+                                          const cplx<R> *twc, const cplx<R> *twf) {
+    const int T = L / RAD;
     const int nb = MULTI ? cx * T : T;
-    const int tws = N / (p * RAD);
+    const int tws = (L / (p * RAD)) * tmul;
     const float invT = 1.0f / (float)T, invp = 1.0f / (float)p;
-    cplx<R> v[ROUNDS][RAD];
+#pragma unroll 1
+    for (int b = threadIdx.x; b < nb; b += TPB) {
+        const int c = MULTI ? fdiv(b, T, invT) : 0;
+        const int i = b - c * T;
+        const int k = p == 1 ? 0 : i - fdiv(i, p, invp) * p;
+        const cplx<R> *s_ = src + c * Lp;
+        cplx<R> v[RAD];
 #pragma unroll
-    for (int rr = 0; rr < ROUNDS; ++rr) {
-        const int b = threadIdx.x + rr * TPB;
-        if (b < nb) {
-            const int c = MULTI ? fdiv(b, T, invT) : 0;
-            const int i = b - c * T;
-            const int base = c * Np;
+        for (int j = 0; j < RAD; ++j) v[j] = s_[cpad(i + j * T)];
+        if (k) {
 #pragma unroll
-            for (int j = 0; j < RAD; ++j) {
-                const int e = base + lds_pad(i + j * T);
-                v[rr][j] = cmake<R>(re[e], im[e]);
-            }
+            for (int j = 1; j < RAD; ++j) v[j] = cmul<R>(v[j], twiddle<R>(twc, twf, j * k * tws));
         }
-    }
-    __syncthreads();
+        dft_small<R, RAD>(v);
+        cplx<R> *d_ = dst + c * Lp;
+        const int o0 = (i - k) * RAD + k;
 #pragma unroll
-    for (int rr = 0; rr < ROUNDS; ++rr) {
-        const int b = threadIdx.x + rr * TPB;
-        if (b < nb) {
-            const int c = MULTI ? fdiv(b, T, invT) : 0;
-            const int i = b - c * T;
-            const int k = p == 1 ? 0 : i - fdiv(i, p, invp) * p;
-            if (k) {
-#pragma unroll
-                for (int j = 1; j < RAD; ++j) v[rr][j] = cmul<R>(v[rr][j], twiddle<R>(twc, twf, j * k * tws));
-            }
-            dft_small<R, RAD>(v[rr]);
-            const int o0 = (i - k) * RAD + k, base = c * Np;
-#pragma unroll
-            for (int q = 0; q < RAD; ++q) {
-                const int e = base + lds_pad(o0 + q * p);
-                re[e] = v[rr][q].x;
-                im[e] = v[rr][q].y;
-            }
-        }
+        for (int q = 0; q < RAD; ++q) d_[cpad(o0 + q * p)] = v[q];
     }
     __syncthreads();
 }
 
+// Mixed-radix FFT of cx lines; the input is in `a`, `b` is scratch of the same
+// size; returns the buffer holding the result.
 template <typename R, int TPB, bool MULTI>
-__device__ void fft_lds(R *re, R *im, int N, int Np, int cx, const cplx<R> *twc, const cplx<R> *twf) {
-    int p = 1, rem = N;
-    while (rem % 8 == 0) { fft_stage<R, TPB, 8, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 8; rem /= 8; }
-    while (rem % 4 == 0) { fft_stage<R, TPB, 4, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 4; rem /= 4; }
-    while (rem % 2 == 0) { fft_stage<R, TPB, 2, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 2; rem /= 2; }
-    while (rem % 3 == 0) { fft_stage<R, TPB, 3, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 3; rem /= 3; }
-    while (rem % 5 == 0) { fft_stage<R, TPB, 5, MULTI>(re, im, N, Np, cx, p, twc, twf); p *= 5; rem /= 5; }
+__device__ cplx<R> *fft_lds(cplx<R> *a, cplx<R> *b, int L, int Lp, int cx, int tmul, const cplx<R> *twc,
+                            const cplx<R> *twf) {
+    int p = 1, rem = L;
+    while (rem % 8 == 0) { fft_stage<R, TPB, 8, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 8; rem /= 8; }
+    while (rem % 4 == 0) { fft_stage<R, TPB, 4, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 4; rem /= 4; }
+    while (rem % 2 == 0) { fft_stage<R, TPB, 2, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 2; rem /= 2; }
+    while (rem % 3 == 0) { fft_stage<R, TPB, 3, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 3; rem /= 3; }
+    while (rem % 5 == 0) { fft_stage<R, TPB, 5, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 5; rem /= 5; }
+    return a;
 }
 
-// LDS bytes of the two twiddle tables of an N-point line.
+// Entries of the two twiddle tables of an N-point line.
 __host__ __device__ inline int fft_tw_entries(int N) { return (N >> 6) + 1 + 64; }
 
-// Padded LDS length of one FFT line (real or imaginary plane).
-__host__ __device__ inline int fft_line_pad(int N) { return N + (N >> 5) + 1; }
-
-// One pass along axis `a` for every snapshot: lines of n1[a] inputs (already
-// deconvolved), placed at (m mod n2), FFT of length n2, outputs p in [-P, P].
+// One pass along axis `a` for every snapshot.  A line holds the n1 deconvolved
+// mode values b~_m, m in [-n1/2, n1/2); the pass evaluates
+// g_p = sum_m b~_m W_N^(m p), N = n2 = 2 n1, at p in [-P, P] only.  With
+// a[j] = b~_m at j = m mod n1, the even outputs are g_2k = sum_j a[j] W_n1^(jk)
+// and the odd outputs g_2k+1 = sum_j s_j a[j] W_N^j W_n1^(jk), s_j = +1 for
+// j < n1/2 and -1 otherwise (W_N^n1 = -1): two n1-point FFTs per line, with
+// no zero padding held in LDS.
 // Input layout [slow: n1 of axes > a][n1_a][fast: M of axes < a]; output
 // [slow][M_a][fast].  Passes alternate bufA -> bufB -> bufA (-> bufB).
 template <typename R, int TPB>
-__global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int n_snap, int a, cplx<R> *grid) {
+__global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R> *grid) {
     extern __shared__ __align__(16) char smem[];
     const SnapDev &S = snaps[blockIdx.y];
-    const int N = S.n2[a], n1a = S.n1[a], Ma = S.M[a], Pa = S.P[a], CX = S.cx[a];
-    const int Np = fft_line_pad(N);
+    const int N = S.n2[a], L = S.n1[a], Ma = S.M[a], Pa = S.P[a], CX = S.cx[a];
+    const int Lp = cline_pad(L), half = L / 2;
     long long F = 1, Sl = 1;
     for (int b = 0; b < a; ++b) F *= S.M[b];
     for (int b = a + 1; b < S.dim; ++b) Sl *= S.n1[b];
@@ -529,67 +659,46 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int n_snap, i
     const long long o = wl / ngrp;
     const long long i0 = (wl - o * ngrp) * CX;
     const int cx = (int)min((long long)CX, F - i0);
-    cplx<R> *twc = (cplx<R> *)smem;  // [N/64 + 1] coarse, then [64] fine twiddles
+    cplx<R> *twc = (cplx<R> *)smem;  // [N/64 + 1] coarse, then [64] fine twiddles of W_N
     cplx<R> *twf = twc + (N >> 6) + 1;
-    R *re = (R *)(twf + 64);
-    R *im = re + (size_t)cx * Np;
+    cplx<R> *buf = twf + 64;              // [cx][Lp]
+    cplx<R> *buf2 = buf + (size_t)cx * Lp;  // ping-pong partner
     const bool fromA = (a % 2) == 0;
-    const cplx<R> *in = grid + (fromA ? S.bufA : S.bufB) + o * ((long long)n1a * F) + i0;
+    const cplx<R> *in = grid + (fromA ? S.bufA : S.bufB) + o * ((long long)L * F) + i0;
     cplx<R> *out = grid + (fromA ? S.bufB : S.bufA) + o * ((long long)Ma * F) + i0;
     const cplx<R> *tw = (const cplx<R> *)S.tw[a];
     for (int t = threadIdx.x; t < (N >> 6) + 1 + 64; t += TPB) {
         const int g = t <= (N >> 6) ? t << 6 : t - (N >> 6) - 1;
         twc[t] = tw[g < N ? g : 0];
     }
-    const int half = n1a / 2;
-    if (cx == 1) {
-        for (int l2 = threadIdx.x + half; l2 < N - half; l2 += TPB) {
-            re[lds_pad(l2)] = 0;
-            im[lds_pad(l2)] = 0;
-        }
-        for (int l = threadIdx.x; l < n1a; l += TPB) {
-            int idx = l - half;
-            if (idx < 0) idx += N;
-            const cplx<R> v = in[(long long)l * F];
-            re[lds_pad(idx)] = v.x;
-            im[lds_pad(idx)] = v.y;
+    const float invcx = 1.0f / (float)cx;
+    for (int parity = 0; parity < 2; ++parity) {
+        if (parity) __syncthreads();  // the even outputs have been read out of buf
+        for (int e = threadIdx.x; e < cx * L; e += TPB) {
+            const int l = fdiv(e, cx, invcx), c = e - l * cx;
+            int j = l + half;
+            if (j >= L) j -= L;
+            cplx<R> v = in[(long long)l * F + c];
+            if (parity) {
+                v = cmul<R>(v, twiddle<R>(twc, twf, j));
+                if (j >= half) v = cmake<R>(-v.x, -v.y);
+            }
+            buf[c * Lp + cpad(j)] = v;
         }
         __syncthreads();
-        fft_lds<R, TPB, false>(re, im, N, Np, 1, twc, twf);
-        for (int po = threadIdx.x; po < Ma; po += TPB) {
-            int idx = po - Pa;
-            idx += idx < 0 ? N : 0;
-            idx -= idx >= N ? N : 0;
-            const int e = lds_pad(idx);
-            out[(long long)po * F] = cmake<R>(re[e], im[e]);
+        const cplx<R> *res = cx == 1 ? fft_lds<R, TPB, false>(buf, buf2, L, Lp, 1, 2, twc, twf)
+                                     : fft_lds<R, TPB, true>(buf, buf2, L, Lp, cx, 2, twc, twf);
+        // outputs p in [-P, P] of this parity: p = p0 + 2 q
+        const int p0 = ((-Pa) & 1) == parity ? -Pa : -Pa + 1;
+        const int cnt = (Pa - p0) / 2 + 1;
+        for (int e = threadIdx.x; e < cx * cnt; e += TPB) {
+            const int q = fdiv(e, cx, invcx), c = e - q * cx;
+            const int pp = p0 + 2 * q;
+            int k = (pp - parity) / 2;
+            k %= L;
+            if (k < 0) k += L;
+            out[(long long)(pp + Pa) * F + c] = res[c * Lp + cpad(k)];
         }
-        return;
-    }
-    const int zl = N - 2 * half;
-    const float invz = 1.0f / (float)zl, invcx = 1.0f / (float)cx;
-    for (int e = threadIdx.x; e < cx * zl; e += TPB) {
-        const int c = fdiv(e, zl, invz);
-        const int l2 = half + e - c * zl;
-        re[c * Np + lds_pad(l2)] = 0;
-        im[c * Np + lds_pad(l2)] = 0;
-    }
-    for (int e = threadIdx.x; e < cx * n1a; e += TPB) {
-        const int l = fdiv(e, cx, invcx), c = e - l * cx;
-        int idx = l - half;
-        if (idx < 0) idx += N;
-        const cplx<R> v = in[(long long)l * F + c];
-        re[c * Np + lds_pad(idx)] = v.x;
-        im[c * Np + lds_pad(idx)] = v.y;
-    }
-    __syncthreads();
-    fft_lds<R, TPB, true>(re, im, N, Np, cx, twc, twf);
-    for (int e = threadIdx.x; e < cx * Ma; e += TPB) {
-        const int po = fdiv(e, cx, invcx), c = e - po * cx;
-        int idx = po - Pa;
-        idx += idx < 0 ? N : 0;
-        idx -= idx >= N ? N : 0;
-        const int q = c * Np + lds_pad(idx);
-        out[(long long)po * F + c] = cmake<R>(re[q], im[q]);
     }
 }
 
@@ -624,7 +733,7 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, const cplx
     for (int iz = 0; iz < (D == 3 ? W : 1); ++iz) {
         R zr = 0, zi = 0;
         const long long zoff = D == 3 ? (long long)(p0[2] + iz) * My * Mx : 0;
-#pragma unroll
+#pragma unroll 2
         for (int iy = 0; iy < W; ++iy) {
             const cplx<R> *row = g + zoff + (long long)(p0[1] + iy) * Mx + p0[0];
             R rr = 0, ri = 0;
@@ -739,10 +848,21 @@ inline int fft_max_lines() {
     return v;
 }
 
-inline int fft_tpb_for(int N) {
-    if (N <= kFftSlots * 256) return 256;
-    if (N <= kFftSlots * 512) return 512;
-    return 1024;
+// Threads of an FFT workgroup: single-line passes by line length,
+// multi-line passes 512.
+inline int env_int(const char *name, int dflt) {
+    const char *e = std::getenv(name);
+    return e ? std::atoi(e) : dflt;
+}
+
+// Tunables (environment, read once): FV_FFT_TPB1 threads of single-line
+// passes (0 = by line length), FV_FFT_TPBM threads of multi-line passes.
+inline int fft_tpb_for(int L, bool multi) {
+    static const int t1 = env_int("FV_FFT_TPB1", 0), tm = env_int("FV_FFT_TPBM", 512);
+    int t = multi ? tm : t1;
+    if (t != 128 && t != 256 && t != 512 && t != 1024) t = 0;
+    if (t == 0) t = L <= 2048 ? 256 : (L <= 4096 ? 512 : 1024);
+    return t;
 }
 
 inline size_t rec_bytes(int dim, int prec_bits) {
@@ -755,12 +875,15 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
     const size_t csz = prec_bits == 32 ? 8 : 16;
     const int T[3] = {dim == 2 ? TileShape<2>::X : TileShape<3>::X, dim == 2 ? TileShape<2>::Y : TileShape<3>::Y,
                       dim == 2 ? 1 : TileShape<3>::Z};
-    // FFT threads per pass from the largest line length
+    // FFT threads per pass from the largest line length (n1 points per line)
     for (int a = 0; a < dim; ++a) {
-        int nmax = 0;
-        for (auto &j : jobs) nmax = std::max(nmax, j.plan.n2[a]);
-        L.tpb[a] = fft_tpb_for(nmax);
-        if ((long long)nmax > (long long)kFftSlots * 1024 || (size_t)fft_line_pad(nmax) * csz > 160u * 1024)
+        int lmax = 0, nmax = 0;
+        for (auto &j : jobs) {
+            lmax = std::max(lmax, j.plan.n1[a]);
+            nmax = std::max(nmax, j.plan.n2[a]);
+        }
+        L.tpb[a] = fft_tpb_for(lmax, a > 0);
+        if ((size_t)(2 * cline_pad(lmax) + fft_tw_entries(nmax)) * csz > 160u * 1024)
             fail(FV_EUNSUPPORTED, "FFT line of " + std::to_string(nmax) + " points exceeds the LDS transform");
     }
     for (auto &j : jobs) {
@@ -817,14 +940,14 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
             for (int b = a + 1; b < dim; ++b) Sl *= p.n1[b];
             int cx = 1;
             if (F > 1) {
-                const long long byreg = (long long)kFftSlots * L.tpb[a] / p.n2[a];
-                const long long bylds = 65536LL / ((long long)fft_line_pad(p.n2[a]) * csz);
-                cx = (int)std::max(1LL, std::min({F, byreg, bylds, (long long)fft_max_lines()}));
+                const long long bylds = (65536LL - (long long)fft_tw_entries(p.n2[a]) * csz) /
+                                        (2LL * cline_pad(p.n1[a]) * csz);
+                cx = (int)std::max(1LL, std::min({F, bylds, (long long)fft_max_lines()}));
             }
             d.cx[a] = cx;
             d.wg_base[a] = L.wg_total[a];
             L.wg_total[a] += Sl * ((F + cx - 1) / cx);
-            L.fft_lds[a] = std::max(L.fft_lds[a], (size_t)cx * fft_line_pad(p.n2[a]) * csz +
+            L.fft_lds[a] = std::max(L.fft_lds[a], 2 * (size_t)cx * cline_pad(p.n1[a]) * csz +
                                                       (size_t)fft_tw_entries(p.n2[a]) * csz);
             L.max_wg[a] = std::max(L.max_wg[a], Sl * ((F + cx - 1) / cx));
         }
@@ -929,12 +1052,20 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
     tm->end(st);
     tm->add(FV_STAGE_SORT, L.sbytes[FV_STAGE_SORT], 4);
     {
-        using Cfg = SpreadCfg<R, D, W>;
         tm->begin(FV_STAGE_SPREAD, st);
-        const size_t lds = spread_lds<R, D, W>();
-        ensure_lds((const void *)k_spread<R, D, W>, lds);
-        hipLaunchKernelGGL((k_spread<R, D, W>), dim3((unsigned)L.max_tiles, n_snap), dim3(64 * Cfg::WPB), lds, st,
-                           snaps_dev, (const int *)bins, (const Rec<R, D> *)recs, (const R *)ipsi, grid);
+        if constexpr (D == 2) {
+            using MC = SpreadMfmaCfg<R, W>;
+            const size_t lds = (size_t)MC::WPB * MC::WAVE_BYTES;
+            ensure_lds((const void *)k_spread_mfma<R, W>, lds);
+            hipLaunchKernelGGL((k_spread_mfma<R, W>), dim3((unsigned)L.max_tiles, n_snap), dim3(64 * MC::WPB), lds,
+                               st, snaps_dev, (const int *)bins, (const Rec<R, 2> *)recs, (const R *)ipsi, grid);
+        } else {
+            using Cfg = SpreadCfg<R, D, W>;
+            const size_t lds = spread_lds<R, D, W>();
+            ensure_lds((const void *)k_spread<R, D, W>, lds);
+            hipLaunchKernelGGL((k_spread<R, D, W>), dim3((unsigned)L.max_tiles, n_snap), dim3(64 * Cfg::WPB), lds, st,
+                               snaps_dev, (const int *)bins, (const Rec<R, D> *)recs, (const R *)ipsi, grid);
+        }
         tm->end(st);
         tm->add(FV_STAGE_SPREAD, L.sbytes[FV_STAGE_SPREAD], 1);
     }
@@ -944,18 +1075,21 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
         const dim3 nb((unsigned)L.max_wg[a], (unsigned)n_snap);
         tm->begin(FV_STAGE_FFT_X + a, st);
         switch (L.tpb[a]) {
+            case 128:
+                ensure_lds((const void *)k_fft<R, 128>, L.fft_lds[a]);
+                hipLaunchKernelGGL((k_fft<R, 128>), nb, dim3(128), L.fft_lds[a], st, snaps_dev, a, grid);
+                break;
             case 256:
                 ensure_lds((const void *)k_fft<R, 256>, L.fft_lds[a]);
-                hipLaunchKernelGGL((k_fft<R, 256>), dim3(nb), dim3(256), L.fft_lds[a], st, snaps_dev, n_snap, a, grid);
+                hipLaunchKernelGGL((k_fft<R, 256>), nb, dim3(256), L.fft_lds[a], st, snaps_dev, a, grid);
                 break;
             case 512:
                 ensure_lds((const void *)k_fft<R, 512>, L.fft_lds[a]);
-                hipLaunchKernelGGL((k_fft<R, 512>), dim3(nb), dim3(512), L.fft_lds[a], st, snaps_dev, n_snap, a, grid);
+                hipLaunchKernelGGL((k_fft<R, 512>), nb, dim3(512), L.fft_lds[a], st, snaps_dev, a, grid);
                 break;
             default:
                 ensure_lds((const void *)k_fft<R, 1024>, L.fft_lds[a]);
-                hipLaunchKernelGGL((k_fft<R, 1024>), dim3(nb), dim3(1024), L.fft_lds[a], st, snaps_dev, n_snap, a,
-                                   grid);
+                hipLaunchKernelGGL((k_fft<R, 1024>), nb, dim3(1024), L.fft_lds[a], st, snaps_dev, a, grid);
                 break;
         }
         tm->end(st);
