@@ -66,6 +66,32 @@ __device__ __forceinline__ double phihat_quad(double xi, const double *qn) {
     return acc;
 }
 
+// One 16x16x4 matrix-core step D += A B on a wavefront: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+    typedef mfma_f4 T;
+    static __device__ __forceinline__ T step(float a, float b, T c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // accumulator register r of lane l holds row 4 (l / 16) + r, column l % 16
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct MfmaAcc<double> {
+    typedef mfma_d4 T;
+    static __device__ __forceinline__ T step(double a, double b, T c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // accumulator register r of lane l holds row (l / 16) + 4 r, column l % 16
+    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

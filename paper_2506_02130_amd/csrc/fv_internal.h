@@ -197,9 +197,11 @@ void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
 void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
                    int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits,
                    double *vis_dev, hipStream_t s, StageTimer *timer = nullptr);
-size_t zz_work_bytes(int n_ant, int n_src);
+// Matrix-core direct sum V = Z diag(c) Z^H.  The workspace holds Z for a chunk
+// of sources sized so that the total stays within `cap` bytes.
+size_t zz_work_bytes(int n_ant, int n_src, int prec_bits, size_t cap);
 void launch_zz(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
-               int n_freq, const double *flux_dev, const double *beam_dev, int dim, double *vis_dev, void *work,
-               hipStream_t s, StageTimer *timer = nullptr);
+               int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits, double *vis_dev,
+               void *work, size_t cap, hipStream_t s, StageTimer *timer = nullptr);
 
 }  // namespace fv

@@ -367,30 +367,6 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, const int 
 // by v_mfma_{f32,f64}_16x16x4 (A = y weights of 4 records, B = strength-scaled
 // x weights, real and imaginary parts in two accumulators).  Each lane builds
 // one A and one B element per step from the records staged in LDS.
-typedef float mfma_f4 __attribute__((ext_vector_type(4)));
-typedef double mfma_d4 __attribute__((ext_vector_type(4)));
-
-template <typename R>
-struct MfmaAcc;
-template <>
-struct MfmaAcc<float> {
-    typedef mfma_f4 T;
-    static __device__ __forceinline__ T step(float a, float b, T c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // accumulator register r of lane l holds row 4 (l / 16) + r, column l % 16
-    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
-};
-template <>
-struct MfmaAcc<double> {
-    typedef mfma_d4 T;
-    static __device__ __forceinline__ T step(double a, double b, T c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // accumulator register r of lane l holds row (l / 16) + 4 r, column l % 16
-    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
-};
-
 template <typename R, int W>
 struct SpreadMfmaCfg {
     static constexpr int T = 16;            // tile edge

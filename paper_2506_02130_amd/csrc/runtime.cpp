@@ -271,10 +271,13 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
         launch_direct(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, prec, vis_dev, st,
                       &tm);
     } else if (method == FV_METHOD_MFMA) {
-        slot.arena.ensure(zz_work_bytes(n_ant, n_src));
+        const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
+        const size_t need = zz_work_bytes(n_ant, n_src, prec, cap);
+        slot.arena.ensure(need);
         slot.arena.reset();
-        void *work = slot.arena.take(zz_work_bytes(n_ant, n_src));
-        launch_zz(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, vis_dev, work, st, &tm);
+        void *work = slot.arena.take(need);
+        launch_zz(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, prec, vis_dev, work, cap, st,
+                  &tm);
     } else {
         const bool fold = !(p->flags & FV_NO_FOLD);
         GeomPlan g = ctx_geometry(ctx, p->ant_enu, n_ant, dim, p->eps, in.s_c, in.S, fold);
@@ -417,7 +420,7 @@ fv_status fv_create(int device, size_t hbm_budget_bytes, fv_ctx **out) {
     c->device = device;
     size_t fr = fv::device_free_bytes();
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * fr);
-    c->chunk_bytes = std::max<size_t>(c->budget / 4, 256u << 20);
+    c->chunk_bytes = std::max<size_t>(c->budget / 4, std::min<size_t>(c->budget, 256u << 20));
     hipError_t e = hipStreamCreateWithFlags(&c->main.stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;

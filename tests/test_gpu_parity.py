@@ -114,6 +114,43 @@ def test_direct_kernel(gpu_lib, ctx, eps, tol):
     assert oracle.rel_l2(v, oracle.direct_problem(p)) <= tol
 
 
+# ---------------------------------------------------------------- matrix-core direct sum
+@pytest.mark.parametrize("three_d,eps,tol", [(False, 1e-6, 1e-6), (True, 1e-6, 1e-6), (False, 1e-10, 1e-12),
+                                             (True, 1e-12, 1e-12)])
+def test_zz_matrix_core_direct(gpu_lib, ctx, three_d, eps, tol):
+    # 45 antennas: two 32-antenna tiles, the second ragged; 1501 sources: a
+    # ragged last step of 4
+    p = synth.small_problem(50, n_ant=45, n_src=1501, n_freq=2, three_d=three_d, radius=150.0)
+    v, rep = _run(gpu_lib, ctx, p, eps=eps, flags=gpu_lib.METHOD_MFMA)
+    assert rep["method"] == gpu_lib.METHOD_MFMA and rep["dim"] == (3 if three_d else 2)
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= tol
+
+
+def test_zz_source_chunks_and_splits(gpu_lib):
+    # a 2 MiB budget forces several source chunks per frequency (outputs added
+    # chunk after chunk) and few splits
+    p = synth.small_problem(51, n_ant=70, n_src=9000, n_freq=2, radius=150.0)
+    with gpu_lib.Context(0, hbm_budget_bytes=2 << 20) as c:
+        v, rep = _run(gpu_lib, c, p, eps=1e-6, flags=gpu_lib.METHOD_MFMA)
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= 1e-6
+
+
+def test_zz_single_antenna_and_single_source(gpu_lib, ctx):
+    p = synth.small_problem(52, n_ant=1, n_src=1, n_freq=1)
+    v, _ = _run(gpu_lib, ctx, p, eps=1e-10, flags=gpu_lib.METHOD_MFMA)
+    assert np.allclose(v[:, 0], p.strengths().sum(1), rtol=1e-12)
+    p = synth.small_problem(53, n_ant=33, n_src=3, n_freq=1)
+    v, _ = _run(gpu_lib, ctx, p, eps=1e-10, flags=gpu_lib.METHOD_MFMA)
+    assert oracle.rel_l2(v, oracle.direct_problem(p)) <= 1e-12
+
+
+def test_zz_agrees_with_vector_direct(gpu_lib, ctx):
+    p = synth.small_problem(54, n_ant=64, n_src=4000, n_freq=1, hex_layout=True)
+    v1, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=gpu_lib.METHOD_DIRECT)
+    v2, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=gpu_lib.METHOD_MFMA)
+    assert oracle.rel_l2(v2, v1) <= 2e-6
+
+
 # ---------------------------------------------------------------- edges
 def test_empty_sky_gives_exact_zero(gpu_lib, ctx):
     p = synth.small_problem(39, n_ant=6, n_src=0, n_freq=2)
