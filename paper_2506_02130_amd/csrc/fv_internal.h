@@ -61,6 +61,7 @@ struct SnapDev {
     const double *tphi;              // phihat at each target, [dim][n_tgt]
     const double *qn;                // quadrature table of this w
     const void *tw[3];               // twiddle table of n2[a]
+    const int *drev[3];              // output position of each bin of an n1[a]-point transform
     double gscale[3];                // grid cells per unit of s: sigma X / pi
     double s_c[3];
     double qscale[3];                // target grid coordinate q = qscale (b - b_c)
@@ -122,7 +123,9 @@ struct Arena {
 struct DevCache {
     std::map<std::pair<int, int>, void *> twiddles;
     std::map<int, double *> qnodes;
+    std::map<int, int *> drevs;
     const void *twiddle(int n, int prec_bits, hipStream_t s);
+    const int *digit_reversal(int n, hipStream_t s);
     const double *quad(int w, hipStream_t s);
     void release();
 };

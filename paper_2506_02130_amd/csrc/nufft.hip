@@ -39,7 +39,10 @@ Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w
     for (size_t i = 0; i < jobs.size(); ++i) {
         SnapDev &d = L.snaps[i];
         d.qn = qn;
-        for (int a = 0; a < dim; ++a) d.tw[a] = cache.twiddle(d.n2[a], prec_bits, st);
+        for (int a = 0; a < dim; ++a) {
+            d.tw[a] = cache.twiddle(d.n2[a], prec_bits, st);
+            d.drev[a] = cache.digit_reversal(d.n1[a], st);
+        }
     }
     const int n = (int)jobs.size();
     const size_t need = layout_bytes(L, dim, prec_bits, n);
@@ -120,6 +123,17 @@ const void *DevCache::twiddle(int n, int prec_bits, hipStream_t st) {
     return p;
 }
 
+const int *DevCache::digit_reversal(int n, hipStream_t st) {
+    auto it = drevs.find(n);
+    if (it != drevs.end()) return it->second;
+    int *p = nullptr;
+    FV_HIP(hipMalloc(&p, (size_t)n * sizeof(int)));
+    hipLaunchKernelGGL(k_digrev, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p);
+    FV_HIP(hipGetLastError());
+    drevs[n] = p;
+    return p;
+}
+
 const double *DevCache::quad(int w, hipStream_t st) {
     auto it = qnodes.find(w);
     if (it != qnodes.end()) return it->second;
@@ -135,6 +149,8 @@ const double *DevCache::quad(int w, hipStream_t st) {
 
 void DevCache::release() {
     for (auto &kv : twiddles) (void)hipFree(kv.second);
+    for (auto &kv : drevs) (void)hipFree(kv.second);
+    drevs.clear();
     for (auto &kv : qnodes) (void)hipFree(kv.second);
     twiddles.clear();
     qnodes.clear();

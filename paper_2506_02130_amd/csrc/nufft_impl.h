@@ -473,14 +473,14 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, const
 }
 
 // ---------------------------------------------------------------------------
-// FFT: mixed-radix Stockham (autosort) in LDS, + sign.  Butterfly b of a
-// radix-r stage with p = product of earlier radices reads x[i + j N/r],
-// multiplies input j by W_N^(j k N/(p r)) (k = i mod p), takes the r-point
-// DFT and writes outputs q at (i - k) r + k + q p.  The line lives in LDS as
-// separate real and imaginary planes with one pad word every 32 (strided
-// writes of the early stages then spread over the banks).
-__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 5); }
-
+// FFT: mixed-radix decimation in frequency, in place in LDS, + sign.  A
+// radix-r stage on sub-transforms of Ls points (q = Ls / r) takes, for each
+// sub-transform start s0 and k < q, the r points s0 + k + j q, forms their
+// r-point DFT and multiplies output j' by W_Ls^(j' k) before storing it back
+// at s0 + k + j' q.  The input is in natural order; after the last stage
+// X[q] sits at drev[q], with
+//     drev(q) = (q mod r1) L / r1 + drev'(q div r1)
+// over the radices r1, r2, ... in stage order (8s, 4s, 2s, 3s, 5s).
 // a / b for 0 <= a < 2^23 with a float reciprocal and one correction step.
 __device__ __forceinline__ int fdiv(int a, int b, float inv_b) {
     int q = (int)((float)a * inv_b);
@@ -561,65 +561,96 @@ __device__ __forceinline__ cplx<R> twiddle(const cplx<R> *coarse, const cplx<R> 
 __device__ __forceinline__ int cpad(int e) { return e + (e >> 4); }
 __host__ __device__ inline int cline_pad(int L) { return L + (L >> 4) + 1; }
 
-// One radix-RAD Stockham stage over cx lines of L points, out of place
-// (src -> dst, interleaved complex in LDS padded by cpad).  Twiddle exponents
-// are in units of W_L = W_N^tmul.  Each thread walks its butterflies one at a
-// time, so only one butterfly is live in registers.
-template <typename R, int TPB, int RAD, bool MULTI>
-__device__ __forceinline__ void fft_stage(const cplx<R> *src, cplx<R> *dst, int L, int Lp, int cx, int p, int tmul,
-                                          const cplx<R> *twc, const cplx<R> *twf) {
-    const int T = L / RAD;
-    const int nb = MULTI ? cx * T : T;
-    const int tws = (L / (p * RAD)) * tmul;
-    const float invT = 1.0f / (float)T, invp = 1.0f / (float)p;
+// One radix-RAD stage over the m lines of the workgroup.  Work item wi maps
+// to butterfly b = wi mod L/RAD of line group g = wi div L/RAD; its indices
+// and twiddles are formed once and applied to lines g, g + G, g + 2G, ...
+template <typename R, int TPB, int RAD>
+__device__ __forceinline__ void dif_stage(cplx<R> *buf, int L, int Lp, int m, int Ls, int p, const cplx<R> *twc,
+                                          const cplx<R> *twf) {
+    const int q = Ls / RAD;
+    const int nb = L / RAD;
+    const int G = max(1, min(m, TPB / nb));
+    const float invnb = 1.0f / (float)nb, invq = 1.0f / (float)q;
 #pragma unroll 1
-    for (int b = threadIdx.x; b < nb; b += TPB) {
-        const int c = MULTI ? fdiv(b, T, invT) : 0;
-        const int i = b - c * T;
-        const int k = p == 1 ? 0 : i - fdiv(i, p, invp) * p;
-        const cplx<R> *s_ = src + c * Lp;
-        cplx<R> v[RAD];
+    for (int wi = threadIdx.x; wi < nb * G; wi += TPB) {
+        const int g = G == 1 ? 0 : fdiv(wi, nb, invnb);
+        const int b = wi - g * nb;
+        const int blk = q == 1 ? b : fdiv(b, q, invq);
+        const int k = b - blk * q;
+        const int base = blk * Ls + k;
+        int addr[RAD];
 #pragma unroll
-        for (int j = 0; j < RAD; ++j) v[j] = s_[cpad(i + j * T)];
-        if (k) {
+        for (int j = 0; j < RAD; ++j) addr[j] = cpad(base + j * q);
+        cplx<R> tw[RAD];
 #pragma unroll
-            for (int j = 1; j < RAD; ++j) v[j] = cmul<R>(v[j], twiddle<R>(twc, twf, j * k * tws));
+        for (int j = 1; j < RAD; ++j) tw[j] = twiddle<R>(twc, twf, 2 * j * k * p);  // W_N^(2 j k p) = W_Ls^(j k)
+#pragma unroll 1
+        for (int line = g; line < m; line += G) {
+            cplx<R> *s_ = buf + line * Lp;
+            cplx<R> v[RAD];
+#pragma unroll
+            for (int j = 0; j < RAD; ++j) v[j] = s_[addr[j]];
+            dft_small<R, RAD>(v);
+#pragma unroll
+            for (int j = 1; j < RAD; ++j) v[j] = cmul<R>(v[j], tw[j]);
+#pragma unroll
+            for (int j = 0; j < RAD; ++j) s_[addr[j]] = v[j];
         }
-        dft_small<R, RAD>(v);
-        cplx<R> *d_ = dst + c * Lp;
-        const int o0 = (i - k) * RAD + k;
-#pragma unroll
-        for (int q = 0; q < RAD; ++q) d_[cpad(o0 + q * p)] = v[q];
     }
     __syncthreads();
 }
 
-// Mixed-radix FFT of cx lines; the input is in `a`, `b` is scratch of the same
-// size; returns the buffer holding the result.
-template <typename R, int TPB, bool MULTI>
-__device__ cplx<R> *fft_lds(cplx<R> *a, cplx<R> *b, int L, int Lp, int cx, int tmul, const cplx<R> *twc,
-                            const cplx<R> *twf) {
-    int p = 1, rem = L;
-    while (rem % 8 == 0) { fft_stage<R, TPB, 8, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 8; rem /= 8; }
-    while (rem % 4 == 0) { fft_stage<R, TPB, 4, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 4; rem /= 4; }
-    while (rem % 2 == 0) { fft_stage<R, TPB, 2, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 2; rem /= 2; }
-    while (rem % 3 == 0) { fft_stage<R, TPB, 3, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 3; rem /= 3; }
-    while (rem % 5 == 0) { fft_stage<R, TPB, 5, MULTI>(a, b, L, Lp, cx, p, tmul, twc, twf); cplx<R> *t = a; a = b; b = t; p *= 5; rem /= 5; }
-    return a;
+template <typename R, int TPB>
+__device__ void dif_fft(cplx<R> *buf, int L, int Lp, int m, const cplx<R> *twc, const cplx<R> *twf) {
+    int Ls = L, p = 1;
+    while (Ls % 8 == 0) { dif_stage<R, TPB, 8>(buf, L, Lp, m, Ls, p, twc, twf); Ls /= 8; p *= 8; }
+    while (Ls % 4 == 0) { dif_stage<R, TPB, 4>(buf, L, Lp, m, Ls, p, twc, twf); Ls /= 4; p *= 4; }
+    while (Ls % 2 == 0) { dif_stage<R, TPB, 2>(buf, L, Lp, m, Ls, p, twc, twf); Ls /= 2; p *= 2; }
+    while (Ls % 3 == 0) { dif_stage<R, TPB, 3>(buf, L, Lp, m, Ls, p, twc, twf); Ls /= 3; p *= 3; }
+    while (Ls % 5 == 0) { dif_stage<R, TPB, 5>(buf, L, Lp, m, Ls, p, twc, twf); Ls /= 5; p *= 5; }
+}
+
+// Output position of X[q] of an L-point transform (same radix order as dif_fft).
+__global__ void k_digrev(int L, int *drev) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= L) return;
+    int pos = 0, Ls = L, rem = q;
+    const int radices[5] = {8, 4, 2, 3, 5};
+    for (int ri = 0; ri < 5; ++ri) {
+        const int r = radices[ri];
+        while (Ls % r == 0) {
+            Ls /= r;
+            pos += (rem % r) * Ls;
+            rem /= r;
+        }
+    }
+    drev[q] = pos;
 }
 
 // Entries of the two twiddle tables of an N-point line.
 __host__ __device__ inline int fft_tw_entries(int N) { return (N >> 6) + 1 + 64; }
+
+// Physical workgroup b runs on XCD b mod 8 (round-robin dispatch); logical
+// workgroups are handed out so that each XCD gets one contiguous range, and
+// neighbouring line groups, which share cache lines, share an L2.  nblk is a
+// multiple of 8.
+__device__ __forceinline__ long long xcd_order(long long b, long long nblk) {
+    return (b & 7) * (nblk >> 3) + (b >> 3);
+}
 
 // One pass along axis `a` for every snapshot.  A line holds the n1 deconvolved
 // mode values b~_m, m in [-n1/2, n1/2); the pass evaluates
 // g_p = sum_m b~_m W_N^(m p), N = n2 = 2 n1, at p in [-P, P] only.  With
 // a[j] = b~_m at j = m mod n1, the even outputs are g_2k = sum_j a[j] W_n1^(jk)
 // and the odd outputs g_2k+1 = sum_j s_j a[j] W_N^j W_n1^(jk), s_j = +1 for
-// j < n1/2 and -1 otherwise (W_N^n1 = -1): two n1-point FFTs per line, with
-// no zero padding held in LDS.
+// j < n1/2 and -1 otherwise (W_N^n1 = -1): each line becomes two n1-point
+// transforms held side by side in LDS (2 cx transforms per workgroup, one
+// index and twiddle computation per butterfly for all of them), with no zero
+// padding stored.  Outputs of both parities are written interleaved, in order.
 // Input layout [slow: n1 of axes > a][n1_a][fast: M of axes < a]; output
-// [slow][M_a][fast].  Passes alternate bufA -> bufB -> bufA (-> bufB).
+// [slow][M_a][fast].  When the fast extent is 1 (the x pass) a workgroup takes
+// cx consecutive rows, else cx consecutive columns of one slow index.
+// Passes alternate bufA -> bufB -> bufA (-> bufB).
 template <typename R, int TPB>
 __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R> *grid) {
     extern __shared__ __align__(16) char smem[];
@@ -629,52 +660,82 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
     long long F = 1, Sl = 1;
     for (int b = 0; b < a; ++b) F *= S.M[b];
     for (int b = a + 1; b < S.dim; ++b) Sl *= S.n1[b];
-    const long long ngrp = (F + CX - 1) / CX;
-    const long long wl = (long long)blockIdx.x;
-    if (wl >= Sl * ngrp) return;
-    const long long o = wl / ngrp;
-    const long long i0 = (wl - o * ngrp) * CX;
-    const int cx = (int)min((long long)CX, F - i0);
+    const bool rows = F == 1;
+    const long long ngrp = rows ? (Sl + CX - 1) / CX : (F + CX - 1) / CX;
+    const long long nblk = rows ? ngrp : Sl * ngrp;
+    const long long wl = xcd_order((long long)blockIdx.x, (long long)gridDim.x);
+    if (wl >= nblk) return;
+    const bool fromA = (a % 2) == 0;
+    const cplx<R> *in = grid + (fromA ? S.bufA : S.bufB);
+    cplx<R> *out = grid + (fromA ? S.bufB : S.bufA);
+    int cx;
+    long long in_ls, out_ls;  // line strides; element strides are 1 (rows) or F (columns)
+    if (rows) {
+        const long long o0 = wl * CX;
+        cx = (int)min((long long)CX, Sl - o0);
+        in += o0 * L;
+        out += o0 * Ma;
+        in_ls = L;
+        out_ls = Ma;
+    } else {
+        const long long o = wl / ngrp, i0 = (wl - o * ngrp) * CX;
+        cx = (int)min((long long)CX, F - i0);
+        in += o * ((long long)L * F) + i0;
+        out += o * ((long long)Ma * F) + i0;
+        in_ls = 1;
+        out_ls = 1;
+    }
     cplx<R> *twc = (cplx<R> *)smem;  // [N/64 + 1] coarse, then [64] fine twiddles of W_N
     cplx<R> *twf = twc + (N >> 6) + 1;
-    cplx<R> *buf = twf + 64;              // [cx][Lp]
-    cplx<R> *buf2 = buf + (size_t)cx * Lp;  // ping-pong partner
-    const bool fromA = (a % 2) == 0;
-    const cplx<R> *in = grid + (fromA ? S.bufA : S.bufB) + o * ((long long)L * F) + i0;
-    cplx<R> *out = grid + (fromA ? S.bufB : S.bufA) + o * ((long long)Ma * F) + i0;
+    cplx<R> *buf = twf + 64;              // [2 cx][Lp]: line 2c even, 2c + 1 odd outputs
     const cplx<R> *tw = (const cplx<R> *)S.tw[a];
     for (int t = threadIdx.x; t < (N >> 6) + 1 + 64; t += TPB) {
         const int g = t <= (N >> 6) ? t << 6 : t - (N >> 6) - 1;
         twc[t] = tw[g < N ? g : 0];
     }
-    const float invcx = 1.0f / (float)cx;
-    for (int parity = 0; parity < 2; ++parity) {
-        if (parity) __syncthreads();  // the even outputs have been read out of buf
-        for (int e = threadIdx.x; e < cx * L; e += TPB) {
-            const int l = fdiv(e, cx, invcx), c = e - l * cx;
-            int j = l + half;
-            if (j >= L) j -= L;
-            cplx<R> v = in[(long long)l * F + c];
-            if (parity) {
-                v = cmul<R>(v, twiddle<R>(twc, twf, j));
-                if (j >= half) v = cmake<R>(-v.x, -v.y);
-            }
-            buf[c * Lp + cpad(j)] = v;
+    __syncthreads();
+    const float invL = 1.0f / (float)L, invcx = 1.0f / (float)cx;
+    for (int e = threadIdx.x; e < cx * L; e += TPB) {
+        int l, c;
+        long long src;
+        if (rows) {
+            c = fdiv(e, L, invL);
+            l = e - c * L;
+            src = c * in_ls + l;
+        } else {
+            l = fdiv(e, cx, invcx);
+            c = e - l * cx;
+            src = (long long)l * F + c;
         }
-        __syncthreads();
-        const cplx<R> *res = cx == 1 ? fft_lds<R, TPB, false>(buf, buf2, L, Lp, 1, 2, twc, twf)
-                                     : fft_lds<R, TPB, true>(buf, buf2, L, Lp, cx, 2, twc, twf);
-        // outputs p in [-P, P] of this parity: p = p0 + 2 q
-        const int p0 = ((-Pa) & 1) == parity ? -Pa : -Pa + 1;
-        const int cnt = (Pa - p0) / 2 + 1;
-        for (int e = threadIdx.x; e < cx * cnt; e += TPB) {
-            const int q = fdiv(e, cx, invcx), c = e - q * cx;
-            const int pp = p0 + 2 * q;
-            int k = (pp - parity) / 2;
-            k %= L;
-            if (k < 0) k += L;
-            out[(long long)(pp + Pa) * F + c] = res[c * Lp + cpad(k)];
+        int j = l + half;
+        if (j >= L) j -= L;
+        const cplx<R> v = in[src];
+        cplx<R> vo = cmul<R>(v, twiddle<R>(twc, twf, j));
+        if (j >= half) vo = cmake<R>(-vo.x, -vo.y);
+        buf[(2 * c) * Lp + cpad(j)] = v;
+        buf[(2 * c + 1) * Lp + cpad(j)] = vo;
+    }
+    __syncthreads();
+    dif_fft<R, TPB>(buf, L, Lp, 2 * cx, twc, twf);
+    const int *drev = S.drev[a];
+    const float invM = 1.0f / (float)Ma;
+    for (int e = threadIdx.x; e < cx * Ma; e += TPB) {
+        int pi, c;
+        long long dst;
+        if (rows) {
+            c = fdiv(e, Ma, invM);
+            pi = e - c * Ma;
+            dst = c * out_ls + pi;
+        } else {
+            pi = fdiv(e, cx, invcx);
+            c = e - pi * cx;
+            dst = (long long)pi * F + c;
         }
+        const int pp = pi - Pa, par = pp & 1;
+        int k = (pp - par) >> 1;
+        if (k < 0) k += L;
+        if (k >= L) k -= L;
+        out[dst] = buf[(2 * c + par) * Lp + cpad(drev[k])];
     }
 }
 
@@ -818,14 +879,23 @@ struct Layout {
 inline int fft_max_lines() {
     static int v = [] {
         const char *e = std::getenv("FV_FFT_MAX_LINES");
-        int x = e ? std::atoi(e) : 16;
+        int x = e ? std::atoi(e) : 2;
         return x < 1 ? 1 : (x > 64 ? 64 : x);
     }();
     return v;
 }
 
+inline int fft_max_rows() {
+    static int v = [] {
+        const char *e = std::getenv("FV_FFT_ROWS");
+        int x = e ? std::atoi(e) : 1;
+        return x < 1 ? 1 : (x > 16 ? 16 : x);
+    }();
+    return v;
+}
+
 // Threads of an FFT workgroup: single-line passes by line length,
-// multi-line passes 512.
+// multi-line passes 256 (measured on the 350-antenna workload).
 inline int env_int(const char *name, int dflt) {
     const char *e = std::getenv(name);
     return e ? std::atoi(e) : dflt;
@@ -834,7 +904,7 @@ inline int env_int(const char *name, int dflt) {
 // Tunables (environment, read once): FV_FFT_TPB1 threads of single-line
 // passes (0 = by line length), FV_FFT_TPBM threads of multi-line passes.
 inline int fft_tpb_for(int L, bool multi) {
-    static const int t1 = env_int("FV_FFT_TPB1", 0), tm = env_int("FV_FFT_TPBM", 512);
+    static const int t1 = env_int("FV_FFT_TPB1", 0), tm = env_int("FV_FFT_TPBM", 256);
     int t = multi ? tm : t1;
     if (t != 128 && t != 256 && t != 512 && t != 1024) t = 0;
     if (t == 0) t = L <= 2048 ? 256 : (L <= 4096 ? 512 : 1024);
@@ -914,18 +984,19 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
             long long F = 1, Sl = 1;
             for (int b = 0; b < a; ++b) F *= p.M[b];
             for (int b = a + 1; b < dim; ++b) Sl *= p.n1[b];
-            int cx = 1;
-            if (F > 1) {
-                const long long bylds = (65536LL - (long long)fft_tw_entries(p.n2[a]) * csz) /
-                                        (2LL * cline_pad(p.n1[a]) * csz);
-                cx = (int)std::max(1LL, std::min({F, bylds, (long long)fft_max_lines()}));
-            }
+            // lines per workgroup: columns (fast extent F > 1) or rows (F == 1),
+            // each line held as two transforms within 64 KB of LDS
+            const long long bylds = (65536LL - (long long)fft_tw_entries(p.n2[a]) * csz) /
+                                    (2LL * cline_pad(p.n1[a]) * csz);
+            const long long lim = F > 1 ? (long long)fft_max_lines() : (long long)fft_max_rows();
+            const int cx = (int)std::max(1LL, std::min({F > 1 ? F : Sl, bylds, lim}));
+            const long long nwg = F > 1 ? Sl * ((F + cx - 1) / cx) : (Sl + cx - 1) / cx;
             d.cx[a] = cx;
             d.wg_base[a] = L.wg_total[a];
-            L.wg_total[a] += Sl * ((F + cx - 1) / cx);
+            L.wg_total[a] += nwg;
             L.fft_lds[a] = std::max(L.fft_lds[a], 2 * (size_t)cx * cline_pad(p.n1[a]) * csz +
                                                       (size_t)fft_tw_entries(p.n2[a]) * csz);
-            L.max_wg[a] = std::max(L.max_wg[a], Sl * ((F + cx - 1) / cx));
+            L.max_wg[a] = std::max(L.max_wg[a], nwg);
         }
         d.src = j.src;
         d.flux = j.flux;
@@ -1048,7 +1119,8 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
     }
     if (stages & 2)
     for (int a = 0; a < D; ++a) {
-        const dim3 nb((unsigned)L.max_wg[a], (unsigned)n_snap);
+        // a multiple of 8 workgroups along x, so that the XCD of (x, y) is x mod 8
+        const dim3 nb((unsigned)((L.max_wg[a] + 7) / 8 * 8), (unsigned)n_snap);
         tm->begin(FV_STAGE_FFT_X + a, st);
         switch (L.tpb[a]) {
             case 128:
