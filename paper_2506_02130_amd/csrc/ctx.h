@@ -46,6 +46,7 @@ struct fv_ctx {
     std::vector<std::pair<uint64_t, fv::GeomPlan>> geos;
     std::list<std::shared_ptr<fv::TargetTable>> targets;
     double *scalar_buf = nullptr;
+    fv::PinnedBuf plan_pin;  // host staging of the planning scalars of fv_simulate_dev
     fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
     double *scalars(hipStream_t) {
         if (!scalar_buf) FV_HIP(hipMalloc((void **)&scalar_buf, (8 + 7 * fv::kSrcCheckBlocks) * sizeof(double)));

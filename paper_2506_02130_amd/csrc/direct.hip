@@ -99,25 +99,49 @@ __global__ __launch_bounds__(256) void k_src_check(const double *src, int n_src,
     }
 }
 
+// One wavefront folds the per-block partials (lane l takes blocks l, l + 64,
+// ...), then a butterfly reduction across the lanes.
 __global__ __launch_bounds__(64) void k_src_reduce(const double *part, int nblk, double *out) {
-    if (threadIdx.x != 0) return;
+    const int l = threadIdx.x;
     double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = l; b < nblk; b += 64) {
         for (int k = 0; k < 6; k += 2) {
             v[k] = fmin(v[k], part[7 * b + k]);
             v[k + 1] = fmax(v[k + 1], part[7 * b + k + 1]);
         }
         v[6] += part[7 * b + 6];
     }
-    for (int k = 0; k < 7; ++k) out[k] = v[k];
-    int *cnt = (int *)(out + 7);
-    cnt[0] = 0;
-    cnt[1] = 0;
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int k = 0; k < 6; k += 2) {
+            v[k] = fmin(v[k], __shfl_xor(v[k], off, 64));
+            v[k + 1] = fmax(v[k + 1], __shfl_xor(v[k + 1], off, 64));
+        }
+        v[6] += __shfl_xor(v[6], off, 64);
+    }
+    if (l == 0) {
+        for (int k = 0; k < 7; ++k) out[k] = v[k];
+        int *cnt = (int *)(out + 7);
+        cnt[0] = 0;
+        cnt[1] = 0;
+    }
 }
 
+// Count of non-finite values; 16-byte loads when x is 16-byte aligned.
 __global__ void k_count_nonfinite(const double *x, long long n, int *out) {
     int bad = 0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x, nth = (long long)gridDim.x * blockDim.x;
+    long long done = 0;
+    if (((uintptr_t)x & 15) == 0) {
+        const double2 *x2 = (const double2 *)x;
+        const long long n2 = n / 2;
+        for (long long i = tid; i < n2; i += nth) {
+            const double2 v = x2[i];
+            bad += !isfinite(v.x);
+            bad += !isfinite(v.y);
+        }
+        done = 2 * n2;
+    }
+    for (long long i = done + tid; i < n; i += nth)
         if (!isfinite(x[i])) ++bad;
     if (bad) atomicAdd(out, bad);
 }

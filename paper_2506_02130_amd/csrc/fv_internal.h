@@ -109,9 +109,24 @@ void quad_table(int w, double *out64);  // host: the 2*kQuadHalf quadrature tabl
 // ---------------------------------------------------------------------------
 // Device memory: a growable bump arena (one allocation).  Callers make sure
 // no in-flight work uses the arena before `ensure` reallocates it.
+// Pinned host staging (hipHostMalloc), grown on demand.  An upload from it
+// records `ev`; wait() blocks until that upload has been read, so the buffer
+// can be refilled.
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    void *get(size_t bytes);  // waits for a pending upload first
+    void record(hipStream_t s);
+    void wait();
+    void release();
+};
+
 struct Arena {
     char *base = nullptr;
     size_t cap = 0, used = 0;
+    PinnedBuf host;  // staging of the per-launch snapshot table
     void ensure(size_t bytes);          // reallocate (contents lost) if smaller
     void reset() { used = 0; }
     void *take(size_t bytes, size_t align = 256);

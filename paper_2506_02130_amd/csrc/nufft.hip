@@ -22,9 +22,7 @@ namespace {
 struct Prepared {
     Layout L;
     PipeFn fn = nullptr;
-    SnapDev *snaps_dev = nullptr;
-    int *bins = nullptr, *rank = nullptr;
-    void *recs = nullptr, *ipsi = nullptr, *grid = nullptr;
+    Bufs B;
 };
 
 Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
@@ -48,15 +46,24 @@ Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w
     const size_t need = layout_bytes(L, dim, prec_bits, n);
     arena.ensure(need);
     arena.reset();
-    P.snaps_dev = (SnapDev *)arena.take(n * sizeof(SnapDev));
-    P.bins = (int *)arena.take(std::max<long long>(L.total_bins, 1) * 4);
-    P.rank = (int *)arena.take(std::max<long long>(L.total_src, 1) * 4);
-    P.recs = arena.take(std::max<long long>(L.total_src, 1) * rec_bytes(dim, prec_bits));
-    P.ipsi = arena.take(std::max<long long>(L.total_ipsi, 1) * (prec_bits == 32 ? 4 : 8));
-    P.grid = arena.take(std::max<long long>(L.total_grid, 1) * (prec_bits == 32 ? 8 : 16));
-    // the table is small; a blocking copy keeps the host vector's lifetime simple
-    FV_HIP(hipMemcpyAsync(P.snaps_dev, L.snaps.data(), n * sizeof(SnapDev), hipMemcpyHostToDevice, st));
-    FV_HIP(hipStreamSynchronize(st));
+    SnapDev *snaps_dev = (SnapDev *)arena.take(n * sizeof(SnapDev));
+    P.B.snaps = snaps_dev;
+    P.B.bins = (int *)arena.take(std::max<long long>(L.total_bins, 1) * 4);
+    P.B.rank = (int *)arena.take(std::max<long long>(L.total_src, 1) * 4);
+    P.B.recs = arena.take(std::max<long long>(L.total_src, 1) * rec_bytes(dim, prec_bits));
+    P.B.ipsi = arena.take(std::max<long long>(L.total_ipsi, 1) * (prec_bits == 32 ? 4 : 8));
+    P.B.grid = arena.take(std::max<long long>(L.total_grid, 1) * (prec_bits == 32 ? 8 : 16));
+    if (L.order_snap >= 0) {
+        P.B.perm = (int *)arena.take(L.order_src * 4);
+        P.B.order_counts = (int *)arena.take((L.order_bins + 1) * 4);
+        P.B.src_ord = (double *)arena.take(L.order_src * 24);
+    }
+    // the table goes up from pinned staging; the staging is reused only after
+    // this copy has completed (PinnedBuf::get waits for it)
+    void *stage = arena.host.get(n * sizeof(SnapDev));
+    std::memcpy(stage, L.snaps.data(), n * sizeof(SnapDev));
+    FV_HIP(hipMemcpyAsync(snaps_dev, stage, n * sizeof(SnapDev), hipMemcpyHostToDevice, st));
+    arena.host.record(st);
     return P;
 }
 
@@ -77,7 +84,7 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
                      hipStream_t st, StageTimer *timer) {
     if (jobs.empty()) return 0.0;
     Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st);
-    P.fn(P.L, P.snaps_dev, (int)jobs.size(), P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 7, timer);
+    P.fn(P.L, P.B, (int)jobs.size(), st, 7, timer);
     return P.L.model_bytes;
 }
 
@@ -87,12 +94,12 @@ void nufft_debug(const SnapJob &job, int dim, int prec_bits, int w, Arena &arena
     Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st);
     const SnapDev &d = P.L.snaps[0];
     const size_t csz = prec_bits == 32 ? 8 : 16;
-    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 1, nullptr);
-    if (spread) fetch_c128((char *)P.grid + d.bufA * csz, job.plan.cells1(), prec_bits, spread, st);
-    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 2, nullptr);
+    P.fn(P.L, P.B, 1, st, 1, nullptr);
+    if (spread) fetch_c128((char *)P.B.grid + d.bufA * csz, job.plan.cells1(), prec_bits, spread, st);
+    P.fn(P.L, P.B, 1, st, 2, nullptr);
     const long long fin = dim == 2 ? d.bufA : d.bufB;
-    if (fftout) fetch_c128((char *)P.grid + fin * csz, job.plan.cellsM(), prec_bits, fftout, st);
-    P.fn(P.L, P.snaps_dev, 1, P.bins, P.rank, P.recs, P.ipsi, P.grid, st, 4, nullptr);
+    if (fftout) fetch_c128((char *)P.B.grid + fin * csz, job.plan.cellsM(), prec_bits, fftout, st);
+    P.fn(P.L, P.B, 1, st, 4, nullptr);
     FV_HIP(hipStreamSynchronize(st));
 }
 

@@ -74,6 +74,24 @@ __device__ inline int find_snap(const SnapDev *snaps, int n_snap, long long v, i
     return lo;
 }
 
+// Workgroup coordinates (x within its snapshot, snapshot y).  gx == 0: the
+// plain 2-D grid (x, y) = blockIdx.  gx > 0: a 1-D grid of 8 gx ceil(n_snap / 8)
+// workgroups in which every workgroup of snapshot y runs on XCD y mod 8
+// (workgroups are dispatched to the 8 XCDs round-robin), so the data of one
+// snapshot stays in one L2.  Returns false for padding workgroups.
+__device__ __forceinline__ bool snap_block(int gx, int n_snap, int &x, int &y) {
+    if (gx <= 0) {
+        x = blockIdx.x;
+        y = blockIdx.y;
+        return true;
+    }
+    const int per = 8 * gx, id = blockIdx.x;
+    const int hi = id / per, r = id - hi * per;
+    y = hi * 8 + (r & 7);
+    x = r >> 3;
+    return y < n_snap;
+}
+
 // First kernel cell and sub-bin of a source (FP64 coordinates).
 template <int D>
 __device__ __forceinline__ int src_cell(const SnapDev &S, const double *s, double *g, int *l0) {
@@ -96,25 +114,50 @@ __global__ void k_fill_int(int *p, long long n, int v) {
     if (i < n) p[i] = v;
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_bin(const SnapDev *snaps, int *bins, int *rank) {
-    const SnapDev &S = snaps[blockIdx.y];
-    int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= S.n_src) return;
-    double s[3], g[3];
-    int l0[3];
-    for (int a = 0; a < D; ++a) s[a] = S.src[3 * (size_t)j + a];
-    int key = src_cell<D>(S, s, g, l0);
-    rank[S.src_base + j] = atomicAdd(&bins[S.bin_base + key], 1);
+// Rank of this lane's key among the lanes of its wavefront that share the key,
+// plus the count already in counts[key]: one returning atomic per distinct key
+// in the wavefront (lanes of a spatially ordered source list mostly share a
+// few sub-bins).  Every active lane of the wavefront must call it.
+__device__ __forceinline__ int wave_rank(int *counts, int key) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long todo = __ballot(1);
+    int rank = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lk = __shfl(key, leader, 64);
+        const unsigned long long m = __ballot(key == lk) & todo;
+        int old = 0;
+        if (lane == leader) old = atomicAdd(&counts[lk], __popcll(m));
+        old = __shfl(old, leader, 64);
+        if ((m >> lane) & 1ull) rank = old + __popcll(m & ((1ull << lane) - 1ull));
+        todo &= ~m;
+    }
+    return rank;
 }
 
-// Exclusive scan of each snapshot's sub-bin counts, one 1024-thread block per
-// snapshot, 4 counts per thread per chunk.
-__global__ __launch_bounds__(1024) void k_scan(const SnapDev *snaps, int *bins) {
-    const SnapDev &S = snaps[blockIdx.x];
-    long long nb = 1;
-    for (int a = 0; a < S.dim; ++a) nb *= S.nsb[a];
-    int *b = bins + S.bin_base;
+// Per-snapshot counting sort of the sources by sub-bin.  Sources are visited
+// in the order perm (a spatial order shared by all snapshots of one source
+// list) when perm is non-null, else in input order; rank and the records are
+// indexed by that visiting position i.
+template <int D>
+__global__ __launch_bounds__(256) void k_bin(const SnapDev *snaps, int gx, int n_snap, const int *perm,
+                                             const double *src_ord, int *bins, int *rank) {
+    int bx, sy;
+    if (!snap_block(gx, n_snap, bx, sy)) return;
+    const SnapDev &S = snaps[sy];
+    const int i = bx * 256 + threadIdx.x;
+    if (i >= S.n_src) return;
+    const double *sp = perm ? src_ord + 3 * (size_t)i : S.src + 3 * (size_t)i;
+    double s[3], g[3];
+    int l0[3];
+    for (int a = 0; a < D; ++a) s[a] = sp[a];
+    const int key = src_cell<D>(S, s, g, l0);
+    rank[S.src_base + i] = wave_rank(bins + S.bin_base, key);
+}
+
+// Exclusive scan of n counts in place (b[n] receives the total), by one
+// 1024-thread workgroup, 4 counts per thread per chunk.
+__device__ void scan_counts(int *b, long long nb) {
     __shared__ int wsum[16];
     __shared__ int carry_sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -158,17 +201,58 @@ __global__ __launch_bounds__(1024) void k_scan(const SnapDev *snaps, int *bins) 
     if (tid == 0) b[nb] = carry_sh;
 }
 
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_scatter(const SnapDev *snaps, const int *bins, const int *rank,
-                                                 Rec<R, D> *recs) {
-    const SnapDev &S = snaps[blockIdx.y];
-    int j = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(1024) void k_scan(const SnapDev *snaps, int *bins) {
+    const SnapDev &S = snaps[blockIdx.x];
+    long long nb = 1;
+    for (int a = 0; a < S.dim; ++a) nb *= S.nsb[a];
+    scan_counts(bins + S.bin_base, nb);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_one(int *b, long long nb) { scan_counts(b, nb); }
+
+// Spatial order of one source list: counting sort by the sub-bins of one
+// snapshot (the finest grid of the list), perm[position] = source index.
+template <int D>
+__global__ __launch_bounds__(256) void k_order_count(const SnapDev *S_, int *counts, int *rank) {
+    const SnapDev &S = *S_;
+    const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= S.n_src) return;
     double s[3], g[3];
     int l0[3];
     for (int a = 0; a < D; ++a) s[a] = S.src[3 * (size_t)j + a];
+    rank[j] = atomicAdd(&counts[src_cell<D>(S, s, g, l0)], 1);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_order_place(const SnapDev *S_, const int *starts, const int *rank,
+                                                     int *perm, double *src_ord) {
+    const SnapDev &S = *S_;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= S.n_src) return;
+    double s[3], g[3];
+    int l0[3];
+    for (int a = 0; a < 3; ++a) s[a] = S.src[3 * (size_t)j + a];
+    const int pos = starts[src_cell<D>(S, s, g, l0)] + rank[j];
+    perm[pos] = j;
+    for (int a = 0; a < 3; ++a) src_ord[3 * (size_t)pos + a] = s[a];
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_scatter(const SnapDev *snaps, int gx, int n_snap, const int *perm,
+                                                 const double *src_ord, const int *bins, const int *rank,
+                                                 Rec<R, D> *recs) {
+    int bx, sy;
+    if (!snap_block(gx, n_snap, bx, sy)) return;
+    const SnapDev &S = snaps[sy];
+    const int i = bx * 256 + threadIdx.x;
+    if (i >= S.n_src) return;
+    const int j = perm ? perm[i] : i;
+    const double *sp = perm ? src_ord + 3 * (size_t)i : S.src + 3 * (size_t)i;
+    double s[3], g[3];
+    int l0[3];
+    for (int a = 0; a < D; ++a) s[a] = sp[a];
     int key = src_cell<D>(S, s, g, l0);
-    long long pos = (long long)bins[S.bin_base + key] + rank[S.src_base + j];
+    long long pos = (long long)bins[S.bin_base + key] + rank[S.src_base + i];
     double c = S.flux[j];
     if (S.beam) c *= S.beam[j];
     double t = 0.0;
@@ -233,15 +317,16 @@ __device__ __forceinline__ double es_phi_fast(double z, double beta) { return es
 // accumulates.  No atomics; each grid cell is written once, after
 // multiplication by 1/psi2hat (the first deconvolution).
 template <typename R, int D, int W>
-__global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, const int *bins, const Rec<R, D> *recs,
-                                                const R *ipsi, cplx<R> *grid) {
+__global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, int n_snap, const int *bins,
+                                                const Rec<R, D> *recs, const R *ipsi, cplx<R> *grid) {
     using Cfg = SpreadCfg<R, D, W>;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const SnapDev &S = snaps[blockIdx.y];
+    int blk, sy;
+    if (!snap_block(gx, n_snap, blk, sy)) return;
+    const SnapDev &S = snaps[sy];
     const int nbx = (S.n1[0] + Cfg::BX - 1) / Cfg::BX, nby = (S.n1[1] + Cfg::BY - 1) / Cfg::BY;
     const int nbz = D == 3 ? (S.n1[2] + Cfg::BZ - 1) / Cfg::BZ : 1;
-    const int blk = blockIdx.x;
     if (blk >= nbx * nby * nbz) return;
     const int x0 = (blk % nbx) * Cfg::BX + 8 * wave;
     if (x0 >= S.n1[0]) return;
@@ -345,15 +430,15 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, const int 
             wave_sync();
         }
         // flush: divide by psi2hat at the modes and store each owned cell once
-        const int gx = x0 + cx, gy = y0 + cy;
-        if (gx < S.n1[0] && gy < S.n1[1]) {
-            const R fxy = ix_t[gx] * iy_t[gy];
+        const int ox = x0 + cx, oy = y0 + cy;
+        if (ox < S.n1[0] && oy < S.n1[1]) {
+            const R fxy = ix_t[ox] * iy_t[oy];
 #pragma unroll
             for (int k = 0; k < Cfg::TZ; ++k) {
-                const int gz = z0 + k;
-                if (D == 3 && gz >= S.n1[2]) break;
-                const R f = D == 3 ? fxy * iz_t[gz] : fxy;
-                dst[((long long)gz * S.n1[1] + gy) * S.n1[0] + gx] = cmake<R>(accr[k] * f, acci[k] * f);
+                const int oz = z0 + k;
+                if (D == 3 && oz >= S.n1[2]) break;
+                const R f = D == 3 ? fxy * iz_t[oz] : fxy;
+                dst[((long long)oz * S.n1[1] + oy) * S.n1[0] + ox] = cmake<R>(accr[k] * f, acci[k] * f);
             }
         }
     }
@@ -379,15 +464,16 @@ struct SpreadMfmaCfg {
 };
 
 template <typename R, int W>
-__global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, const int *bins, const Rec<R, 2> *recs,
-                                                     const R *ipsi, cplx<R> *grid) {
+__global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int gx, int n_snap, const int *bins,
+                                                     const Rec<R, 2> *recs, const R *ipsi, cplx<R> *grid) {
     using Cfg = SpreadMfmaCfg<R, W>;
     using MA = MfmaAcc<R>;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const SnapDev &S = snaps[blockIdx.y];
+    int blk, sy;
+    if (!snap_block(gx, n_snap, blk, sy)) return;
+    const SnapDev &S = snaps[sy];
     const int nbx = (S.n1[0] + Cfg::BX - 1) / Cfg::BX, nby = (S.n1[1] + Cfg::BY - 1) / Cfg::BY;
-    const int blk = blockIdx.x;
     if (blk >= nbx * nby) return;
     const int x0 = (blk % nbx) * Cfg::BX + Cfg::T * wave;
     if (x0 >= S.n1[0]) return;
@@ -461,13 +547,13 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, const
     const R *ix_t = ipsi + S.ipsi_base;
     const R *iy_t = ix_t + S.n1[0];
     cplx<R> *dst = grid + S.bufA;
-    const int gx = x0 + li;
+    const int cx_ = x0 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int gy = y0 + MA::row(lane, r);
-        if (gx < S.n1[0] && gy < S.n1[1]) {
-            const R f = ix_t[gx] * iy_t[gy];
-            dst[(long long)gy * S.n1[0] + gx] = cmake<R>(accr[r] * f, acci[r] * f);
+        const int cy_ = y0 + MA::row(lane, r);
+        if (cx_ < S.n1[0] && cy_ < S.n1[1]) {
+            const R f = ix_t[cx_] * iy_t[cy_];
+            dst[(long long)cy_ * S.n1[0] + cx_] = cmake<R>(accr[r] * f, acci[r] * f);
         }
     }
 }
@@ -742,9 +828,11 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
 // Interpolation at the targets, deconvolution by psi1hat, centring phase,
 // reflection undone, written to the caller's pair layout.
 template <typename R, int D, int W>
-__global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, const cplx<R> *grid) {
-    const SnapDev &S = snaps[blockIdx.y];
-    const int t = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, int n_snap, const cplx<R> *grid) {
+    int bx, sy;
+    if (!snap_block(gx, n_snap, bx, sy)) return;
+    const SnapDev &S = snaps[sy];
+    const int t = bx * 256 + threadIdx.x;
     if (t >= S.n_tgt) return;
     const cplx<R> *g = grid + (D == 2 ? S.bufA : S.bufB);
     const R beta = (R)S.beta;
@@ -872,6 +960,19 @@ struct Layout {
     size_t fft_lds[3] = {0, 0, 0};
     double model_bytes = 0;
     double sbytes[FV_NSTAGE] = {0, 0, 0, 0, 0, 0, 0, 0};  // algorithmic bytes per stage
+    // one spatial source order shared by every snapshot (all snapshots read
+    // the same source list): taken from the sub-bins of snapshot `order_snap`
+    int order_snap = -1;
+    long long order_bins = 0, order_src = 0;
+};
+
+// Device buffers of one pipeline run.
+struct Bufs {
+    const SnapDev *snaps = nullptr;  // device copy of Layout::snaps
+    int *bins = nullptr, *rank = nullptr;
+    void *recs = nullptr, *ipsi = nullptr, *grid = nullptr;
+    int *perm = nullptr, *order_counts = nullptr;  // null unless Layout::order_snap >= 0
+    double *src_ord = nullptr;                     // source directions in the order perm
 };
 
 // Upper bound on the lines one FFT workgroup transforms together (tunable
@@ -1055,6 +1156,21 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         }
         L.snaps.push_back(d);
     }
+    // a shared source order pays off when several snapshots bin the same list
+    if (jobs.size() >= 2 && jobs[0].n_src > 0) {
+        bool same = true;
+        for (auto &j : jobs) same = same && j.src == jobs[0].src && j.n_src == jobs[0].n_src;
+        if (same) {
+            int best = 0;
+            for (int i = 1; i < (int)jobs.size(); ++i)
+                if (jobs[i].plan.cells1() > jobs[best].plan.cells1()) best = i;
+            long long nb = 1;
+            for (int a = 0; a < dim; ++a) nb *= L.snaps[best].nsb[a];
+            L.order_snap = best;
+            L.order_bins = nb;
+            L.order_src = jobs[0].n_src;
+        }
+    }
     return L;
 }
 
@@ -1063,7 +1179,16 @@ inline size_t layout_bytes(const Layout &L, int dim, int prec_bits, int n_snap) 
     const size_t csz = prec_bits == 32 ? 8 : 16, rsz = prec_bits == 32 ? 4 : 8;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     return al(n_snap * sizeof(SnapDev)) + al(L.total_bins * 4) + al(L.total_src * 4) +
-           al(L.total_src * rec_bytes(dim, prec_bits)) + al(L.total_ipsi * rsz) + al(L.total_grid * csz) + 4096;
+           al(L.total_src * rec_bytes(dim, prec_bits)) + al(L.total_ipsi * rsz) + al(L.total_grid * csz) +
+           al(L.order_src * 4) + al((L.order_bins + 1) * 4) + al(L.order_src * 24) + 4096;
+}
+
+// Snapshot-per-XCD launches when the snapshots fill the 8 XCDs evenly enough
+// (FV_XCD_AFFINE=0 turns them off, =1 forces them on).
+inline bool xcd_affine(int n_snap) {
+    static const int mode = env_int("FV_XCD_AFFINE", -1);
+    if (mode >= 0) return mode == 1;
+    return n_snap % 8 == 0 || n_snap >= 32;
 }
 
 // Kernels asking for more than 64 KB of dynamic LDS must say so first.
@@ -1073,11 +1198,22 @@ inline void ensure_lds(const void *fn, size_t bytes) {
 
 // stages: bit 0 sort + spread, bit 1 FFT passes, bit 2 interpolation.
 template <typename R, int D, int W>
-void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bins, int *rank, void *recs_v,
-                  R *ipsi, cplx<R> *grid, hipStream_t st, int stages, StageTimer *tm) {
+void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, int stages, StageTimer *tm) {
     StageTimer dummy;
     if (!tm) tm = &dummy;
-    auto recs = (Rec<R, D> *)recs_v;
+    const SnapDev *snaps_dev = B.snaps;
+    int *bins = B.bins, *rank = B.rank;
+    auto recs = (Rec<R, D> *)B.recs;
+    R *ipsi = (R *)B.ipsi;
+    cplx<R> *grid = (cplx<R> *)B.grid;
+    const int *perm = L.order_snap >= 0 ? B.perm : nullptr;
+    // per-snapshot launches: XCD-affine 1-D grids when the snapshots spread
+    // evenly over the 8 XCDs, else plain (x, snapshot) grids
+    const bool affine = xcd_affine(n_snap);
+    auto sgrid = [&](long long gx) {
+        return affine ? dim3((unsigned)(8 * gx * ((n_snap + 7) / 8))) : dim3((unsigned)gx, (unsigned)n_snap);
+    };
+    auto sgx = [&](long long gx) { return affine ? (int)gx : 0; };
     auto blocks = [](long long n, int b) { return (unsigned)((n + b - 1) / b); };
     if (stages & 1) {
     if (L.total_bins)
@@ -1088,30 +1224,48 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
     tm->end(st);
     tm->add(FV_STAGE_OTHER, L.sbytes[FV_STAGE_OTHER], 1);
     tm->begin(FV_STAGE_SORT, st);
+    int sort_launches = 3;
+    if (perm) {
+        // the shared spatial order (rank is scratch here; k_bin rewrites it)
+        const SnapDev *os = snaps_dev + L.order_snap;
+        hipLaunchKernelGGL(k_fill_int, dim3(blocks(L.order_bins + 1, 256)), dim3(256), 0, st, B.order_counts,
+                           L.order_bins + 1, 0);
+        hipLaunchKernelGGL(k_order_count<D>, dim3(blocks(L.order_src, 256)), dim3(256), 0, st, os, B.order_counts,
+                           rank);
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, B.order_counts, L.order_bins);
+        hipLaunchKernelGGL(k_order_place<D>, dim3(blocks(L.order_src, 256)), dim3(256), 0, st, os,
+                           (const int *)B.order_counts, (const int *)rank, B.perm, B.src_ord);
+        sort_launches += 4;
+    }
     if (L.max_src) {
-        hipLaunchKernelGGL(k_bin<D>, dim3(blocks(L.max_src, 256), n_snap), dim3(256), 0, st, snaps_dev, bins, rank);
+        const long long gx = blocks(L.max_src, 256);
+        hipLaunchKernelGGL(k_bin<D>, sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap, perm,
+                           (const double *)B.src_ord, bins, rank);
     }
     hipLaunchKernelGGL(k_scan, dim3(n_snap), dim3(1024), 0, st, snaps_dev, bins);
     if (L.max_src) {
-        hipLaunchKernelGGL((k_scatter<R, D>), dim3(blocks(L.max_src, 256), n_snap), dim3(256), 0, st, snaps_dev,
-                           (const int *)bins, (const int *)rank, recs);
+        const long long gx = blocks(L.max_src, 256);
+        hipLaunchKernelGGL((k_scatter<R, D>), sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap, perm,
+                           (const double *)B.src_ord, (const int *)bins, (const int *)rank, recs);
     }
     tm->end(st);
-    tm->add(FV_STAGE_SORT, L.sbytes[FV_STAGE_SORT], 4);
+    tm->add(FV_STAGE_SORT, L.sbytes[FV_STAGE_SORT], sort_launches);
     {
         tm->begin(FV_STAGE_SPREAD, st);
         if constexpr (D == 2) {
             using MC = SpreadMfmaCfg<R, W>;
             const size_t lds = (size_t)MC::WPB * MC::WAVE_BYTES;
             ensure_lds((const void *)k_spread_mfma<R, W>, lds);
-            hipLaunchKernelGGL((k_spread_mfma<R, W>), dim3((unsigned)L.max_tiles, n_snap), dim3(64 * MC::WPB), lds,
-                               st, snaps_dev, (const int *)bins, (const Rec<R, 2> *)recs, (const R *)ipsi, grid);
+            hipLaunchKernelGGL((k_spread_mfma<R, W>), sgrid(L.max_tiles), dim3(64 * MC::WPB), lds, st, snaps_dev,
+                               sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, 2> *)recs, (const R *)ipsi,
+                               grid);
         } else {
             using Cfg = SpreadCfg<R, D, W>;
             const size_t lds = spread_lds<R, D, W>();
             ensure_lds((const void *)k_spread<R, D, W>, lds);
-            hipLaunchKernelGGL((k_spread<R, D, W>), dim3((unsigned)L.max_tiles, n_snap), dim3(64 * Cfg::WPB), lds, st,
-                               snaps_dev, (const int *)bins, (const Rec<R, D> *)recs, (const R *)ipsi, grid);
+            hipLaunchKernelGGL((k_spread<R, D, W>), sgrid(L.max_tiles), dim3(64 * Cfg::WPB), lds, st, snaps_dev,
+                               sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, D> *)recs,
+                               (const R *)ipsi, grid);
         }
         tm->end(st);
         tm->add(FV_STAGE_SPREAD, L.sbytes[FV_STAGE_SPREAD], 1);
@@ -1145,7 +1299,8 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
     }
     if ((stages & 4) && L.max_tgt) {
         tm->begin(FV_STAGE_INTERP, st);
-        hipLaunchKernelGGL((k_interp<R, D, W>), dim3(blocks(L.max_tgt, 256), n_snap), dim3(256), 0, st, snaps_dev,
+        const long long gx = blocks(L.max_tgt, 256);
+        hipLaunchKernelGGL((k_interp<R, D, W>), sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap,
                            (const cplx<R> *)grid);
         tm->end(st);
         tm->add(FV_STAGE_INTERP, L.sbytes[FV_STAGE_INTERP], 1);
@@ -1153,13 +1308,11 @@ void run_pipeline(const Layout &L, const SnapDev *snaps_dev, int n_snap, int *bi
     FV_HIP(hipGetLastError());
 }
 
-using PipeFn = void (*)(const Layout &, const SnapDev *, int, int *, int *, void *, void *, void *, hipStream_t,
-                        int, StageTimer *);
+using PipeFn = void (*)(const Layout &, const Bufs &, int, hipStream_t, int, StageTimer *);
 
 template <typename R, int D, int W>
-void pipe_entry(const Layout &L, const SnapDev *sd, int n, int *bins, int *rank, void *recs, void *ipsi, void *grid,
-                hipStream_t st, int stages, StageTimer *tm) {
-    run_pipeline<R, D, W>(L, sd, n, bins, rank, recs, (R *)ipsi, (cplx<R> *)grid, st, stages, tm);
+void pipe_entry(const Layout &L, const Bufs &B, int n, hipStream_t st, int stages, StageTimer *tm) {
+    run_pipeline<R, D, W>(L, B, n, st, stages, tm);
 }
 
 template <typename R, int D, int... Ws>

@@ -34,6 +34,42 @@ void *Arena::take(size_t bytes, size_t align) {
     return base + off;
 }
 
+void *PinnedBuf::get(size_t bytes) {
+    wait();
+    if (bytes > cap) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t want = std::max<size_t>(bytes, 4096);
+        FV_HIP(hipHostMalloc(&p, want, hipHostMallocDefault));
+        cap = want;
+    }
+    return p;
+}
+
+void PinnedBuf::record(hipStream_t s) {
+    if (!ev) FV_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    FV_HIP(hipEventRecord(ev, s));
+    pending = true;
+}
+
+void PinnedBuf::wait() {
+    if (pending) {
+        pending = false;
+        FV_HIP(hipEventSynchronize(ev));
+    }
+}
+
+void PinnedBuf::release() {
+    if (pending && ev) (void)hipEventSynchronize(ev);
+    pending = false;
+    if (p) (void)hipHostFree(p);
+    if (ev) (void)hipEventDestroy(ev);
+    p = nullptr;
+    ev = nullptr;
+    cap = 0;
+}
+
 void Arena::ensure(size_t bytes) {
     if (bytes <= cap) return;
     release();
@@ -128,6 +164,8 @@ static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603u
 }
 
 Slot::~Slot() {
+    arena.host.release();
+    inputs.host.release();
     arena.release();
     inputs.release();
     if (stream && own_stream) (void)hipStreamDestroy(stream);
@@ -140,6 +178,7 @@ using namespace fv;
 fv_ctx::~fv_ctx() {
     targets.clear();
     cache.release();
+    plan_pin.release();
     if (scalar_buf) (void)hipFree(scalar_buf);
 }
 
@@ -463,20 +502,23 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     if (!(p->eps >= 1e-14 && p->eps <= 1e-1)) fv::fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
     FV_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    // planning scalars to the host
-    std::vector<double> ant(3 * (size_t)p->n_ant), freq(p->n_freq);
-    FV_HIP(hipMemcpyAsync(ant.data(), p->ant_enu, ant.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    FV_HIP(hipMemcpyAsync(freq.data(), p->freq_hz, freq.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    // planning scalars to the host, through pinned staging: [check 8][freq][ant]
+    const size_t n_ant3 = 3 * (size_t)p->n_ant;
+    double *pin = (double *)ctx->plan_pin.get((8 + (size_t)p->n_freq + n_ant3) * sizeof(double));
+    double *host_chk = pin, *pfreq = pin + 8, *pant = pfreq + p->n_freq;
+    for (int k = 0; k < 8; ++k) host_chk[k] = 0.0;
+    FV_HIP(hipMemcpyAsync(pant, p->ant_enu, n_ant3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    FV_HIP(hipMemcpyAsync(pfreq, p->freq_hz, p->n_freq * sizeof(double), hipMemcpyDeviceToHost, st));
     double *chk = ctx->scalars(st);  // device: 7 doubles + 1 int
-    double host_chk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (p->n_src > 0) {
         fv::launch_src_check(p->src_lmn, p->n_src, chk, st);
         int *bad = (int *)(chk + 7);
         fv::launch_count_nonfinite(p->flux, (long long)p->n_src * p->n_freq, bad, st);
         if (p->beam) fv::launch_count_nonfinite(p->beam, (long long)p->n_src * p->n_freq, bad, st);
-        FV_HIP(hipMemcpyAsync(host_chk, chk, sizeof(host_chk), hipMemcpyDeviceToHost, st));
+        FV_HIP(hipMemcpyAsync(host_chk, chk, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
     }
     FV_HIP(hipStreamSynchronize(st));
+    const std::vector<double> ant(pant, pant + n_ant3), freq(pfreq, pfreq + p->n_freq);
     fv_problem meta = *p;
     meta.ant_enu = ant.data();
     meta.freq_hz = freq.data();
