@@ -4,6 +4,7 @@
 #include <condition_variable>
 #include <deque>
 #include <list>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -65,7 +66,24 @@ void validate_host(const fv_problem *p);
 DevInputs upload(Slot &slot, const fv_problem *p, double *s_c, double *S);
 void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevInputs &in, double *vis_dev,
                 fv_report *rep);
+
+// Kernel family of a group of NUFFT jobs.
+struct NufftGroupKey {
+    int dim = 2, prec = 32, w = 8, fold_axis = -1;
+    bool operator<(const NufftGroupKey &o) const {
+        return std::tie(dim, prec, w) < std::tie(o.dim, o.prec, o.w);
+    }
+};
+NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in, double *vis_dev, hipStream_t st,
+                          std::vector<SnapJob> &jobs, std::vector<std::shared_ptr<TargetTable>> &hold,
+                          SnapPlan *top);
+double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, const NufftGroupKey &k,
+                    StageTimer *tm);
+void run_direct(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int dim,
+                int prec, StageTimer *tm);
+void fill_report(StageTimer &tm, fv_report &r);
 void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv_report *rep);
+void simulate_batch(fv_ctx *ctx, Slot &slot, int n, const fv_problem *ps, double *const *vis, fv_report *rep);
 const char *last_error_cstr();
 void set_last_error(const std::string &msg);
 

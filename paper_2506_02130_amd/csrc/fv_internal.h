@@ -52,6 +52,7 @@ struct SnapDev {
     long long bufA, bufB;            // element offsets of the two grid regions
     long long ipsi_base;             // offset of the 1/psi2hat tables (n1[0] | n1[1] | n1[2])
     long long wg_base[3];            // first workgroup of each FFT pass
+    long long order_base;            // offset of this source list's shared order, or -1
     const double *src;               // [n_src][3]
     const double *flux;              // [n_src] this frequency
     const double *beam;              // [n_src] this frequency, or nullptr

@@ -53,16 +53,21 @@ Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w
     P.B.recs = arena.take(std::max<long long>(L.total_src, 1) * rec_bytes(dim, prec_bits));
     P.B.ipsi = arena.take(std::max<long long>(L.total_ipsi, 1) * (prec_bits == 32 ? 4 : 8));
     P.B.grid = arena.take(std::max<long long>(L.total_grid, 1) * (prec_bits == 32 ? 8 : 16));
-    if (L.order_snap >= 0) {
+    const size_t ng = L.orders.size();
+    if (ng) {
         P.B.perm = (int *)arena.take(L.order_src * 4);
-        P.B.order_counts = (int *)arena.take((L.order_bins + 1) * 4);
+        P.B.order_counts = (int *)arena.take(L.order_counts * 4);
         P.B.src_ord = (double *)arena.take(L.order_src * 24);
+        P.B.orders = (OrderGroup *)arena.take(ng * sizeof(OrderGroup));
     }
-    // the table goes up from pinned staging; the staging is reused only after
+    // the tables go up from pinned staging; the staging is reused only after
     // this copy has completed (PinnedBuf::get waits for it)
-    void *stage = arena.host.get(n * sizeof(SnapDev));
-    std::memcpy(stage, L.snaps.data(), n * sizeof(SnapDev));
-    FV_HIP(hipMemcpyAsync(snaps_dev, stage, n * sizeof(SnapDev), hipMemcpyHostToDevice, st));
+    const size_t tb = n * sizeof(SnapDev), ob = ng * sizeof(OrderGroup);
+    char *stage = (char *)arena.host.get(tb + ob);
+    std::memcpy(stage, L.snaps.data(), tb);
+    if (ng) std::memcpy(stage + tb, L.orders.data(), ob);
+    FV_HIP(hipMemcpyAsync(snaps_dev, stage, tb, hipMemcpyHostToDevice, st));
+    if (ng) FV_HIP(hipMemcpyAsync(P.B.orders, stage + tb, ob, hipMemcpyHostToDevice, st));
     arena.host.record(st);
     return P;
 }

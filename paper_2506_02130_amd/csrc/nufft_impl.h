@@ -27,6 +27,7 @@
 #include <utility>
 
 #include <algorithm>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 #include <stdexcept>
@@ -140,14 +141,14 @@ __device__ __forceinline__ int wave_rank(int *counts, int key) {
 // list) when perm is non-null, else in input order; rank and the records are
 // indexed by that visiting position i.
 template <int D>
-__global__ __launch_bounds__(256) void k_bin(const SnapDev *snaps, int gx, int n_snap, const int *perm,
-                                             const double *src_ord, int *bins, int *rank) {
+__global__ __launch_bounds__(256) void k_bin(const SnapDev *snaps, int gx, int n_snap, const double *src_ord,
+                                             int *bins, int *rank) {
     int bx, sy;
     if (!snap_block(gx, n_snap, bx, sy)) return;
     const SnapDev &S = snaps[sy];
     const int i = bx * 256 + threadIdx.x;
     if (i >= S.n_src) return;
-    const double *sp = perm ? src_ord + 3 * (size_t)i : S.src + 3 * (size_t)i;
+    const double *sp = S.order_base >= 0 ? src_ord + 3 * (S.order_base + i) : S.src + 3 * (size_t)i;
     double s[3], g[3];
     int l0[3];
     for (int a = 0; a < D; ++a) s[a] = sp[a];
@@ -208,33 +209,50 @@ __global__ __launch_bounds__(1024) void k_scan(const SnapDev *snaps, int *bins) 
     scan_counts(bins + S.bin_base, nb);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_one(int *b, long long nb) { scan_counts(b, nb); }
+// Shared spatial order of a source list read by several snapshots: counting
+// sort by the sub-bins of one snapshot of the list (its finest grid).
+// Workgroup row y handles list y; perm[base + position] = source index and
+// src_ord holds the directions in that order.
+struct OrderGroup {
+    int snap;              // snapshot whose sub-bins define the order
+    int n_src;
+    long long base;        // offset in perm / rank scratch (and 3x in src_ord)
+    long long cnt_base;    // offset of the list's nb + 1 counts
+    long long nb;          // sub-bins of that snapshot
+};
 
-// Spatial order of one source list: counting sort by the sub-bins of one
-// snapshot (the finest grid of the list), perm[position] = source index.
 template <int D>
-__global__ __launch_bounds__(256) void k_order_count(const SnapDev *S_, int *counts, int *rank) {
-    const SnapDev &S = *S_;
+__global__ __launch_bounds__(256) void k_order_count(const SnapDev *snaps, const OrderGroup *groups, int *counts,
+                                                     int *rank) {
+    const OrderGroup G = groups[blockIdx.y];
+    const SnapDev &S = snaps[G.snap];
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= S.n_src) return;
+    if (j >= G.n_src) return;
     double s[3], g[3];
     int l0[3];
     for (int a = 0; a < D; ++a) s[a] = S.src[3 * (size_t)j + a];
-    rank[j] = atomicAdd(&counts[src_cell<D>(S, s, g, l0)], 1);
+    rank[G.base + j] = atomicAdd(&counts[G.cnt_base + src_cell<D>(S, s, g, l0)], 1);
+}
+
+__global__ __launch_bounds__(1024) void k_order_scan(const OrderGroup *groups, int *counts) {
+    const OrderGroup G = groups[blockIdx.x];
+    scan_counts(counts + G.cnt_base, G.nb);
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_order_place(const SnapDev *S_, const int *starts, const int *rank,
-                                                     int *perm, double *src_ord) {
-    const SnapDev &S = *S_;
+__global__ __launch_bounds__(256) void k_order_place(const SnapDev *snaps, const OrderGroup *groups,
+                                                     const int *starts, const int *rank, int *perm,
+                                                     double *src_ord) {
+    const OrderGroup G = groups[blockIdx.y];
+    const SnapDev &S = snaps[G.snap];
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= S.n_src) return;
+    if (j >= G.n_src) return;
     double s[3], g[3];
     int l0[3];
     for (int a = 0; a < 3; ++a) s[a] = S.src[3 * (size_t)j + a];
-    const int pos = starts[src_cell<D>(S, s, g, l0)] + rank[j];
+    const long long pos = G.base + starts[G.cnt_base + src_cell<D>(S, s, g, l0)] + rank[G.base + j];
     perm[pos] = j;
-    for (int a = 0; a < 3; ++a) src_ord[3 * (size_t)pos + a] = s[a];
+    for (int a = 0; a < 3; ++a) src_ord[3 * pos + a] = s[a];
 }
 
 template <typename R, int D>
@@ -246,8 +264,9 @@ __global__ __launch_bounds__(256) void k_scatter(const SnapDev *snaps, int gx, i
     const SnapDev &S = snaps[sy];
     const int i = bx * 256 + threadIdx.x;
     if (i >= S.n_src) return;
-    const int j = perm ? perm[i] : i;
-    const double *sp = perm ? src_ord + 3 * (size_t)i : S.src + 3 * (size_t)i;
+    const bool ord = S.order_base >= 0;
+    const int j = ord ? perm[S.order_base + i] : i;
+    const double *sp = ord ? src_ord + 3 * (S.order_base + i) : S.src + 3 * (size_t)i;
     double s[3], g[3];
     int l0[3];
     for (int a = 0; a < D; ++a) s[a] = sp[a];
@@ -960,10 +979,9 @@ struct Layout {
     size_t fft_lds[3] = {0, 0, 0};
     double model_bytes = 0;
     double sbytes[FV_NSTAGE] = {0, 0, 0, 0, 0, 0, 0, 0};  // algorithmic bytes per stage
-    // one spatial source order shared by every snapshot (all snapshots read
-    // the same source list): taken from the sub-bins of snapshot `order_snap`
-    int order_snap = -1;
-    long long order_bins = 0, order_src = 0;
+    // shared spatial orders, one per source list read by several snapshots
+    std::vector<OrderGroup> orders;
+    long long order_src = 0, order_counts = 0, max_order_src = 0;
 };
 
 // Device buffers of one pipeline run.
@@ -971,8 +989,9 @@ struct Bufs {
     const SnapDev *snaps = nullptr;  // device copy of Layout::snaps
     int *bins = nullptr, *rank = nullptr;
     void *recs = nullptr, *ipsi = nullptr, *grid = nullptr;
-    int *perm = nullptr, *order_counts = nullptr;  // null unless Layout::order_snap >= 0
+    int *perm = nullptr, *order_counts = nullptr;  // null unless Layout::orders is non-empty
     double *src_ord = nullptr;                     // source directions in the order perm
+    OrderGroup *orders = nullptr;                  // device copy of Layout::orders
 };
 
 // Upper bound on the lines one FFT workgroup transforms together (tunable
@@ -1037,6 +1056,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         const SnapPlan &p = j.plan;
         SnapDev d;
         std::memset(&d, 0, sizeof(d));
+        d.order_base = -1;
         long long nb = 1, ncell = 1, nipsi = 0;
         for (int a = 0; a < 3; ++a) {
             d.n1[a] = p.n1[a];
@@ -1157,19 +1177,26 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         L.snaps.push_back(d);
     }
     // a shared source order pays off when several snapshots bin the same list
-    if (jobs.size() >= 2 && jobs[0].n_src > 0) {
-        bool same = true;
-        for (auto &j : jobs) same = same && j.src == jobs[0].src && j.n_src == jobs[0].n_src;
-        if (same) {
-            int best = 0;
-            for (int i = 1; i < (int)jobs.size(); ++i)
-                if (jobs[i].plan.cells1() > jobs[best].plan.cells1()) best = i;
-            long long nb = 1;
-            for (int a = 0; a < dim; ++a) nb *= L.snaps[best].nsb[a];
-            L.order_snap = best;
-            L.order_bins = nb;
-            L.order_src = jobs[0].n_src;
-        }
+    std::map<std::pair<const double *, int>, std::vector<int>> lists;
+    for (int i = 0; i < (int)jobs.size(); ++i)
+        if (jobs[i].n_src > 0) lists[{jobs[i].src, jobs[i].n_src}].push_back(i);
+    for (auto &kv : lists) {
+        if (kv.second.size() < 2) continue;
+        int best = kv.second[0];
+        for (int i : kv.second)
+            if (jobs[i].plan.cells1() > jobs[best].plan.cells1()) best = i;
+        OrderGroup G;
+        G.snap = best;
+        G.n_src = kv.first.second;
+        G.base = L.order_src;
+        G.cnt_base = L.order_counts;
+        G.nb = 1;
+        for (int a = 0; a < dim; ++a) G.nb *= L.snaps[best].nsb[a];
+        for (int i : kv.second) L.snaps[i].order_base = G.base;
+        L.order_src += G.n_src;
+        L.order_counts += G.nb + 1;
+        L.max_order_src = std::max<long long>(L.max_order_src, G.n_src);
+        L.orders.push_back(G);
     }
     return L;
 }
@@ -1180,7 +1207,8 @@ inline size_t layout_bytes(const Layout &L, int dim, int prec_bits, int n_snap) 
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     return al(n_snap * sizeof(SnapDev)) + al(L.total_bins * 4) + al(L.total_src * 4) +
            al(L.total_src * rec_bytes(dim, prec_bits)) + al(L.total_ipsi * rsz) + al(L.total_grid * csz) +
-           al(L.order_src * 4) + al((L.order_bins + 1) * 4) + al(L.order_src * 24) + 4096;
+           al(L.order_src * 4) + al(L.order_counts * 4) + al(L.order_src * 24) +
+           al(L.orders.size() * sizeof(OrderGroup)) + 4096;
 }
 
 // Snapshot-per-XCD launches when the snapshots fill the 8 XCDs evenly enough
@@ -1206,7 +1234,7 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     auto recs = (Rec<R, D> *)B.recs;
     R *ipsi = (R *)B.ipsi;
     cplx<R> *grid = (cplx<R> *)B.grid;
-    const int *perm = L.order_snap >= 0 ? B.perm : nullptr;
+    const int *perm = L.orders.empty() ? nullptr : B.perm;
     // per-snapshot launches: XCD-affine 1-D grids when the snapshots spread
     // evenly over the 8 XCDs, else plain (x, snapshot) grids
     const bool affine = xcd_affine(n_snap);
@@ -1226,20 +1254,22 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     tm->begin(FV_STAGE_SORT, st);
     int sort_launches = 3;
     if (perm) {
-        // the shared spatial order (rank is scratch here; k_bin rewrites it)
-        const SnapDev *os = snaps_dev + L.order_snap;
-        hipLaunchKernelGGL(k_fill_int, dim3(blocks(L.order_bins + 1, 256)), dim3(256), 0, st, B.order_counts,
-                           L.order_bins + 1, 0);
-        hipLaunchKernelGGL(k_order_count<D>, dim3(blocks(L.order_src, 256)), dim3(256), 0, st, os, B.order_counts,
-                           rank);
-        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, B.order_counts, L.order_bins);
-        hipLaunchKernelGGL(k_order_place<D>, dim3(blocks(L.order_src, 256)), dim3(256), 0, st, os,
-                           (const int *)B.order_counts, (const int *)rank, B.perm, B.src_ord);
+        // the shared spatial orders (rank is scratch here; k_bin rewrites it)
+        const unsigned ng = (unsigned)L.orders.size();
+        hipLaunchKernelGGL(k_fill_int, dim3(blocks(L.order_counts, 256)), dim3(256), 0, st, B.order_counts,
+                           L.order_counts, 0);
+        hipLaunchKernelGGL(k_order_count<D>, dim3(blocks(L.max_order_src, 256), ng), dim3(256), 0, st, snaps_dev,
+                           (const OrderGroup *)B.orders, B.order_counts, rank);
+        hipLaunchKernelGGL(k_order_scan, dim3(ng), dim3(1024), 0, st, (const OrderGroup *)B.orders,
+                           B.order_counts);
+        hipLaunchKernelGGL(k_order_place<D>, dim3(blocks(L.max_order_src, 256), ng), dim3(256), 0, st, snaps_dev,
+                           (const OrderGroup *)B.orders, (const int *)B.order_counts, (const int *)rank, B.perm,
+                           B.src_ord);
         sort_launches += 4;
     }
     if (L.max_src) {
         const long long gx = blocks(L.max_src, 256);
-        hipLaunchKernelGGL(k_bin<D>, sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap, perm,
+        hipLaunchKernelGGL(k_bin<D>, sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap,
                            (const double *)B.src_ord, bins, rank);
     }
     hipLaunchKernelGGL(k_scan, dim3(n_snap), dim3(1024), 0, st, snaps_dev, bins);

@@ -284,6 +284,89 @@ void validate_host(const fv_problem *p) {
     if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6) fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
 }
 
+// NUFFT jobs (one per frequency) of one problem whose inputs are on the
+// device; keeps the target table alive through `hold`.
+NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in, double *vis_dev, hipStream_t st,
+                          std::vector<SnapJob> &jobs, std::vector<std::shared_ptr<TargetTable>> &hold,
+                          SnapPlan *top) {
+    const int n_freq = p.n_freq, n_src = p.n_src;
+    const long long n_pairs = (long long)p.n_ant * (p.n_ant + 1) / 2;
+    NufftGroupKey k;
+    k.dim = choose_dim(p.ant_enu, p.n_ant, p.eps, p.freq_hz, n_freq, p.flags);
+    k.prec = choose_prec(p.eps, p.flags);
+    const bool fold = !(p.flags & FV_NO_FOLD);
+    GeomPlan g = ctx_geometry(ctx, p.ant_enu, p.n_ant, k.dim, p.eps, in.s_c, in.S, fold);
+    k.w = g.w;
+    k.fold_axis = g.fold_axis;
+    std::shared_ptr<TargetTable> tt = ctx_targets(ctx, p.ant_enu, in.ant, g, st);
+    hold.push_back(tt);
+    int best_f = 0;
+    for (int f = 0; f < n_freq; ++f) {
+        SnapJob j;
+        j.plan = plan_snapshot(g, p.freq_hz[f]);
+        j.src = in.src;
+        j.n_src = n_src;
+        j.flux = in.flux + (size_t)f * n_src;
+        j.beam = in.beam ? in.beam + (size_t)f * n_src : nullptr;
+        j.out = vis_dev + 2 * (size_t)f * n_pairs;
+        j.tt = tt.get();
+        jobs.push_back(j);
+        if (p.freq_hz[f] > p.freq_hz[best_f]) best_f = f;
+    }
+    if (top) *top = jobs[jobs.size() - n_freq + best_f].plan;
+    return k;
+}
+
+// Runs jobs of one (dim, precision, w) in groups whose workspace fits the
+// context's chunk size; returns the algorithmic bytes of the grid stages.
+double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, const NufftGroupKey &k,
+                    StageTimer *tm) {
+    hipStream_t st = slot.stream;
+    const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
+    std::vector<size_t> each(jobs.size());
+    for (size_t i = 0; i < jobs.size(); ++i)
+        each[i] = nufft_workspace_bytes(std::vector<SnapJob>{jobs[i]}, k.dim, k.prec, k.w);
+    double bytes = 0.0;
+    size_t i0 = 0;
+    while (i0 < jobs.size()) {
+        size_t i1 = i0 + 1, tot = each[i0];
+        while (i1 < jobs.size() && tot + each[i1] <= cap) tot += each[i1++];
+        std::vector<SnapJob> part(jobs.begin() + i0, jobs.begin() + i1);
+        if (i0 > 0) FV_HIP(hipStreamSynchronize(st));  // the arena is reused
+        bytes += nufft_execute(part, k.dim, k.prec, k.w, slot.arena, ctx->cache, st, tm);
+        i0 = i1;
+    }
+    return bytes;
+}
+
+// Direct-sum methods of one problem.
+void run_direct(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int dim,
+                int prec, StageTimer *tm) {
+    const unsigned method = p.flags & FV_METHOD_MASK;
+    hipStream_t st = slot.stream;
+    if (method == FV_METHOD_DIRECT) {
+        launch_direct(in.ant, p.n_ant, in.src, p.n_src, p.freq_hz, p.n_freq, in.flux, in.beam, dim, prec, vis_dev,
+                      st, tm);
+    } else {
+        const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
+        const size_t need = zz_work_bytes(p.n_ant, p.n_src, prec, cap);
+        slot.arena.ensure(need);
+        slot.arena.reset();
+        void *work = slot.arena.take(need);
+        launch_zz(in.ant, p.n_ant, in.src, p.n_src, p.freq_hz, p.n_freq, in.flux, in.beam, dim, prec, vis_dev, work,
+                  cap, st, tm);
+    }
+}
+
+void fill_report(StageTimer &tm, fv_report &r) {
+    tm.collect();
+    for (int i = 0; i < FV_NSTAGE; ++i) {
+        r.t_stage_ms[i] = tm.ms[i];
+        r.stage_bytes[i] = tm.bytes[i];
+        r.stage_launches[i] = tm.launches[i];
+    }
+}
+
 // Everything the device path needs once the inputs are on the device and the
 // planning scalars (antenna positions, frequencies, source box) on the host.
 void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevInputs &in, double *vis_dev,
@@ -306,71 +389,26 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
     r.src_pairs = (double)n_src * (double)n_pairs * (double)n_freq;
     if (n_src == 0) {
         launch_zero_c128(vis_dev, n_pairs * n_freq, st);
-    } else if (method == FV_METHOD_DIRECT) {
-        launch_direct(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, prec, vis_dev, st,
-                      &tm);
-    } else if (method == FV_METHOD_MFMA) {
-        const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
-        const size_t need = zz_work_bytes(n_ant, n_src, prec, cap);
-        slot.arena.ensure(need);
-        slot.arena.reset();
-        void *work = slot.arena.take(need);
-        launch_zz(in.ant, n_ant, in.src, n_src, p->freq_hz, n_freq, in.flux, in.beam, dim, prec, vis_dev, work, cap, st,
-                  &tm);
+    } else if (method != FV_METHOD_NUFFT) {
+        run_direct(ctx, slot, *p, in, vis_dev, dim, prec, &tm);
     } else {
-        const bool fold = !(p->flags & FV_NO_FOLD);
-        GeomPlan g = ctx_geometry(ctx, p->ant_enu, n_ant, dim, p->eps, in.s_c, in.S, fold);
-        std::shared_ptr<TargetTable> tt_hold = ctx_targets(ctx, p->ant_enu, in.ant, g, st);
-        const TargetTable *tt = tt_hold.get();
         std::vector<SnapJob> jobs;
-        jobs.reserve(n_freq);
-        for (int f = 0; f < n_freq; ++f) {
-            SnapJob j;
-            j.plan = plan_snapshot(g, p->freq_hz[f]);
-            j.src = in.src;
-            j.n_src = n_src;
-            j.flux = in.flux + (size_t)f * n_src;
-            j.beam = in.beam ? in.beam + (size_t)f * n_src : nullptr;
-            j.out = vis_dev + 2 * (size_t)f * n_pairs;
-            j.tt = tt;
-            jobs.push_back(j);
-        }
-        // run in chunks of frequencies whose workspace fits the budget share
-        const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
-        std::vector<size_t> each(jobs.size());
-        for (size_t i = 0; i < jobs.size(); ++i)
-            each[i] = nufft_workspace_bytes(std::vector<SnapJob>{jobs[i]}, dim, prec, g.w);
-        size_t i0 = 0;
-        int best_f = 0;
-        for (int f = 1; f < n_freq; ++f)
-            if (p->freq_hz[f] > p->freq_hz[best_f]) best_f = f;
-        while (i0 < jobs.size()) {
-            size_t i1 = i0 + 1, tot = each[i0];
-            while (i1 < jobs.size() && tot + each[i1] <= cap) tot += each[i1++];
-            std::vector<SnapJob> part(jobs.begin() + i0, jobs.begin() + i1);
-            if (i0 > 0) FV_HIP(hipStreamSynchronize(st));  // the arena is reused
-            r.model_bytes += nufft_execute(part, dim, prec, g.w, slot.arena, ctx->cache, st, &tm);
-            i0 = i1;
-        }
-        const SnapPlan top = jobs.empty() ? SnapPlan() : jobs[best_f].plan;
-        r.w = g.w;
-        r.fold_axis = g.fold_axis;
+        std::vector<std::shared_ptr<TargetTable>> hold;
+        SnapPlan top;
+        NufftGroupKey k = append_jobs(ctx, *p, in, vis_dev, st, jobs, hold, &top);
+        r.model_bytes = execute_jobs(ctx, slot, jobs, k, &tm);
+        r.w = k.w;
+        r.fold_axis = k.fold_axis;
         for (int a = 0; a < 3; ++a) {
             r.n1[a] = top.n1[a];
             r.n2[a] = top.n2[a];
         }
     }
     FV_HIP(hipGetLastError());
-    tm.collect();
-    for (int i = 0; i < FV_NSTAGE; ++i) {
-        r.t_stage_ms[i] = tm.ms[i];
-        r.stage_bytes[i] = tm.bytes[i];
-        r.stage_launches[i] = tm.launches[i];
-    }
+    fill_report(tm, r);
     if (rep) *rep = r;
 }
 
-// Upload a host problem into the slot's input arena.
 DevInputs upload(Slot &slot, const fv_problem *p, double *s_c, double *S) {
     const int n_ant = p->n_ant, n_src = p->n_src, n_freq = p->n_freq;
     const size_t b_ant = sizeof(double) * 3 * n_ant, b_src = sizeof(double) * 3 * (size_t)n_src;
