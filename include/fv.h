@@ -70,6 +70,13 @@ typedef enum {
 #define FV_NO_FOLD         0x100u /* do not reflect targets into a half-space */
 #define FV_TIMING          0x200u /* record HIP events around every stage launch (the call then
                                      waits for its own work and fills the t_stage_ms fields) */
+#define FV_AUTOTUNE        0x400u /* NUFFT: when this problem class (dimension, precision, grid and
+                                     snapshot-count buckets) has no tuned FFT launch shape yet, time
+                                     the candidates on this call's grids first and keep the fastest
+                                     (in the context, and in the file set by fv_set_tune_cache) */
+#define FV_GRAPH           0x800u /* NUFFT: capture the call's launch sequence as a HIP graph and
+                                     replay it on later calls with the same sizes and workspace;
+                                     needs a non-null stream; per-stage timing is then not recorded */
 
 /* stage indices of fv_report.t_stage_ms / stage_bytes / stage_launches */
 #define FV_STAGE_SORT      0      /* key, count, scan and scatter of the source records */
@@ -143,6 +150,12 @@ fv_status fv_submit(fv_ctx *ctx, const fv_problem *p, double *vis, uint64_t *tic
  * with t_total_ms = submit -> completion latency. */
 fv_status fv_wait(fv_ctx *ctx, uint64_t ticket, double timeout_s, fv_report *rep);
 fv_status fv_server_stop(fv_ctx *ctx);
+
+/* Autotuner cache file (JSON object: class key -> launch shape).  Entries in
+ * the file are loaded now; new entries found by FV_AUTOTUNE calls are written
+ * back.  path NULL or "" keeps the cache in memory only.  An unreadable or
+ * missing file is not an error. */
+fv_status fv_set_tune_cache(fv_ctx *ctx, const char *path);
 
 /* Diagnostic entry point for stage-by-stage checks of the NUFFT path
  * (section 2.2 steps 1-3) on one frequency `f` of a host problem.

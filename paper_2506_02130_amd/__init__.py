@@ -28,10 +28,12 @@ PREC_AUTO, PREC_FP32, PREC_FP64 = 0x0, 0x4, 0x8
 METHOD_NUFFT, METHOD_DIRECT, METHOD_MFMA = 0x00, 0x10, 0x20
 NO_FOLD = 0x100
 TIMING = 0x200
+AUTOTUNE = 0x400
+GRAPH = 0x800
 STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
-               "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_debug_stages")
+               "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages")
 
 
 class FvError(RuntimeError):
@@ -83,8 +85,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, P(Report)]
     lib.fv_server_stop.argtypes = [vp]
     lib.fv_debug_stages.argtypes = [vp, P(Problem), ctypes.c_int, dp, vp, ctypes.c_size_t, vp, ctypes.c_size_t]
+    lib.fv_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
-                 "fv_submit", "fv_wait", "fv_server_stop", "fv_debug_stages"):
+                 "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -186,6 +189,10 @@ class Context:
                                     ctypes.byref(rep)))
         self.last_report = rep.as_dict()
         return self.last_report
+
+    def set_tune_cache(self, path: Optional[str]):
+        """Autotuner cache file (JSON); None keeps the cache in memory only."""
+        _check(_lib.fv_set_tune_cache(self._h, None if path is None else str(path).encode()))
 
     # ------------------------------------------------------------------ batch API
     def simulate_batch(self, problems: Sequence[HostProblem]) -> list:

@@ -27,7 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-u
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
 HOST_ONLY_FLAGS = ["-ffp-contract=off"]
 
-SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp", "server.cpp", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip",
+SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp", "server.cpp", "tune.cpp", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip",
            "nufft_f64_2d.hip", "nufft_f64_3d.hip", "direct.hip", "zz.hip"]
 
 

@@ -30,6 +30,7 @@ struct Slot {
     Arena arena;   // NUFFT workspace
     Arena inputs;  // uploaded inputs and the device output
     StageTimer timer;
+    GraphCache graphs;  // launch graphs captured on this slot's workspace
     ~Slot();
 };
 
@@ -48,6 +49,7 @@ struct fv_ctx {
     std::list<std::shared_ptr<fv::TargetTable>> targets;
     double *scalar_buf = nullptr;
     fv::PinnedBuf plan_pin;  // host staging of the planning scalars of fv_simulate_dev
+    fv::TuneCache tunes;     // autotuned FFT launch shapes
     fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
     double *scalars(hipStream_t) {
         if (!scalar_buf) FV_HIP(hipMalloc((void **)&scalar_buf, (8 + 7 * fv::kSrcCheckBlocks) * sizeof(double)));
@@ -70,8 +72,9 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
 // Kernel family of a group of NUFFT jobs.
 struct NufftGroupKey {
     int dim = 2, prec = 32, w = 8, fold_axis = -1;
+    unsigned flags = 0;  // FV_AUTOTUNE | FV_GRAPH of the problem
     bool operator<(const NufftGroupKey &o) const {
-        return std::tie(dim, prec, w) < std::tie(o.dim, o.prec, o.w);
+        return std::tie(dim, prec, w, flags) < std::tie(o.dim, o.prec, o.w, o.flags);
     }
 };
 NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in, double *vis_dev, hipStream_t st,

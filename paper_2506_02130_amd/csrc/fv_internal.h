@@ -9,6 +9,8 @@
 #include <string>
 #include <utility>
 #include <vector>
+#include <mutex>
+#include <list>
 
 #include "../../include/fv.h"
 
@@ -195,11 +197,51 @@ struct SnapJob {
     const TargetTable *tt = nullptr;
 };
 
+// Launch shape of the FFT passes: transforms per workgroup and threads per
+// workgroup.  Defaults were measured on the 350-antenna workload;
+// FV_FFT_ROWS, FV_FFT_MAX_LINES, FV_FFT_TPB1 and FV_FFT_TPBM override them,
+// and the autotuner searches them per problem class.
+struct Tuning {
+    int rows = 1;    // rows per workgroup of the x pass
+    int lines = 2;   // columns per workgroup of the other passes
+    int tpb1 = 0;    // threads of the x pass (0: by line length)
+    int tpbm = 256;  // threads of the other passes
+    double fft_ms = 0.0;  // FFT time measured by the autotuner (0: not tuned)
+    static Tuning defaults();
+    int tpb(int line_len, bool multi) const;
+};
+
+// Autotuned launch shapes per problem class, optionally persisted as JSON.
+struct TuneCache {
+    std::mutex mu;
+    std::map<std::string, Tuning> entries;
+    std::string path;  // empty: in memory only
+    bool find(const std::string &key, Tuning *t);
+    void put(const std::string &key, const Tuning &t);
+    void load(const std::string &file);
+};
+
+// Instantiated graphs of whole launch sequences, keyed by every launch
+// argument and dimension they bake in.
+struct GraphCache {
+    std::list<std::pair<uint64_t, hipGraphExec_t>> entries;  // most recent at the back
+    hipGraphExec_t find(uint64_t key);
+    void put(uint64_t key, hipGraphExec_t g);
+    void release();
+};
+
+struct ExecOpts {
+    bool autotune = false;   // search the launch shape when the class is not cached
+    bool graph = false;      // capture / replay the launch sequence as a HIP graph
+    TuneCache *tunes = nullptr;
+    GraphCache *graphs = nullptr;
+};
+
 // Enqueue the whole type-3 pipeline for jobs that share (dim, precision, w).
 // Allocates its workspace from `arena` (which must be idle); returns the
 // algorithmic HBM bytes of the grid stages.
 double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena,
-                     DevCache &cache, hipStream_t s, StageTimer *timer = nullptr);
+                     DevCache &cache, hipStream_t s, StageTimer *timer = nullptr, const ExecOpts *opts = nullptr);
 // Workspace bytes nufft_execute would take for these jobs.
 size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w);
 

@@ -14,7 +14,7 @@ PipeFn pick(int dim, int prec_bits, int w) {
 }  // namespace
 
 size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w) {
-    Layout L = make_layout(jobs, dim, prec_bits, w);
+    Layout L = make_layout(jobs, dim, prec_bits, w, Tuning::defaults());
     return layout_bytes(L, dim, prec_bits, (int)jobs.size());
 }
 
@@ -26,12 +26,12 @@ struct Prepared {
 };
 
 Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
-                 hipStream_t st) {
+                 hipStream_t st, const Tuning &tune) {
     if (w < kMinW || w > kMaxW) fail(FV_EUNSUPPORTED, "kernel width out of range");
     Prepared P;
     P.fn = pick(dim, prec_bits, w);
     if (!P.fn) fail(FV_EUNSUPPORTED, "no kernel instance for this width");
-    P.L = make_layout(jobs, dim, prec_bits, w);
+    P.L = make_layout(jobs, dim, prec_bits, w, tune);
     Layout &L = P.L;
     const double *qn = cache.quad(w, st);
     for (size_t i = 0; i < jobs.size(); ++i) {
@@ -85,18 +85,141 @@ void fetch_c128(const void *dev, long long n, int prec_bits, double *host, hipSt
 }
 }  // namespace
 
+// Class of a launch group for the autotuner: dimension, precision and the
+// power-of-two buckets of the largest line length per axis and of the
+// snapshot count.
+std::string tune_key(const std::vector<SnapJob> &jobs, int dim, int prec_bits) {
+    auto bucket = [](long long v) {
+        long long b = 1;
+        while (b < v) b <<= 1;
+        return b;
+    };
+    int n1max[3] = {1, 1, 1};
+    for (auto &j : jobs)
+        for (int a = 0; a < dim; ++a) n1max[a] = std::max(n1max[a], j.plan.n1[a]);
+    std::string k = "d" + std::to_string(dim) + "_p" + std::to_string(prec_bits) + "_n";
+    for (int a = 0; a < dim; ++a) k += (a ? "x" : "") + std::to_string(bucket(n1max[a]));
+    return k + "_s" + std::to_string(bucket((long long)jobs.size()));
+}
+
+namespace {
+// Times the FFT passes (stage 2 only, on whatever the grid holds) for each
+// candidate launch shape and returns the fastest.
+Tuning autotune(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
+                hipStream_t st) {
+    hipEvent_t a, b;
+    FV_HIP(hipEventCreate(&a));
+    FV_HIP(hipEventCreate(&b));
+    Tuning best = Tuning::defaults();
+    best.fft_ms = 1e30;
+    try {
+        for (int rows : {1, 2})
+            for (int lines : {1, 2, 4})
+                for (int tpb1 : {256, 512})
+                    for (int tpbm : {128, 256, 512}) {
+                        Tuning t;
+                        t.rows = rows;
+                        t.lines = lines;
+                        t.tpb1 = tpb1;
+                        t.tpbm = tpbm;
+                        Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st, t);
+                        P.fn(P.L, P.B, (int)jobs.size(), st, 2, nullptr);  // warm
+                        float ms = 1e30f;
+                        for (int r = 0; r < 2; ++r) {
+                            FV_HIP(hipEventRecord(a, st));
+                            P.fn(P.L, P.B, (int)jobs.size(), st, 2, nullptr);
+                            FV_HIP(hipEventRecord(b, st));
+                            FV_HIP(hipEventSynchronize(b));
+                            float x = 0;
+                            FV_HIP(hipEventElapsedTime(&x, a, b));
+                            ms = std::min(ms, x);
+                        }
+                        if (ms < best.fft_ms) {
+                            best = t;
+                            best.fft_ms = ms;
+                        }
+                    }
+    } catch (...) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        throw;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+// Everything a captured launch sequence bakes in: kernel arguments (buffer
+// addresses, sizes) and launch dimensions.  The per-snapshot table itself is
+// device memory, uploaded before every replay.
+uint64_t graph_key(const Prepared &P, int n, int dim, int prec_bits, int w) {
+    const Layout &L = P.L;
+    uint64_t h = 1469598103934665603ull;
+    for (long long v : {(long long)n, (long long)dim, (long long)prec_bits, (long long)w, L.max_wg[0], L.max_wg[1],
+                        L.max_wg[2], L.max_tiles, L.max_src, L.max_tgt, L.max_ipsi, L.total_bins,
+                        (long long)L.orders.size(), L.max_order_src, L.order_counts, (long long)L.tpb[0],
+                        (long long)L.tpb[1], (long long)L.tpb[2], (long long)L.fft_lds[0], (long long)L.fft_lds[1],
+                        (long long)L.fft_lds[2]})
+        h = mix(h, (uint64_t)v);
+    for (const void *p : {(const void *)P.B.snaps, (const void *)P.B.bins, (const void *)P.B.rank,
+                          (const void *)P.B.recs, (const void *)P.B.ipsi, (const void *)P.B.grid,
+                          (const void *)P.B.perm, (const void *)P.B.order_counts, (const void *)P.B.src_ord,
+                          (const void *)P.B.orders})
+        h = mix(h, (uint64_t)(uintptr_t)p);
+    return h;
+}
+}  // namespace
+
 double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
-                     hipStream_t st, StageTimer *timer) {
+                     hipStream_t st, StageTimer *timer, const ExecOpts *opts) {
     if (jobs.empty()) return 0.0;
-    Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st);
-    P.fn(P.L, P.B, (int)jobs.size(), st, 7, timer);
+    Tuning tune = Tuning::defaults();
+    if (opts && opts->tunes) {
+        const std::string key = tune_key(jobs, dim, prec_bits);
+        if (!opts->tunes->find(key, &tune) && opts->autotune) {
+            tune = autotune(jobs, dim, prec_bits, w, arena, cache, st);
+            opts->tunes->put(key, tune);
+        }
+    }
+    Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st, tune);
+    const int n = (int)jobs.size();
+    // graphs need a capturable (non-null) stream; per-stage timing stays eager
+    const bool graph = opts && opts->graph && opts->graphs && st != nullptr && !(timer && timer->on);
+    if (!graph) {
+        P.fn(P.L, P.B, n, st, 7, timer);
+        return P.L.model_bytes;
+    }
+    const uint64_t key = graph_key(P, n, dim, prec_bits, w);
+    hipGraphExec_t ex = opts->graphs->find(key);
+    if (!ex) {
+        hipGraph_t g = nullptr;
+        FV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+            P.fn(P.L, P.B, n, st, 7, nullptr);
+        } catch (...) {
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        FV_HIP(hipStreamEndCapture(st, &g));
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        FV_HIP(e);
+        opts->graphs->put(key, ex);
+    }
+    FV_HIP(hipGraphLaunch(ex, st));
     return P.L.model_bytes;
 }
 
 void nufft_debug(const SnapJob &job, int dim, int prec_bits, int w, Arena &arena, DevCache &cache, double *spread,
                  double *fftout, hipStream_t st) {
     std::vector<SnapJob> jobs{job};
-    Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st);
+    Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st, Tuning::defaults());
     const SnapDev &d = P.L.snaps[0];
     const size_t csz = prec_bits == 32 ? 8 : 16;
     P.fn(P.L, P.B, 1, st, 1, nullptr);

@@ -994,41 +994,9 @@ struct Bufs {
     OrderGroup *orders = nullptr;                  // device copy of Layout::orders
 };
 
-// Upper bound on the lines one FFT workgroup transforms together (tunable
-// through FV_FFT_MAX_LINES).
-inline int fft_max_lines() {
-    static int v = [] {
-        const char *e = std::getenv("FV_FFT_MAX_LINES");
-        int x = e ? std::atoi(e) : 2;
-        return x < 1 ? 1 : (x > 64 ? 64 : x);
-    }();
-    return v;
-}
-
-inline int fft_max_rows() {
-    static int v = [] {
-        const char *e = std::getenv("FV_FFT_ROWS");
-        int x = e ? std::atoi(e) : 1;
-        return x < 1 ? 1 : (x > 16 ? 16 : x);
-    }();
-    return v;
-}
-
-// Threads of an FFT workgroup: single-line passes by line length,
-// multi-line passes 256 (measured on the 350-antenna workload).
 inline int env_int(const char *name, int dflt) {
     const char *e = std::getenv(name);
     return e ? std::atoi(e) : dflt;
-}
-
-// Tunables (environment, read once): FV_FFT_TPB1 threads of single-line
-// passes (0 = by line length), FV_FFT_TPBM threads of multi-line passes.
-inline int fft_tpb_for(int L, bool multi) {
-    static const int t1 = env_int("FV_FFT_TPB1", 0), tm = env_int("FV_FFT_TPBM", 256);
-    int t = multi ? tm : t1;
-    if (t != 128 && t != 256 && t != 512 && t != 1024) t = 0;
-    if (t == 0) t = L <= 2048 ? 256 : (L <= 4096 ? 512 : 1024);
-    return t;
 }
 
 inline size_t rec_bytes(int dim, int prec_bits) {
@@ -1036,7 +1004,7 @@ inline size_t rec_bytes(int dim, int prec_bits) {
     return dim == 2 ? sizeof(Rec<double, 2>) : sizeof(Rec<double, 3>);
 }
 
-inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w) {
+inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, const Tuning &tune) {
     Layout L;
     const size_t csz = prec_bits == 32 ? 8 : 16;
     const int T[3] = {dim == 2 ? TileShape<2>::X : TileShape<3>::X, dim == 2 ? TileShape<2>::Y : TileShape<3>::Y,
@@ -1048,7 +1016,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
             lmax = std::max(lmax, j.plan.n1[a]);
             nmax = std::max(nmax, j.plan.n2[a]);
         }
-        L.tpb[a] = fft_tpb_for(lmax, a > 0);
+        L.tpb[a] = tune.tpb(lmax, a > 0);
         if ((size_t)(2 * cline_pad(lmax) + fft_tw_entries(nmax)) * csz > 160u * 1024)
             fail(FV_EUNSUPPORTED, "FFT line of " + std::to_string(nmax) + " points exceeds the LDS transform");
     }
@@ -1109,7 +1077,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
             // each line held as two transforms within 64 KB of LDS
             const long long bylds = (65536LL - (long long)fft_tw_entries(p.n2[a]) * csz) /
                                     (2LL * cline_pad(p.n1[a]) * csz);
-            const long long lim = F > 1 ? (long long)fft_max_lines() : (long long)fft_max_rows();
+            const long long lim = F > 1 ? (long long)tune.lines : (long long)tune.rows;
             const int cx = (int)std::max(1LL, std::min({F > 1 ? F : Sl, bylds, lim}));
             const long long nwg = F > 1 ? Sl * ((F + cx - 1) / cx) : (Sl + cx - 1) / cx;
             d.cx[a] = cx;

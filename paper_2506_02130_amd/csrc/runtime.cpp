@@ -164,6 +164,7 @@ static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603u
 }
 
 Slot::~Slot() {
+    graphs.release();
     arena.host.release();
     inputs.host.release();
     arena.release();
@@ -293,6 +294,7 @@ NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in,
     const long long n_pairs = (long long)p.n_ant * (p.n_ant + 1) / 2;
     NufftGroupKey k;
     k.dim = choose_dim(p.ant_enu, p.n_ant, p.eps, p.freq_hz, n_freq, p.flags);
+    k.flags = p.flags & (FV_AUTOTUNE | FV_GRAPH);
     k.prec = choose_prec(p.eps, p.flags);
     const bool fold = !(p.flags & FV_NO_FOLD);
     GeomPlan g = ctx_geometry(ctx, p.ant_enu, p.n_ant, k.dim, p.eps, in.s_c, in.S, fold);
@@ -322,6 +324,11 @@ NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in,
 double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, const NufftGroupKey &k,
                     StageTimer *tm) {
     hipStream_t st = slot.stream;
+    ExecOpts opts;
+    opts.autotune = (k.flags & FV_AUTOTUNE) != 0;
+    opts.graph = (k.flags & FV_GRAPH) != 0;
+    opts.tunes = &ctx->tunes;
+    opts.graphs = &slot.graphs;
     const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
     std::vector<size_t> each(jobs.size());
     for (size_t i = 0; i < jobs.size(); ++i)
@@ -333,7 +340,7 @@ double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, c
         while (i1 < jobs.size() && tot + each[i1] <= cap) tot += each[i1++];
         std::vector<SnapJob> part(jobs.begin() + i0, jobs.begin() + i1);
         if (i0 > 0) FV_HIP(hipStreamSynchronize(st));  // the arena is reused
-        bytes += nufft_execute(part, k.dim, k.prec, k.w, slot.arena, ctx->cache, st, tm);
+        bytes += nufft_execute(part, k.dim, k.prec, k.w, slot.arena, ctx->cache, st, tm, &opts);
         i0 = i1;
     }
     return bytes;
@@ -596,6 +603,14 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     }
     slot.stream = keep;
     if (rep) rep->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return FV_OK;
+    FV_GUARD_END
+}
+
+fv_status fv_set_tune_cache(fv_ctx *ctx, const char *path) {
+    FV_GUARD_BEGIN
+    if (!ctx) fv::fail(FV_EINVAL, "null context");
+    ctx->tunes.load(path ? std::string(path) : std::string());
     return FV_OK;
     FV_GUARD_END
 }
