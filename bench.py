@@ -66,6 +66,56 @@ def _traffic_from_profiles(kernel: str, units: float):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def serving_leg(fv, synth, np, n_req: int) -> dict:
+    """The serving mix: the first n_req requests of the seeded request stream
+    (hex arrays of 37-350 antennas, 1e3-1e6 sources, 1-64 frequencies, eps in
+    {1e-4, 1e-6, 1e-10}), host buffers.  The plain path runs them one after
+    the other; the server then replays them with Poisson arrivals at 0.7 of
+    the plain path's measured capacity.  Latency = arrival (submit) to
+    completion."""
+    reqs = synth.config5_requests(n_req)
+    probs = [r.materialize() for r in reqs]
+    hps = [fv.HostProblem.of(q) for q in probs]
+    pairs = sum(float(q.n_src) * q.n_pairs * q.n_freq for q in probs)
+    with fv.Context(0) as c:
+        for h in hps[:4]:
+            c.simulate_problem(h)  # warm: tables and code objects
+        t0 = time.perf_counter()
+        plain_lat = []
+        for h in hps:
+            ta = time.perf_counter()
+            c.simulate_problem(h)
+            plain_lat.append((time.perf_counter() - ta) * 1e3)
+        t_plain = time.perf_counter() - t0
+        rate = 0.7 * len(hps) / t_plain
+        rng = np.random.default_rng(np.random.PCG64(2506021305))
+        arrive = np.cumsum(rng.exponential(1.0 / rate, len(hps)))
+        arrive -= arrive[0]
+        outs = [np.empty((q.n_freq, q.n_pairs, 2)) for q in probs]
+        c.server_start(4)
+        tickets = []
+        ts = time.perf_counter()
+        for h, o, at in zip(hps, outs, arrive):
+            dt = ts + at - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(c.submit(h, o))
+        lat = []
+        for t in tickets:
+            st, rep = c.wait(t)
+            if st != 0:
+                raise RuntimeError(f"serving request failed with status {st}")
+            lat.append(rep["t_total_ms"])
+        t_serve = time.perf_counter() - ts
+        c.server_stop()
+    return {"requests": len(hps), "slots": 4, "arrival_rate_hz": rate, "pairs": pairs,
+            "latency_ms": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99)},
+            "pairs_per_s": pairs / t_serve,
+            "plain": {"pairs_per_s": pairs / t_plain,
+                      "latency_ms": {"p50": _pct(plain_lat, 0.5), "p99": _pct(plain_lat, 0.99)}},
+            "note": "host buffers (PCIe included); latency from submit to completion"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +130,7 @@ def main():
                     help="after the steps, one device copy of this many MiB (reference for byte counters)")
     ap.add_argument("--no-autotune", action="store_true", help="default FFT launch shapes instead of tuned ones")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving mix leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -240,6 +291,7 @@ def main():
             "gpu_stage_ms": sum(rb["t_stage_ms"]), "gpu_pairs_per_s": rb["src_pairs"] / (sum(rb["t_stage_ms"]) * 1e-3)}
         print(f"bench: graph replay {g_ms:.3f} ms/step; batch of {len(probs)} x {probs[0].n_freq} snapshots "
               f"{tb * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        extras["serving"] = serving_leg(fv, synth, np, args.serve_requests)
 
     line = {
         "metric": METRIC,

@@ -86,6 +86,8 @@ void run_direct(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &i
                 int prec, StageTimer *tm);
 void fill_report(StageTimer &tm, fv_report &r);
 void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv_report *rep);
+void server_free(Server *s);  // stops the workers (cancelling queued requests) and frees
+size_t request_footprint(fv_ctx *ctx, const fv_problem &p);
 void simulate_batch(fv_ctx *ctx, Slot &slot, int n, const fv_problem *ps, double *const *vis, fv_report *rep);
 const char *last_error_cstr();
 void set_last_error(const std::string &msg);

@@ -139,6 +139,7 @@ struct Arena {
 // Device tables reused across calls: twiddles per (n, precision), quadrature
 // tables per w.
 struct DevCache {
+    std::mutex mu;  // the tables are shared by every slot of a context
     std::map<std::pair<int, int>, void *> twiddles;
     std::map<int, double *> qnodes;
     std::map<int, int *> drevs;

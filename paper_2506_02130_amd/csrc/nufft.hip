@@ -242,7 +242,11 @@ void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, con
     FV_HIP(hipGetLastError());
 }
 
+// Each table is built once, on the stream of the first call that needs it;
+// the build is waited for before the table is published, since later users
+// may run on other streams.
 const void *DevCache::twiddle(int n, int prec_bits, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(mu);
     auto key = std::make_pair(n, prec_bits);
     auto it = twiddles.find(key);
     if (it != twiddles.end()) return it->second;
@@ -254,22 +258,26 @@ const void *DevCache::twiddle(int n, int prec_bits, hipStream_t st) {
     else
         hipLaunchKernelGGL(k_twiddle<double>, dim3((n + 255) / 256), dim3(256), 0, st, n, (double2 *)p);
     FV_HIP(hipGetLastError());
+    FV_HIP(hipStreamSynchronize(st));
     twiddles[key] = p;
     return p;
 }
 
 const int *DevCache::digit_reversal(int n, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(mu);
     auto it = drevs.find(n);
     if (it != drevs.end()) return it->second;
     int *p = nullptr;
     FV_HIP(hipMalloc(&p, (size_t)n * sizeof(int)));
     hipLaunchKernelGGL(k_digrev, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p);
     FV_HIP(hipGetLastError());
+    FV_HIP(hipStreamSynchronize(st));
     drevs[n] = p;
     return p;
 }
 
 const double *DevCache::quad(int w, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(mu);
     auto it = qnodes.find(w);
     if (it != qnodes.end()) return it->second;
     double host[2 * kQuadHalf];
@@ -283,6 +291,7 @@ const double *DevCache::quad(int w, hipStream_t st) {
 }
 
 void DevCache::release() {
+    std::lock_guard<std::mutex> lk(mu);
     for (auto &kv : twiddles) (void)hipFree(kv.second);
     for (auto &kv : drevs) (void)hipFree(kv.second);
     drevs.clear();

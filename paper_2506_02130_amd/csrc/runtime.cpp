@@ -177,6 +177,8 @@ Slot::~Slot() {
 using namespace fv;
 
 fv_ctx::~fv_ctx() {
+    fv::server_free(server);
+    server = nullptr;
     targets.clear();
     cache.release();
     plan_pin.release();
@@ -250,6 +252,8 @@ std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, co
     FV_HIP(hipMalloc((void **)&t->tphi, n * g.dim * sizeof(double)));
     const double *qn = ctx->cache.quad(g.w, st);
     build_targets(ant_dev, g.n_ant, g.dim, g.fold_axis, g.b_c, g.B, g.w, qn, *t, st);
+    // built once per array; later users may run on other streams
+    FV_HIP(hipStreamSynchronize(st));
     ctx->targets.push_back(t);
     return t;
 }
