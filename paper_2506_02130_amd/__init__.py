@@ -178,8 +178,14 @@ class Context:
         if beam is not None and not (beam.is_cuda and beam.dtype == torch.float64 and beam.is_contiguous()):
             raise ValueError("beam must be a contiguous float64 device tensor")
         n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
-        if vis.numel() != 2 * n_freq * n_ant * (n_ant + 1) // 2:
-            raise ValueError("vis has the wrong size")
+        # the C ABI takes bare device pointers: every size is checked here
+        sizes = (("ant_enu", ant_enu, 3 * n_ant), ("src_lmn", src_lmn, 3 * n_src), ("freq_hz", freq_hz, n_freq),
+                 ("flux", flux, n_freq * n_src), ("vis", vis, 2 * n_freq * n_ant * (n_ant + 1) // 2))
+        if beam is not None:
+            sizes += (("beam", beam, n_freq * n_src),)
+        for name, t, want in sizes:
+            if t.numel() != want:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {want}")
         st = stream if stream is not None else torch.cuda.current_stream()
         c = Problem(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
                     freq_hz.data_ptr(), flux.data_ptr() if n_src else None,

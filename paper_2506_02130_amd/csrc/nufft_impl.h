@@ -1077,7 +1077,10 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
             // each line held as two transforms within 64 KB of LDS
             const long long bylds = (65536LL - (long long)fft_tw_entries(p.n2[a]) * csz) /
                                     (2LL * cline_pad(p.n1[a]) * csz);
-            const long long lim = F > 1 ? (long long)tune.lines : (long long)tune.rows;
+            // short lines take more lines per workgroup so that every thread
+            // has butterflies (about 4 TPB points per workgroup)
+            const long long fill = 4LL * L.tpb[a] / (2LL * p.n1[a]);
+            const long long lim = std::max(fill, F > 1 ? (long long)tune.lines : (long long)tune.rows);
             const int cx = (int)std::max(1LL, std::min({F > 1 ? F : Sl, bylds, lim}));
             const long long nwg = F > 1 ? Sl * ((F + cx - 1) / cx) : (Sl + cx - 1) / cx;
             d.cx[a] = cx;

@@ -151,6 +151,26 @@ def test_zz_agrees_with_vector_direct(gpu_lib, ctx):
     assert oracle.rel_l2(v2, v1) <= 2e-6
 
 
+def test_device_entry_rejects_wrong_tensor_sizes(gpu_lib, ctx):
+    # sizes are checked in the binding, before any device work: a beam that
+    # is not [n_freq][n_src] (for example a 0-d array made from None) must
+    # never reach the kernels
+    import torch
+    p = synth.small_problem(55, n_ant=6, n_src=50, n_freq=2)
+    dev = torch.device("cuda:0")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    vis = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+    good = [d(p.ant_enu), d(p.src_lmn), d(p.freq_hz), d(p.flux), d(p.beam)]
+    for k, bad in ((4, d(np.ascontiguousarray(None, dtype=np.float64))), (3, d(p.flux[:1])), (1, d(p.src_lmn[:-1])),
+                   (0, d(p.ant_enu[:, :2]))):
+        args = list(good)
+        args[k] = bad
+        with pytest.raises(ValueError):
+            ctx.simulate_dev(*args, vis, eps=1e-6)
+    ctx.simulate_dev(*good, vis, eps=1e-6)
+    torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------- edges
 def test_empty_sky_gives_exact_zero(gpu_lib, ctx):
     p = synth.small_problem(39, n_ant=6, n_src=0, n_freq=2)
