@@ -50,9 +50,11 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic_from_profiles(kernel: str, units: float):
-    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc summary
-    (profiles/traffic_*.json), only if it was taken on the current sources."""
+def _traffic_from_profiles(stage: str):
+    """HBM bytes per launch of a stage, from a committed pair of rocprofv3
+    --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the calibration copy
+    (profiles/traffic_c2.json), only if they were taken on the current kernel
+    sources."""
     path = os.path.join(ROOT, "profiles", "traffic_c2.json")
     if not os.path.exists(path):
         return None
@@ -62,7 +64,7 @@ def _traffic_from_profiles(kernel: str, units: float):
         return None
     if d.get("source_hash") != _kernel_source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel)
+    k = d.get("stages", {}).get(stage)
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -230,7 +232,7 @@ def main():
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": KERNEL_OF_STAGE.get(dom, dom), "stage": dom, "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": _traffic_from_profiles(KERNEL_OF_STAGE.get(dom, dom), 1.0),
+                "traffic": _traffic_from_profiles(dom),
                 "avg_launch_ms": per_launch_ms, "bytes_per_launch": per_launch_bytes}
     stages = {n: {"ms": round(stage_ms[n], 4), "launches": stage_launch[n],
                   "GBps": (stage_bytes[n] / max(stage_launch[n], 1)) / (stage_ms[n] / max(stage_launch[n], 1) * 1e-3)
