@@ -247,7 +247,11 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
 size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w);
 
 void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B,
-                   int w, const double *qn_dev, TargetTable &tt, hipStream_t s);
+                   int w, const double *qn_dev, const int *perm_dev, TargetTable &tt, hipStream_t s);
+// Spatial order of the pairs of an array: Morton order of the folded baselines
+// normalised to the target box (x, y interleaved; z as the least significant
+// part in 3-D).
+std::vector<int> target_order(const double *ant_host, const GeomPlan &g);
 // Device reduction over sources: out[0..5] = min/max of l, m, n; out[6] =
 // count of non-unit or non-finite directions.  out must be device memory.
 void launch_src_check(const double *src, int n_src, double *out7, hipStream_t s);

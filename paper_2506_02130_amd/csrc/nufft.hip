@@ -233,12 +233,12 @@ void nufft_debug(const SnapJob &job, int dim, int prec_bits, int w, Arena &arena
 
 // ---------------------------------------------------------------------------
 void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B, int w,
-                   const double *qn_dev, TargetTable &tt, hipStream_t st) {
+                   const double *qn_dev, const int *perm_dev, TargetTable &tt, hipStream_t st) {
     const long long n = (long long)n_ant * (n_ant + 1) / 2;
     const double xi0 = w * M_PI / (2.0 * kSigma);
     hipLaunchKernelGGL(k_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ant_dev, n_ant, n, dim,
                        fold_axis, make_double3(b_c[0], b_c[1], b_c[2]), make_double3(B[0], B[1], B[2]), xi0, qn_dev,
-                       tt.tb, tt.tidx, tt.tphi);
+                       perm_dev, tt.tb, tt.tidx, tt.tphi);
     FV_HIP(hipGetLastError());
 }
 

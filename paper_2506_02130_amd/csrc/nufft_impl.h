@@ -919,11 +919,16 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, in
 }
 
 // Target table of one array geometry.
+// Target t of the table is pair perm[t] (a spatial order of the folded
+// baselines, so that neighbouring lanes of the interpolation share grid cells),
+// or pair t when perm is null.
 __global__ __launch_bounds__(256) void k_targets(const double *ant, int n_ant, long long n_pairs, int dim,
                                                  int fold_axis, double3 b_c, double3 B, double xi0,
-                                                 const double *qn, double *tb, int *tidx, double *tphi) {
-    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n_pairs) return;
+                                                 const double *qn, const int *perm, double *tb, int *tidx,
+                                                 double *tphi) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_pairs) return;
+    const long long p = perm ? (long long)perm[t] : t;
     int i, j;
     pair_decode(p, n_ant, &i, &j);
     double b[3], f[3];
@@ -943,11 +948,11 @@ __global__ __launch_bounds__(256) void k_targets(const double *ant, int n_ant, l
     const double bc[3] = {b_c.x, b_c.y, b_c.z}, Bh[3] = {B.x, B.y, B.z};
     for (int a = 0; a < dim; ++a) {
         f[a] = flip ? -b[a] : b[a];
-        tb[(long long)a * n_pairs + p] = f[a];
+        tb[(long long)a * n_pairs + t] = f[a];
         const double xi = Bh[a] > 0 ? xi0 * (f[a] - bc[a]) / Bh[a] : 0.0;
-        tphi[(long long)a * n_pairs + p] = phihat_quad(xi, qn);
+        tphi[(long long)a * n_pairs + t] = phihat_quad(xi, qn);
     }
-    tidx[p] = (int)p | (flip ? (int)0x80000000 : 0);
+    tidx[t] = (int)p | (flip ? (int)0x80000000 : 0);
 }
 
 template <typename R>

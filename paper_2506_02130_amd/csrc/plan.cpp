@@ -216,4 +216,40 @@ void quad_table(int w, double *out) {
     }
 }
 
+static uint64_t spread_bits16(uint64_t v) {
+    v &= 0xffff;
+    v = (v | (v << 8)) & 0x00ff00ffull;
+    v = (v | (v << 4)) & 0x0f0f0f0full;
+    v = (v | (v << 2)) & 0x33333333ull;
+    v = (v | (v << 1)) & 0x55555555ull;
+    return v;
+}
+
+std::vector<int> target_order(const double *ant, const GeomPlan &g) {
+    const int n_ant = g.n_ant, dim = g.dim;
+    const long long n = g.n_pairs;
+    std::vector<std::pair<uint64_t, int>> key((size_t)n);
+    auto q = [](double x, double lo, double half, int bits) {
+        const double u = half > 0 ? (x - lo) / (2.0 * half) : 0.5;
+        const double m = (double)((1u << bits) - 1);
+        return (uint64_t)std::min(m, std::max(0.0, std::floor(u * m)));
+    };
+    long long p = 0;
+    for (int i = 0; i < n_ant; ++i)
+        for (int j = i; j < n_ant; ++j, ++p) {
+            double b[3], f[3];
+            bool fl;
+            for (int a = 0; a < 3; ++a) b[a] = ant[3 * (size_t)i + a] - ant[3 * (size_t)j + a];
+            fold_baseline(b, dim, g.fold_axis, f, &fl);
+            uint64_t k = spread_bits16(q(f[0], g.b_c[0] - g.B[0], g.B[0], 16)) |
+                         (spread_bits16(q(f[1], g.b_c[1] - g.B[1], g.B[1], 16)) << 1);
+            if (dim == 3) k = (k << 8) | q(f[2], g.b_c[2] - g.B[2], g.B[2], 8);
+            key[(size_t)p] = {k, (int)p};
+        }
+    std::sort(key.begin(), key.end());
+    std::vector<int> perm((size_t)n);
+    for (long long t = 0; t < n; ++t) perm[(size_t)t] = key[(size_t)t].second;
+    return perm;
+}
+
 }  // namespace fv

@@ -251,9 +251,23 @@ std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, co
     FV_HIP(hipMalloc((void **)&t->tidx, n * sizeof(int)));
     FV_HIP(hipMalloc((void **)&t->tphi, n * g.dim * sizeof(double)));
     const double *qn = ctx->cache.quad(g.w, st);
-    build_targets(ant_dev, g.n_ant, g.dim, g.fold_axis, g.b_c, g.B, g.w, qn, *t, st);
-    // built once per array; later users may run on other streams
-    FV_HIP(hipStreamSynchronize(st));
+    const std::vector<int> order = target_order(ant_host, g);
+    int *perm_dev = nullptr;
+    FV_HIP(hipMalloc((void **)&perm_dev, n * sizeof(int)));
+    hipError_t e = hipMemcpyAsync(perm_dev, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        try {
+            build_targets(ant_dev, g.n_ant, g.dim, g.fold_axis, g.b_c, g.B, g.w, qn, perm_dev, *t, st);
+        } catch (...) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(perm_dev);
+            throw;
+        }
+        // built once per array; later users may run on other streams
+        e = hipStreamSynchronize(st);
+    }
+    (void)hipFree(perm_dev);
+    FV_HIP(e);
     ctx->targets.push_back(t);
     return t;
 }
