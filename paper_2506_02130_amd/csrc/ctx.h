@@ -48,11 +48,18 @@ struct fv_ctx {
     std::vector<std::pair<uint64_t, fv::GeomPlan>> geos;
     std::list<std::shared_ptr<fv::TargetTable>> targets;
     double *scalar_buf = nullptr;
+    size_t scalar_cap = 0;  // doubles
     fv::PinnedBuf plan_pin;  // host staging of the planning scalars of fv_simulate_dev
     fv::TuneCache tunes;     // autotuned FFT launch shapes
     fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
-    double *scalars(hipStream_t) {
-        if (!scalar_buf) FV_HIP(hipMalloc((void **)&scalar_buf, (8 + 7 * fv::kSrcCheckBlocks) * sizeof(double)));
+    double *scalars(size_t n_doubles) {
+        if (n_doubles > scalar_cap) {
+            if (scalar_buf) (void)hipFree(scalar_buf);
+            scalar_buf = nullptr;
+            scalar_cap = 0;
+            FV_HIP(hipMalloc((void **)&scalar_buf, n_doubles * sizeof(double)));
+            scalar_cap = n_doubles;
+        }
         return scalar_buf;
     }
     ~fv_ctx();

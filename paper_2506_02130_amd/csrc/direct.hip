@@ -60,76 +60,14 @@ __global__ __launch_bounds__(256) void k_direct(const double *ant, int n_ant, lo
     }
 }
 
-// Partial min/max of each direction component and count of invalid
-// directions per block; k_src_reduce folds the partials.
-__global__ __launch_bounds__(256) void k_src_check(const double *src, int n_src, double *part) {
-    __shared__ double red[6][256];
-    __shared__ int badsh[256];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+// Input check of the device entry point, one pass over the inputs: per block,
+// min and max of each direction component, the count of non-unit or
+// non-finite directions and the count of non-finite strengths (flux and beam,
+// 16-byte loads when aligned); k_validate_reduce folds the block partials and
+// gathers the frequencies and antenna positions behind them, so that the host
+// fetches every planning scalar with one copy.
+__device__ __forceinline__ int count_nonfinite(const double *x, long long n, long long tid, long long nth) {
     int bad = 0;
-    for (int j = blockIdx.x * 256 + threadIdx.x; j < n_src; j += gridDim.x * 256) {
-        const double a = src[3 * (size_t)j], b = src[3 * (size_t)j + 1], c = src[3 * (size_t)j + 2];
-        if (!(isfinite(a) && isfinite(b) && isfinite(c)) || fabs(sqrt(a * a + b * b + c * c) - 1.0) > 1e-9) ++bad;
-        lo[0] = fmin(lo[0], a);
-        hi[0] = fmax(hi[0], a);
-        lo[1] = fmin(lo[1], b);
-        hi[1] = fmax(hi[1], b);
-        lo[2] = fmin(lo[2], c);
-        hi[2] = fmax(hi[2], c);
-    }
-    for (int a = 0; a < 3; ++a) {
-        red[2 * a][threadIdx.x] = lo[a];
-        red[2 * a + 1][threadIdx.x] = hi[a];
-    }
-    badsh[threadIdx.x] = bad;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            for (int a = 0; a < 3; ++a) {
-                red[2 * a][threadIdx.x] = fmin(red[2 * a][threadIdx.x], red[2 * a][threadIdx.x + off]);
-                red[2 * a + 1][threadIdx.x] = fmax(red[2 * a + 1][threadIdx.x], red[2 * a + 1][threadIdx.x + off]);
-            }
-            badsh[threadIdx.x] += badsh[threadIdx.x + off];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < 6; ++k) part[7 * blockIdx.x + k] = red[k][0];
-        part[7 * blockIdx.x + 6] = (double)badsh[0];
-    }
-}
-
-// One wavefront folds the per-block partials (lane l takes blocks l, l + 64,
-// ...), then a butterfly reduction across the lanes.
-__global__ __launch_bounds__(64) void k_src_reduce(const double *part, int nblk, double *out) {
-    const int l = threadIdx.x;
-    double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
-    for (int b = l; b < nblk; b += 64) {
-        for (int k = 0; k < 6; k += 2) {
-            v[k] = fmin(v[k], part[7 * b + k]);
-            v[k + 1] = fmax(v[k + 1], part[7 * b + k + 1]);
-        }
-        v[6] += part[7 * b + 6];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        for (int k = 0; k < 6; k += 2) {
-            v[k] = fmin(v[k], __shfl_xor(v[k], off, 64));
-            v[k + 1] = fmax(v[k + 1], __shfl_xor(v[k + 1], off, 64));
-        }
-        v[6] += __shfl_xor(v[6], off, 64);
-    }
-    if (l == 0) {
-        for (int k = 0; k < 7; ++k) out[k] = v[k];
-        int *cnt = (int *)(out + 7);
-        cnt[0] = 0;
-        cnt[1] = 0;
-    }
-}
-
-// Count of non-finite values; 16-byte loads when x is 16-byte aligned.
-__global__ void k_count_nonfinite(const double *x, long long n, int *out) {
-    int bad = 0;
-    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x, nth = (long long)gridDim.x * blockDim.x;
     long long done = 0;
     if (((uintptr_t)x & 15) == 0) {
         const double2 *x2 = (const double2 *)x;
@@ -143,7 +81,82 @@ __global__ void k_count_nonfinite(const double *x, long long n, int *out) {
     }
     for (long long i = done + tid; i < n; i += nth)
         if (!isfinite(x[i])) ++bad;
-    if (bad) atomicAdd(out, bad);
+    return bad;
+}
+
+__global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, const double *flux,
+                                                  const double *beam, long long n_fs, double *part) {
+    __shared__ double red[6][256];
+    __shared__ int bsh[2][256];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    const long long tid = (long long)blockIdx.x * 256 + threadIdx.x, nth = (long long)gridDim.x * 256;
+    for (long long j = tid; j < n_src; j += nth) {
+        const double a = src[3 * j], b = src[3 * j + 1], c = src[3 * j + 2];
+        if (!(isfinite(a) && isfinite(b) && isfinite(c)) || fabs(sqrt(a * a + b * b + c * c) - 1.0) > 1e-9) ++bad;
+        lo[0] = fmin(lo[0], a);
+        hi[0] = fmax(hi[0], a);
+        lo[1] = fmin(lo[1], b);
+        hi[1] = fmax(hi[1], b);
+        lo[2] = fmin(lo[2], c);
+        hi[2] = fmax(hi[2], c);
+    }
+    int badv = n_fs ? count_nonfinite(flux, n_fs, tid, nth) : 0;
+    if (beam && n_fs) badv += count_nonfinite(beam, n_fs, tid, nth);
+    for (int a = 0; a < 3; ++a) {
+        red[2 * a][threadIdx.x] = lo[a];
+        red[2 * a + 1][threadIdx.x] = hi[a];
+    }
+    bsh[0][threadIdx.x] = bad;
+    bsh[1][threadIdx.x] = badv;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            for (int a = 0; a < 3; ++a) {
+                red[2 * a][threadIdx.x] = fmin(red[2 * a][threadIdx.x], red[2 * a][threadIdx.x + off]);
+                red[2 * a + 1][threadIdx.x] = fmax(red[2 * a + 1][threadIdx.x], red[2 * a + 1][threadIdx.x + off]);
+            }
+            bsh[0][threadIdx.x] += bsh[0][threadIdx.x + off];
+            bsh[1][threadIdx.x] += bsh[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 6; ++k) part[8 * blockIdx.x + k] = red[k][0];
+        part[8 * blockIdx.x + 6] = (double)bsh[0][0];
+        part[8 * blockIdx.x + 7] = (double)bsh[1][0];
+    }
+}
+
+// One wavefront folds the per-block partials (lane l takes blocks l, l + 64,
+// ...) by a butterfly across the lanes; every thread then helps gather the
+// frequencies and antenna positions.
+__global__ __launch_bounds__(256) void k_validate_reduce(const double *part, int nblk, const double *freq,
+                                                         int n_freq, const double *ant, int n_ant, double *out) {
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        double v[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0, 0.0};
+        for (int b = l; b < nblk; b += 64) {
+            for (int k = 0; k < 6; k += 2) {
+                v[k] = fmin(v[k], part[8 * b + k]);
+                v[k + 1] = fmax(v[k + 1], part[8 * b + k + 1]);
+            }
+            v[6] += part[8 * b + 6];
+            v[7] += part[8 * b + 7];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            for (int k = 0; k < 6; k += 2) {
+                v[k] = fmin(v[k], __shfl_xor(v[k], off, 64));
+                v[k + 1] = fmax(v[k + 1], __shfl_xor(v[k + 1], off, 64));
+            }
+            v[6] += __shfl_xor(v[6], off, 64);
+            v[7] += __shfl_xor(v[7], off, 64);
+        }
+        if (l == 0)
+            for (int k = 0; k < 8; ++k) out[k] = v[k];
+    }
+    for (int i = threadIdx.x; i < n_freq; i += 256) out[8 + i] = freq[i];
+    for (int i = threadIdx.x; i < 3 * n_ant; i += 256) out[8 + n_freq + i] = ant[i];
 }
 
 __global__ void k_zero_f64(double *p, long long n) {
@@ -189,18 +202,18 @@ void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int 
     FV_HIP(hipGetLastError());
 }
 
-void launch_src_check(const double *src, int n_src, double *out8, hipStream_t st) {
-    // out8 is followed by room for kSrcCheckBlocks * 7 partial values
-    const int nblk = kSrcCheckBlocks;
-    double *part = out8 + 8;
-    hipLaunchKernelGGL(k_src_check, dim3(nblk), dim3(256), 0, st, src, n_src, part);
-    hipLaunchKernelGGL(k_src_reduce, dim3(1), dim3(64), 0, st, (const double *)part, nblk, out8);
-    FV_HIP(hipGetLastError());
+size_t validate_doubles(int n_ant, int n_freq) {
+    return 8 + (size_t)n_freq + 3 * (size_t)n_ant + 8 * (size_t)kSrcCheckBlocks;
 }
 
-void launch_count_nonfinite(const double *x, long long n, int *out, hipStream_t st) {
-    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_count_nonfinite, dim3(std::max(1u, nb)), dim3(256), 0, st, x, n, out);
+void launch_validate(const double *src, int n_src, const double *flux, const double *beam, int n_freq,
+                     const double *ant, int n_ant, const double *freq, double *out, hipStream_t st) {
+    double *part = out + 8 + n_freq + 3 * (size_t)n_ant;
+    const long long n_fs = n_src > 0 ? (long long)n_src * n_freq : 0;
+    hipLaunchKernelGGL(k_validate, dim3(kSrcCheckBlocks), dim3(256), 0, st, n_src > 0 ? src : nullptr, n_src,
+                       n_src > 0 ? flux : nullptr, n_src > 0 ? beam : nullptr, n_fs, part);
+    hipLaunchKernelGGL(k_validate_reduce, dim3(1), dim3(256), 0, st, (const double *)part, kSrcCheckBlocks, freq,
+                       n_freq, ant, n_ant, out);
     FV_HIP(hipGetLastError());
 }
 

@@ -23,7 +23,7 @@ constexpr int kMinW = 3;
 constexpr int kQuadHalf = 32;    // positive nodes of the 64-node Gauss-Legendre rule
 constexpr int kSubBin = 8;       // sub-bin edge (cells) of the source sort along x and y
 constexpr int kSubBinZ = 4;      // sub-bin edge along z
-constexpr int kSrcCheckBlocks = 128;  // blocks of the source-direction check reduction
+constexpr int kSrcCheckBlocks = 2048;  // blocks of the input-check pass (one partial each)
 
 // ---------------------------------------------------------------------------
 // Errors: internal code throws fv::Error; every ABI entry converts it to a
@@ -252,11 +252,14 @@ void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, con
 // normalised to the target box (x, y interleaved; z as the least significant
 // part in 3-D).
 std::vector<int> target_order(const double *ant_host, const GeomPlan &g);
-// Device reduction over sources: out[0..5] = min/max of l, m, n; out[6] =
-// count of non-unit or non-finite directions.  out must be device memory.
-void launch_src_check(const double *src, int n_src, double *out7, hipStream_t s);
-// Device count of non-finite values in x[n] added to *out (device int).
-void launch_count_nonfinite(const double *x, long long n, int *out, hipStream_t s);
+// Input check and planning-scalar gather of the device entry point (device
+// buffer `out` of validate_doubles() doubles): out[0..5] = min/max of l, m, n;
+// out[6] = count of non-unit or non-finite directions; out[7] = count of
+// non-finite flux and beam values; out[8 .. 8 + n_freq) = frequencies; then
+// the 3 n_ant antenna coordinates; then block partials (scratch).
+size_t validate_doubles(int n_ant, int n_freq);
+void launch_validate(const double *src, int n_src, const double *flux, const double *beam, int n_freq,
+                     const double *ant, int n_ant, const double *freq, double *out, hipStream_t s);
 void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
 
 // Direct sums.

@@ -348,6 +348,10 @@ double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, c
     opts.tunes = &ctx->tunes;
     opts.graphs = &slot.graphs;
     const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
+    // one launch group when everything fits (the usual case); else groups of
+    // frequencies sized job by job
+    if (nufft_workspace_bytes(jobs, k.dim, k.prec, k.w) <= cap)
+        return nufft_execute(jobs, k.dim, k.prec, k.w, slot.arena, ctx->cache, st, tm, &opts);
     std::vector<size_t> each(jobs.size());
     for (size_t i = 0; i < jobs.size(); ++i)
         each[i] = nufft_workspace_bytes(std::vector<SnapJob>{jobs[i]}, k.dim, k.prec, k.w);
@@ -565,22 +569,17 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     if (!(p->eps >= 1e-14 && p->eps <= 1e-1)) fv::fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
     FV_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    // planning scalars to the host, through pinned staging: [check 8][freq][ant]
+    // input check and planning scalars in one pass, one copy through pinned
+    // staging: [check 8][freq][ant]
     const size_t n_ant3 = 3 * (size_t)p->n_ant;
-    double *pin = (double *)ctx->plan_pin.get((8 + (size_t)p->n_freq + n_ant3) * sizeof(double));
-    double *host_chk = pin, *pfreq = pin + 8, *pant = pfreq + p->n_freq;
-    for (int k = 0; k < 8; ++k) host_chk[k] = 0.0;
-    FV_HIP(hipMemcpyAsync(pant, p->ant_enu, n_ant3 * sizeof(double), hipMemcpyDeviceToHost, st));
-    FV_HIP(hipMemcpyAsync(pfreq, p->freq_hz, p->n_freq * sizeof(double), hipMemcpyDeviceToHost, st));
-    double *chk = ctx->scalars(st);  // device: 7 doubles + 1 int
-    if (p->n_src > 0) {
-        fv::launch_src_check(p->src_lmn, p->n_src, chk, st);
-        int *bad = (int *)(chk + 7);
-        fv::launch_count_nonfinite(p->flux, (long long)p->n_src * p->n_freq, bad, st);
-        if (p->beam) fv::launch_count_nonfinite(p->beam, (long long)p->n_src * p->n_freq, bad, st);
-        FV_HIP(hipMemcpyAsync(host_chk, chk, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-    }
+    const size_t nscal = 8 + (size_t)p->n_freq + n_ant3;
+    double *pin = (double *)ctx->plan_pin.get(nscal * sizeof(double));
+    double *dev = ctx->scalars(fv::validate_doubles(p->n_ant, p->n_freq));
+    fv::launch_validate(p->src_lmn, p->n_src, p->flux, p->beam, p->n_freq, p->ant_enu, p->n_ant, p->freq_hz, dev,
+                        st);
+    FV_HIP(hipMemcpyAsync(pin, dev, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
     FV_HIP(hipStreamSynchronize(st));
+    double *host_chk = pin, *pfreq = pin + 8, *pant = pfreq + p->n_freq;
     const std::vector<double> ant(pant, pant + n_ant3), freq(pfreq, pfreq + p->n_freq);
     fv_problem meta = *p;
     meta.ant_enu = ant.data();
@@ -589,9 +588,8 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
         if (!std::isfinite(a)) fv::fail(FV_EINVAL, "non-finite antenna position");
     for (double f : freq)
         if (!(std::isfinite(f) && f > 0)) fv::fail(FV_EINVAL, "frequency must be finite and > 0");
-    int badcount = 0;
-    std::memcpy(&badcount, host_chk + 7, sizeof(int));
-    if (p->n_src > 0 && (host_chk[6] != 0.0 || badcount != 0)) fv::fail(FV_EINVAL, "invalid source directions or strengths");
+    if (p->n_src > 0 && (host_chk[6] != 0.0 || host_chk[7] != 0.0))
+        fv::fail(FV_EINVAL, "invalid source directions or strengths");
     if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6) fv::fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
     fv::DevInputs in;
     in.ant = nullptr;
