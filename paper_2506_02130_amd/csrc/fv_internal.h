@@ -236,13 +236,15 @@ struct ExecOpts {
     bool graph = false;      // capture / replay the launch sequence as a HIP graph
     TuneCache *tunes = nullptr;
     GraphCache *graphs = nullptr;
+    size_t cap = 0;          // > 0: refuse (set *too_big) when the workspace exceeds cap bytes
 };
 
 // Enqueue the whole type-3 pipeline for jobs that share (dim, precision, w).
 // Allocates its workspace from `arena` (which must be idle); returns the
 // algorithmic HBM bytes of the grid stages.
 double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena,
-                     DevCache &cache, hipStream_t s, StageTimer *timer = nullptr, const ExecOpts *opts = nullptr);
+                     DevCache &cache, hipStream_t s, StageTimer *timer = nullptr, const ExecOpts *opts = nullptr,
+                     bool *too_big = nullptr);
 // Workspace bytes nufft_execute would take for these jobs.
 size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w);
 

@@ -25,13 +25,14 @@ struct Prepared {
     Bufs B;
 };
 
-Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
-                 hipStream_t st, const Tuning &tune) {
+// Uploads the tables of a layout already built for `jobs`.
+Prepared prepare_layout(Layout &&layout, const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w,
+                        Arena &arena, DevCache &cache, hipStream_t st) {
     if (w < kMinW || w > kMaxW) fail(FV_EUNSUPPORTED, "kernel width out of range");
     Prepared P;
     P.fn = pick(dim, prec_bits, w);
     if (!P.fn) fail(FV_EUNSUPPORTED, "no kernel instance for this width");
-    P.L = make_layout(jobs, dim, prec_bits, w, tune);
+    P.L = std::move(layout);
     Layout &L = P.L;
     const double *qn = cache.quad(w, st);
     for (size_t i = 0; i < jobs.size(); ++i) {
@@ -70,6 +71,11 @@ Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w
     if (ng) FV_HIP(hipMemcpyAsync(P.B.orders, stage + tb, ob, hipMemcpyHostToDevice, st));
     arena.host.record(st);
     return P;
+}
+
+Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
+                 hipStream_t st, const Tuning &tune) {
+    return prepare_layout(make_layout(jobs, dim, prec_bits, w, tune), jobs, dim, prec_bits, w, arena, cache, st);
 }
 
 void fetch_c128(const void *dev, long long n, int prec_bits, double *host, hipStream_t st) {
@@ -176,17 +182,27 @@ uint64_t graph_key(const Prepared &P, int n, int dim, int prec_bits, int w) {
 }  // namespace
 
 double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
-                     hipStream_t st, StageTimer *timer, const ExecOpts *opts) {
+                     hipStream_t st, StageTimer *timer, const ExecOpts *opts, bool *too_big) {
+    if (too_big) *too_big = false;
     if (jobs.empty()) return 0.0;
+    // the workspace size does not depend on the launch shape
     Tuning tune = Tuning::defaults();
+    Layout layout = make_layout(jobs, dim, prec_bits, w, tune);
+    if (opts && opts->cap && too_big && layout_bytes(layout, dim, prec_bits, (int)jobs.size()) > opts->cap) {
+        *too_big = true;
+        return 0.0;
+    }
     if (opts && opts->tunes) {
         const std::string key = tune_key(jobs, dim, prec_bits);
-        if (!opts->tunes->find(key, &tune) && opts->autotune) {
+        bool have = opts->tunes->find(key, &tune);
+        if (!have && opts->autotune) {
             tune = autotune(jobs, dim, prec_bits, w, arena, cache, st);
             opts->tunes->put(key, tune);
+            have = true;
         }
+        if (have) layout = make_layout(jobs, dim, prec_bits, w, tune);
     }
-    Prepared P = prepare(jobs, dim, prec_bits, w, arena, cache, st, tune);
+    Prepared P = prepare_layout(std::move(layout), jobs, dim, prec_bits, w, arena, cache, st);
     const int n = (int)jobs.size();
     // graphs need a capturable (non-null) stream; per-stage timing stays eager
     const bool graph = opts && opts->graph && opts->graphs && st != nullptr && !(timer && timer->on);

@@ -20,15 +20,27 @@ int kernel_width(double eps) {
     return std::max(2, std::min(kMaxW, w));
 }
 
+// Even numbers whose only prime factors are 2, 3 and 5, up to 2^31, sorted
+// (about 1.5k of them), built once.
+static const std::vector<long long> &smooth_even_table() {
+    static const std::vector<long long> t = [] {
+        std::vector<long long> v;
+        const long long lim = 1LL << 31;
+        for (long long a = 2; a <= lim; a *= 2)
+            for (long long b = a; b <= lim; b *= 3)
+                for (long long c = b; c <= lim; c *= 5) v.push_back(c);
+        std::sort(v.begin(), v.end());
+        return v;
+    }();
+    return t;
+}
+
 int next_smooth_even(long long n) {
     if (n < 2) n = 2;
-    if (n % 2) ++n;
-    for (;; n += 2) {
-        long long m = n;
-        for (int p : {2, 3, 5})
-            while (m % p == 0) m /= p;
-        if (m == 1) return (int)n;
-    }
+    const auto &t = smooth_even_table();
+    auto it = std::lower_bound(t.begin(), t.end(), n);
+    if (it == t.end()) fail(FV_EUNSUPPORTED, "grid size beyond 2^31");
+    return (int)*it;
 }
 
 void src_box(const double *src, int n_src, int dim, double *s_c, double *S) {

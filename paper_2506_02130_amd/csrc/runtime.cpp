@@ -154,9 +154,18 @@ StageTimer::~StageTimer() {
 }
 
 // ---------------------------------------------------------------------------
+// Cache-key hash (FNV-1a style, over 8-byte words, then the tail bytes).
 static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
     const unsigned char *c = (const unsigned char *)p;
-    for (size_t i = 0; i < n; ++i) {
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, c + i, 8);
+        h ^= w;
+        h *= 1099511628211ull;
+        h ^= h >> 29;
+    }
+    for (; i < n; ++i) {
         h ^= c[i];
         h *= 1099511628211ull;
     }
@@ -350,8 +359,11 @@ double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, c
     const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
     // one launch group when everything fits (the usual case); else groups of
     // frequencies sized job by job
-    if (nufft_workspace_bytes(jobs, k.dim, k.prec, k.w) <= cap)
-        return nufft_execute(jobs, k.dim, k.prec, k.w, slot.arena, ctx->cache, st, tm, &opts);
+    opts.cap = cap;
+    bool too_big = false;
+    const double b1 = nufft_execute(jobs, k.dim, k.prec, k.w, slot.arena, ctx->cache, st, tm, &opts, &too_big);
+    if (!too_big) return b1;
+    opts.cap = 0;
     std::vector<size_t> each(jobs.size());
     for (size_t i = 0; i < jobs.size(); ++i)
         each[i] = nufft_workspace_bytes(std::vector<SnapJob>{jobs[i]}, k.dim, k.prec, k.w);
