@@ -45,6 +45,7 @@ struct SnapDev {
     int ntile[3];                    // spread tiles per axis
     int nsb[3];                      // sort sub-bins per axis
     int cx[3];                       // lines per workgroup of each FFT pass
+    int fft_split[3];                // 1: one parity transform per workgroup
     int dim, w, n_src, n_tgt;
     int degenerate;                  // bit a: X_a was clamped to 1 rad
     int pad0;
@@ -207,6 +208,7 @@ struct Tuning {
     int lines = 2;   // columns per workgroup of the other passes
     int tpb1 = 0;    // threads of the x pass (0: by line length)
     int tpbm = 256;  // threads of the other passes
+    int split = 0;   // 1: even and odd transforms of a line in separate workgroups
     double fft_ms = 0.0;  // FFT time measured by the autotuner (0: not tuned)
     static Tuning defaults();
     int tpb(int line_len, bool multi) const;

@@ -119,11 +119,13 @@ Tuning autotune(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w,
     Tuning best = Tuning::defaults();
     best.fft_ms = 1e30;
     try {
+        for (int split : {0, 1})
         for (int rows : {1, 2})
             for (int lines : {1, 2, 4})
                 for (int tpb1 : {256, 512})
                     for (int tpbm : {128, 256, 512}) {
                         Tuning t;
+                        t.split = split;
                         t.rows = rows;
                         t.lines = lines;
                         t.tpb1 = tpb1;

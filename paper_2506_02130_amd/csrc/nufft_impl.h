@@ -768,8 +768,17 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
     const bool rows = F == 1;
     const long long ngrp = rows ? (Sl + CX - 1) / CX : (F + CX - 1) / CX;
     const long long nblk = rows ? ngrp : Sl * ngrp;
-    const long long wl = xcd_order((long long)blockIdx.x, (long long)gridDim.x);
+    long long wl = xcd_order((long long)blockIdx.x, (long long)gridDim.x);
+    // split passes: workgroups 2 g and 2 g + 1 take the even and the odd
+    // transforms of line group g (half the LDS each, twice the workgroups)
+    const bool split = S.fft_split[a] != 0;
+    int only = 0;
+    if (split) {
+        only = (int)(wl & 1);
+        wl >>= 1;
+    }
     if (wl >= nblk) return;
+    const int tps = split ? 1 : 2;  // transforms per line held in LDS
     const bool fromA = (a % 2) == 0;
     const cplx<R> *in = grid + (fromA ? S.bufA : S.bufB);
     cplx<R> *out = grid + (fromA ? S.bufB : S.bufA);
@@ -792,7 +801,7 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
     }
     cplx<R> *twc = (cplx<R> *)smem;  // [N/64 + 1] coarse, then [64] fine twiddles of W_N
     cplx<R> *twf = twc + (N >> 6) + 1;
-    cplx<R> *buf = twf + 64;              // [2 cx][Lp]: line 2c even, 2c + 1 odd outputs
+    cplx<R> *buf = twf + 64;              // [tps cx][Lp]: line tps c (+ 1): even (odd) outputs
     const cplx<R> *tw = (const cplx<R> *)S.tw[a];
     for (int t = threadIdx.x; t < (N >> 6) + 1 + 64; t += TPB) {
         const int g = t <= (N >> 6) ? t << 6 : t - (N >> 6) - 1;
@@ -815,32 +824,38 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
         int j = l + half;
         if (j >= L) j -= L;
         const cplx<R> v = in[src];
-        cplx<R> vo = cmul<R>(v, twiddle<R>(twc, twf, j));
-        if (j >= half) vo = cmake<R>(-vo.x, -vo.y);
-        buf[(2 * c) * Lp + cpad(j)] = v;
-        buf[(2 * c + 1) * Lp + cpad(j)] = vo;
+        if (!split || only) {
+            cplx<R> vo = cmul<R>(v, twiddle<R>(twc, twf, j));
+            if (j >= half) vo = cmake<R>(-vo.x, -vo.y);
+            buf[(tps * c + tps - 1) * Lp + cpad(j)] = vo;
+        }
+        if (!split || !only) buf[(tps * c) * Lp + cpad(j)] = v;
     }
     __syncthreads();
-    dif_fft<R, TPB>(buf, L, Lp, 2 * cx, twc, twf);
+    dif_fft<R, TPB>(buf, L, Lp, tps * cx, twc, twf);
     const int *drev = S.drev[a];
-    const float invM = 1.0f / (float)Ma;
-    for (int e = threadIdx.x; e < cx * Ma; e += TPB) {
-        int pi, c;
-        long long dst;
+    // outputs p in [-P, P]; a split workgroup writes those of its parity,
+    // p = p0 + 2 q (its partner fills the others)
+    const int p0 = split ? (((-Pa) & 1) == only ? -Pa : -Pa + 1) : -Pa;
+    const int step = split ? 2 : 1;
+    const int cnt = (Pa - p0) / step + 1;
+    const float invM = 1.0f / (float)cnt;
+    for (int e = threadIdx.x; e < cx * cnt; e += TPB) {
+        int qi, c;
         if (rows) {
-            c = fdiv(e, Ma, invM);
-            pi = e - c * Ma;
-            dst = c * out_ls + pi;
+            c = fdiv(e, cnt, invM);
+            qi = e - c * cnt;
         } else {
-            pi = fdiv(e, cx, invcx);
-            c = e - pi * cx;
-            dst = (long long)pi * F + c;
+            qi = fdiv(e, cx, invcx);
+            c = e - qi * cx;
         }
-        const int pp = pi - Pa, par = pp & 1;
+        const int pp = p0 + step * qi, par = pp & 1;
+        const long long pi = pp + Pa;
+        const long long dst = rows ? c * out_ls + pi : pi * F + c;
         int k = (pp - par) >> 1;
         if (k < 0) k += L;
         if (k >= L) k -= L;
-        out[dst] = buf[(2 * c + par) * Lp + cpad(drev[k])];
+        out[dst] = buf[(tps * c + (split ? 0 : par)) * Lp + cpad(drev[k])];
     }
 }
 
@@ -1080,18 +1095,20 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
             for (int b = a + 1; b < dim; ++b) Sl *= p.n1[b];
             // lines per workgroup: columns (fast extent F > 1) or rows (F == 1),
             // each line held as two transforms within 64 KB of LDS
+            const int tps = tune.split ? 1 : 2;
+            d.fft_split[a] = tune.split ? 1 : 0;
             const long long bylds = (65536LL - (long long)fft_tw_entries(p.n2[a]) * csz) /
-                                    (2LL * cline_pad(p.n1[a]) * csz);
+                                    ((long long)tps * cline_pad(p.n1[a]) * csz);
             // short lines take more lines per workgroup so that every thread
             // has butterflies (about 4 TPB points per workgroup)
             const long long fill = 4LL * L.tpb[a] / (2LL * p.n1[a]);
             const long long lim = std::max(fill, F > 1 ? (long long)tune.lines : (long long)tune.rows);
             const int cx = (int)std::max(1LL, std::min({F > 1 ? F : Sl, bylds, lim}));
-            const long long nwg = F > 1 ? Sl * ((F + cx - 1) / cx) : (Sl + cx - 1) / cx;
+            const long long nwg = (F > 1 ? Sl * ((F + cx - 1) / cx) : (Sl + cx - 1) / cx) * (tune.split ? 2 : 1);
             d.cx[a] = cx;
             d.wg_base[a] = L.wg_total[a];
             L.wg_total[a] += nwg;
-            L.fft_lds[a] = std::max(L.fft_lds[a], 2 * (size_t)cx * cline_pad(p.n1[a]) * csz +
+            L.fft_lds[a] = std::max(L.fft_lds[a], (size_t)tps * cx * cline_pad(p.n1[a]) * csz +
                                                       (size_t)fft_tw_entries(p.n2[a]) * csz);
             L.max_wg[a] = std::max(L.max_wg[a], nwg);
         }

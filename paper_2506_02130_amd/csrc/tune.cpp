@@ -21,6 +21,7 @@ Tuning Tuning::defaults() {
         d.lines = std::max(1, std::min(64, env_or("FV_FFT_MAX_LINES", d.lines)));
         d.tpb1 = env_or("FV_FFT_TPB1", d.tpb1);
         d.tpbm = env_or("FV_FFT_TPBM", d.tpbm);
+        d.split = env_or("FV_FFT_SPLIT", d.split) ? 1 : 0;
         return d;
     }();
     return t;
@@ -53,7 +54,7 @@ void TuneCache::put(const std::string &key, const Tuning &t) {
     for (auto &kv : entries) {
         const Tuning &v = kv.second;
         o << "  \"" << kv.first << "\": {\"rows\": " << v.rows << ", \"lines\": " << v.lines << ", \"tpb1\": " << v.tpb1
-          << ", \"tpbm\": " << v.tpbm << ", \"fft_ms\": " << v.fft_ms << "}" << (++k < entries.size() ? "," : "")
+          << ", \"tpbm\": " << v.tpbm << ", \"split\": " << v.split << ", \"fft_ms\": " << v.fft_ms << "}" << (++k < entries.size() ? "," : "")
           << "\n";
     }
     o << "}\n";
@@ -102,6 +103,7 @@ void TuneCache::load(const std::string &file) {
         t.tpb1 = (int)v;
         ok = ok && read_int_field(obj, "tpbm", &v);
         t.tpbm = (int)v;
+        if (read_int_field(obj, "split", &v)) t.split = v != 0.0;
         if (read_int_field(obj, "fft_ms", &v)) t.fft_ms = v;
         if (ok && t.rows >= 1 && t.lines >= 1) entries[key] = t;
         p = b1 + 1;
