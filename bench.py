@@ -30,6 +30,7 @@ FP32_MATRIX_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix cores
 METRIC = "src×baseline pairs/s at 1e-6 rel err, NUFFT vs direct DFT; p99 latency"
 KERNEL_OF_STAGE = {"spread": "k_spread", "fft_x": "k_fft", "fft_y": "k_fft", "fft_z": "k_fft", "interp": "k_interp",
                    "sort": "k_bin/k_scan/k_scatter", "direct": "k_direct", "other": "k_ipsi"}
+KERNEL_OF_STAGE_T1 = {"spread": "k_t1_spread", "fft_x": "k_t1_rows", "fft_y": "k_t1_cols", "interp": "k_t1_out"}
 
 
 def _pct(xs, q):
@@ -66,6 +67,73 @@ def _traffic_from_profiles(stage: str):
         return None
     k = d.get("stages", {}).get(stage)
     return None if k is None else k.get("bytes_per_launch")
+
+
+# pipeline stage of each kernel (the FFT kernel of the type-3 path takes
+# fft_x, fft_y, fft_z in launch order)
+STAGE_OF_KERNEL = {"k_order_count": "sort", "k_order_scan": "sort", "k_order_place": "sort", "k_bin": "sort",
+                   "k_scan": "sort", "k_scatter": "sort", "k_fill_int": "sort", "k_spread_mfma": "spread",
+                   "k_spread": "spread", "k_interp": "interp", "k_ipsi": "other", "k_t1_spread": "spread",
+                   "k_t1_rows": "fft_x", "k_t1_cols": "fft_y", "k_t1_out": "interp", "k_validate": "other",
+                   "k_validate_reduce": "other", "k_targets": "other"}
+
+
+def reduce_traffic(fetch_csv: str, write_csv: str, calib_mib: int, cmd: str, workload: str):
+    """HBM bytes per launch of each stage from two rocprofv3 --pmc runs of
+    `bench.py --profile --calib-copy-mib M` (FETCH_SIZE, then WRITE_SIZE, in
+    KiB per dispatch), each scaled by what the same counter reads for the M MiB
+    device copy issued after the timed steps.  Rows are the dispatches of the
+    last step (from its input-check kernel to the copy).  Writes
+    profiles/traffic_c2.json (read back by the roofline, tagged with the kernel
+    source hash) and prints a markdown table."""
+    import csv
+
+    def load(path):
+        rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+        out = []
+        for r in rows:
+            name = r["Kernel_Name"].replace("void ", "").replace("fv::(anonymous namespace)::", "").split("(")[0]
+            out.append((name, float(r["Counter_Value"])))
+        return out
+
+    fetch, write = load(fetch_csv), load(write_csv)
+    if [x[0] for x in fetch] != [x[0] for x in write]:
+        raise SystemExit("the two counter runs dispatched different kernels")
+    ci = max((i for i, x in enumerate(write) if "copyBuffer" in x[0]), key=lambda i: write[i][1])
+    f_scale = calib_mib * 1024 / fetch[ci][1]
+    w_scale = calib_mib * 1024 / write[ci][1]
+    s0 = [i for i, x in enumerate(fetch) if x[0] == "k_validate" and i < ci][-1]
+    stages, rows, nfft = {}, [], 0
+    for i in range(s0, ci):
+        name = fetch[i][0]
+        base = name.split("<")[0]
+        if base == "k_fft":
+            st = ("fft_x", "fft_y", "fft_z")[min(nfft, 2)]
+            nfft += 1
+        else:
+            st = STAGE_OF_KERNEL.get(base)
+        fb, wb = fetch[i][1] * f_scale * 1024, write[i][1] * w_scale * 1024
+        rows.append((name, st, fetch[i][1], write[i][1], fb, wb))
+        if st is None or "copyBuffer" in name:
+            continue
+        e = stages.setdefault(st, {"fetch_bytes": 0.0, "write_bytes": 0.0, "launches": 0})
+        e["fetch_bytes"] += fb
+        e["write_bytes"] += wb
+        e["launches"] += 1
+    for e in stages.values():
+        e["bytes_per_launch"] = (e["fetch_bytes"] + e["write_bytes"]) / e["launches"]
+    d = {"source_hash": _kernel_source_hash(), "command": cmd, "workload": workload,
+         "calibration": {"copy_MiB": calib_mib, "FETCH_SIZE_KiB": fetch[ci][1], "WRITE_SIZE_KiB": write[ci][1],
+                         "fetch_scale": f_scale, "write_scale": w_scale},
+         "stages": stages}
+    json.dump(d, open(os.path.join(ROOT, "profiles", "traffic_c2.json"), "w"), indent=1)
+    print(f"Calibration: the {calib_mib} MiB device copy after the steps reads FETCH_SIZE {fetch[ci][1]:.1f} KiB "
+          f"and WRITE_SIZE {write[ci][1]:.1f} KiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by "
+          f"{w_scale:.3f}.  Rows are the dispatches of the last step.\n")
+    print("| kernel | stage | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB (scaled) | write MB (scaled) |")
+    print("|---|---|---|---|---|---|")
+    for name, st, fk, wk, fb, wb in rows:
+        print(f"| `{name}` | {st or '-'} | {fk:.0f} | {wk:.0f} | {fb / 1e6:.2f} | {wb / 1e6:.2f} |")
 
 
 def serving_leg(fv, synth, np, n_req: int) -> dict:
@@ -159,7 +227,15 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving mix leg")
+    ap.add_argument("--reduce-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no run: reduce two counter-collection CSVs of a --profile --calib-copy-mib run")
     args = ap.parse_args()
+    if args.reduce_traffic:
+        cmd = ("rocprofv3 --pmc COUNTER --output-format csv -d <out> -o run -- python3 bench.py --profile "
+               f"--steps 2 --warmup 1 --calib-copy-mib {args.calib_copy_mib or 256}")
+        reduce_traffic(args.reduce_traffic[0], args.reduce_traffic[1], args.calib_copy_mib or 256, cmd,
+                       "hex350 14.6 m, 1e5 sources, 64 frequencies, eps 1e-6")
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -230,7 +306,8 @@ def main():
     per_launch_ms = stage_ms[dom] / max(stage_launch[dom], 1)
     per_launch_bytes = stage_bytes[dom] / max(stage_launch[dom], 1)
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": KERNEL_OF_STAGE.get(dom, dom), "stage": dom, "achieved": achieved,
+    kernels = KERNEL_OF_STAGE_T1 if reps[-1].get("lattice") else KERNEL_OF_STAGE
+    roofline = {"bound": "hbm", "kernel": kernels.get(dom, dom), "stage": dom, "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": _traffic_from_profiles(dom),
                 "avg_launch_ms": per_launch_ms, "bytes_per_launch": per_launch_bytes}
@@ -293,7 +370,22 @@ def main():
     # ---------------------------------------------------------------- graph replay and batched snapshots
     extras = {}
     if not args.no_extras:
-        gfl = fv.GRAPH | tune
+        # the same workload on the general type-3 path (the hex array is a lattice,
+        # so the default call takes the type-1 path)
+        t3 = fv.TIMING | fv.NO_LATTICE | tune
+        for _ in range(2):
+            step(t3)
+        torch.cuda.synchronize()
+        t30 = time.perf_counter()
+        r3 = [step(t3) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t3_ms = (time.perf_counter() - t30) * 1e3 / args.steps
+        extras["type3"] = {"ms_per_step": t3_ms, "pairs_per_s": pairs_per_step / (t3_ms * 1e-3),
+                           "stages_ms": {n: round(sum(r["t_stage_ms"][i] for r in r3) / args.steps, 4)
+                                         for i, n in enumerate(names) if r3[0]["stage_launches"][i] > 0},
+                           "n1": r3[-1]["n1"][:2]}
+        print(f"bench: type-3 path {t3_ms:.3f} ms/step", file=sys.stderr, flush=True)
+        gfl = fv.GRAPH | fv.NO_LATTICE | tune
         for _ in range(2):
             step(gfl)
         torch.cuda.synchronize()
@@ -303,7 +395,8 @@ def main():
         torch.cuda.synchronize()
         g_ms = (time.perf_counter() - tg0) * 1e3 / args.steps
         extras["graph_replay"] = {"ms_per_step": g_ms, "pairs_per_s": pairs_per_step / (g_ms * 1e-3),
-                                  "note": "same workload, launch sequence replayed as a HIP graph, no stage events"}
+                                  "note": "type-3 path of the same workload, launch sequence replayed as a HIP "
+                                          "graph, no stage events"}
         probs = synth.config4()
         hps = [fv.HostProblem.of(q, flags=tune | fv.TIMING) for q in probs]
         ctx.simulate_batch(hps)  # warm: target tables, tuning
@@ -337,6 +430,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"hex{p.n_ant} 14.6 m, {p.n_src} power-law sources, Gaussian beam, {p.n_freq} freqs "
                                f"100-200 MHz, eps 1e-6, 2-D, FP32 grids, inputs in HBM",
+                   "path": "type-1 (lattice array)" if reps[-1].get("lattice") else "type-3",
                    "n_ant": p.n_ant, "n_pairs": p.n_pairs, "n_src": p.n_src, "n_freq": p.n_freq, "eps": p.eps,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
@@ -346,7 +440,8 @@ def main():
         "stages": stages,
         "direct": direct or None,
         "extras": extras or None,
-        "report": {k: reps[-1][k] for k in ("dim", "prec_bits", "w", "fold_axis", "n1", "n2", "model_bytes")},
+        "report": {k: reps[-1][k] for k in ("dim", "prec_bits", "w", "fold_axis", "n1", "n2", "model_bytes",
+                                            "lattice")},
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -77,6 +77,11 @@ typedef enum {
 #define FV_GRAPH           0x800u /* NUFFT: capture the call's launch sequence as a HIP graph and
                                      replay it on later calls with the same sizes and workspace;
                                      needs a non-null stream; per-stage timing is then not recorded */
+#define FV_NO_LATTICE      0x1000u /* NUFFT: do not use the type-1 path for lattice arrays (paper section
+                                      2.2.1); by default a coplanar array whose East/North positions form
+                                      a lattice within eps c / (20 pi nu_max) metres is simulated with a
+                                      type-1 transform onto its integer baseline modes when that grid is
+                                      the smaller one */
 
 /* stage indices of fv_report.t_stage_ms / stage_bytes / stage_launches */
 #define FV_STAGE_SORT      0      /* key, count, scan and scatter of the source records */
@@ -114,6 +119,8 @@ typedef struct {
     double t_stage_ms[FV_NSTAGE];     /* FV_TIMING: summed event time of each stage's launches */
     double stage_bytes[FV_NSTAGE];    /* algorithmic HBM bytes of each stage (all launches) */
     int stage_launches[FV_NSTAGE];    /* kernel launches per stage */
+    int lattice;          /* 1 when the type-1 lattice path ran (then n1 holds its fine grid) */
+    int reserved;
 } fv_report;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes = 0 means 90%

@@ -30,6 +30,7 @@ NO_FOLD = 0x100
 TIMING = 0x200
 AUTOTUNE = 0x400
 GRAPH = 0x800
+NO_LATTICE = 0x1000
 STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
@@ -55,14 +56,14 @@ class Report(ctypes.Structure):
                 ("fold_axis", ctypes.c_int), ("n1", ctypes.c_int * 3), ("n2", ctypes.c_int * 3),
                 ("t_total_ms", ctypes.c_double), ("model_bytes", ctypes.c_double), ("src_pairs", ctypes.c_double),
                 ("t_stage_ms", ctypes.c_double * 8), ("stage_bytes", ctypes.c_double * 8),
-                ("stage_launches", ctypes.c_int * 8)]
+                ("stage_launches", ctypes.c_int * 8), ("lattice", ctypes.c_int), ("reserved", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {"dim": self.dim, "prec_bits": self.prec_bits, "method": self.method, "w": self.w,
                 "fold_axis": self.fold_axis, "n1": list(self.n1), "n2": list(self.n2),
                 "t_total_ms": self.t_total_ms, "model_bytes": self.model_bytes, "src_pairs": self.src_pairs,
                 "t_stage_ms": list(self.t_stage_ms), "stage_bytes": list(self.stage_bytes),
-                "stage_launches": list(self.stage_launches)}
+                "stage_launches": list(self.stage_launches), "lattice": self.lattice}
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -92,6 +92,14 @@ void simulate_batch(fv_ctx *ctx, Slot &slot, int n, const fv_problem *ps, double
             run_direct(ctx, slot, p, bi[i].in, bi[i].vis, dim, choose_prec(p.eps, p.flags), &tm);
             arena_busy = method == FV_METHOD_MFMA;
         } else {
+            const int dim = choose_dim(p.ant_enu, p.n_ant, p.eps, p.freq_hz, p.n_freq, p.flags);
+            if (dim == 2 && !(p.flags & FV_NO_LATTICE)) {
+                if (arena_busy) FV_HIP(hipStreamSynchronize(st));
+                if (run_lattice(ctx, slot, p, bi[i].in, bi[i].vis, choose_prec(p.eps, p.flags), &tm, r)) {
+                    arena_busy = true;
+                    continue;
+                }
+            }
             std::vector<SnapJob> jobs;
             SnapPlan top;
             NufftGroupKey k = append_jobs(ctx, p, bi[i].in, bi[i].vis, st, jobs, hold, &top);

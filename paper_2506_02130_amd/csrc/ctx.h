@@ -47,6 +47,7 @@ struct fv_ctx {
     std::mutex geo_mu;
     std::vector<std::pair<uint64_t, fv::GeomPlan>> geos;
     std::list<std::shared_ptr<fv::TargetTable>> targets;
+    std::vector<std::pair<uint64_t, std::shared_ptr<fv::LatticePlan>>> lattices;  // null plan: not a lattice
     double *scalar_buf = nullptr;
     size_t scalar_cap = 0;  // doubles
     fv::PinnedBuf plan_pin;  // host staging of the planning scalars of fv_simulate_dev
@@ -92,6 +93,15 @@ double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, c
 void run_direct(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int dim,
                 int prec, StageTimer *tm);
 void fill_report(StageTimer &tm, fv_report &r);
+// Lattice plan of an array (cached per array, tolerance and kernel width, with
+// its deconvolution tables for that width), null when the
+// East/North positions are not a lattice within tol metres.
+std::shared_ptr<LatticePlan> ctx_lattice(fv_ctx *ctx, const double *ant_host, int n_ant, double tol, int w);
+// The type-1 path (paper section 2.2.1) for a coplanar problem when its
+// antennas form a lattice and its fine grid is the smaller one; false when
+// the type-3 path should run instead.
+bool run_lattice(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int prec,
+                 StageTimer *tm, fv_report &r);
 void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv_report *rep);
 void server_free(Server *s);  // stops the workers (cancelling queued requests) and frees
 size_t request_footprint(fv_ctx *ctx, const fv_problem &p);

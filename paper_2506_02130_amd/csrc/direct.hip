@@ -128,35 +128,46 @@ __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, 
     }
 }
 
-// One wavefront folds the per-block partials (lane l takes blocks l, l + 64,
-// ...) by a butterfly across the lanes; every thread then helps gather the
-// frequencies and antenna positions.
+// The 256 threads fold the per-block partials (thread t takes blocks t,
+// t + 256, ...), then a butterfly across each wavefront's lanes and a pass
+// over the four wavefronts; every thread also helps gather the frequencies
+// and antenna positions.
 __global__ __launch_bounds__(256) void k_validate_reduce(const double *part, int nblk, const double *freq,
                                                          int n_freq, const double *ant, int n_ant, double *out) {
-    if (threadIdx.x < 64) {
-        const int l = threadIdx.x;
-        double v[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0, 0.0};
-        for (int b = l; b < nblk; b += 64) {
-            for (int k = 0; k < 6; k += 2) {
-                v[k] = fmin(v[k], part[8 * b + k]);
-                v[k + 1] = fmax(v[k + 1], part[8 * b + k + 1]);
-            }
-            v[6] += part[8 * b + 6];
-            v[7] += part[8 * b + 7];
+    __shared__ double wred[4][8];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double v[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0, 0.0};
+#pragma unroll 4
+    for (int b = t; b < nblk; b += 256) {
+        const double *q = part + 8 * (size_t)b;
+        for (int k = 0; k < 6; k += 2) {
+            v[k] = fmin(v[k], q[k]);
+            v[k + 1] = fmax(v[k + 1], q[k + 1]);
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            for (int k = 0; k < 6; k += 2) {
-                v[k] = fmin(v[k], __shfl_xor(v[k], off, 64));
-                v[k + 1] = fmax(v[k + 1], __shfl_xor(v[k + 1], off, 64));
-            }
-            v[6] += __shfl_xor(v[6], off, 64);
-            v[7] += __shfl_xor(v[7], off, 64);
-        }
-        if (l == 0)
-            for (int k = 0; k < 8; ++k) out[k] = v[k];
+        v[6] += q[6];
+        v[7] += q[7];
     }
-    for (int i = threadIdx.x; i < n_freq; i += 256) out[8 + i] = freq[i];
-    for (int i = threadIdx.x; i < 3 * n_ant; i += 256) out[8 + n_freq + i] = ant[i];
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int k = 0; k < 6; k += 2) {
+            v[k] = fmin(v[k], __shfl_xor(v[k], off, 64));
+            v[k + 1] = fmax(v[k + 1], __shfl_xor(v[k + 1], off, 64));
+        }
+        v[6] += __shfl_xor(v[6], off, 64);
+        v[7] += __shfl_xor(v[7], off, 64);
+    }
+    if (lane == 0)
+        for (int k = 0; k < 8; ++k) wred[wave][k] = v[k];
+    __syncthreads();
+    if (t < 8) {
+        double r = wred[0][t];
+        for (int w = 1; w < 4; ++w) {
+            const double x = wred[w][t];
+            r = t < 6 ? ((t & 1) ? fmax(r, x) : fmin(r, x)) : r + x;
+        }
+        out[t] = r;
+    }
+    for (int i = t; i < n_freq; i += 256) out[8 + i] = freq[i];
+    for (int i = t; i < 3 * n_ant; i += 256) out[8 + n_freq + i] = ant[i];
 }
 
 __global__ void k_zero_f64(double *p, long long n) {

@@ -241,6 +241,33 @@ struct ExecOpts {
     size_t cap = 0;          // > 0: refuse (set *too_big) when the workspace exceeds cap bytes
 };
 
+// Lattice of a coplanar array (paper section 2.2.1): every antenna offset
+// x_i - x_0 (East, North) is A k_i with k_i integer; A's columns are a
+// reduced basis (the shortest baseline and the shortest one not parallel to
+// it, Gauss-reduced).  K[a] = max - min of k[.][a].
+struct LatticePlan {
+    double A[2][2] = {{0, 0}, {0, 0}};  // A[r][c]: row r (East, North), column c (basis vector)
+    std::vector<int> k;                 // [n_ant][2]
+    int K[2] = {0, 0};
+    int w = 0;                          // kernel width the tables below are for
+    std::vector<double> dc;             // [N0 + N1] deconvolution factor per mode and axis
+};
+// True when the array's East/North positions form a lattice within `tol`
+// metres (n_ant >= 2, not collinear).
+bool find_lattice(const double *ant, int n_ant, double tol, LatticePlan *lp);
+// phihat(xi) of the ES kernel of width w (FP64 quadrature, host).
+double phihat_host(double xi, const double *qtab);  // qtab from quad_table
+
+// Type-1 path for a lattice array: every frequency of one problem.  `work`
+// holds lattice_work_bytes(); `stage` is pinned host staging.
+size_t lattice_work_bytes(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w);
+bool lattice_fits(const LatticePlan &lp, int prec_bits, int w);  // LDS limits of the kernels
+void lattice_tables(LatticePlan &lp, int w);  // fills lp.w and lp.dc (host, once per plan)
+void lattice_grid(const LatticePlan &lp, int w, int nf[2]);       // fine periodic grid per axis
+double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_host, int n_freq,
+                      const double *flux_dev, const double *beam_dev, int n_ant, int prec_bits, int w, double *vis_dev,
+                      void *work, PinnedBuf &stage, hipStream_t st, StageTimer *timer);
+
 // Enqueue the whole type-3 pipeline for jobs that share (dim, precision, w).
 // Allocates its workspace from `arena` (which must be idle); returns the
 // algorithmic HBM bytes of the grid stages.

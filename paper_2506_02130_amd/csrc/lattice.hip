@@ -1,0 +1,420 @@
+// Type-1 path for arrays whose antennas lie on a lattice (paper section
+// 2.2.1, evaluating the measurement equation for gridded arrays).  With the
+// lattice basis A (b = A k, k integer) the phase is b.s = k.(A^T s), so each
+// frequency is a type-1 transform from the points u_s = (nu / c) A^T s (turns,
+// taken mod 1 as k is integer) onto the integer modes k in [-K, K]^2, and
+// V(i, j) is the mode k_i - k_j.  The modes do not depend on the frequency;
+// only the points move.
+//
+//   k_t1_spread  one workgroup per (chunk of sources, frequency):
+//                the ES kernel of every source of the chunk is added into a
+//                private copy of the periodic fine grid in LDS (real: the
+//                strengths are real and no pre-phase is needed), which is
+//                then stored as the chunk's partial grid.
+//   k_t1_rows    one workgroup per (grid row, frequency): the partials of
+//                the row summed in FP64, then the DFT along axis 0 at the
+//                modes k0 (FP64).
+//   k_t1_cols    one workgroup per (mode k0, frequency): the DFT along
+//                axis 1 at the modes k1 and the deconvolution
+//                h / (alpha phihat(alpha k)) per axis (FP64).
+//   k_t1_out     V(i, j) = mode (k_i - k_j), written to the caller's layout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dev_common.h"
+#include "fv_internal.h"
+
+namespace fv {
+namespace {
+
+constexpr size_t kT1MaxLds = 128 * 1024;  // grid bytes one spreading workgroup may hold
+constexpr int kT1Cus = 256;               // compute units of the device
+constexpr int kT1MinChunk = 1024;         // fewest sources per spreading workgroup
+constexpr int kT1Threads = 1024;          // threads of a spreading workgroup (16 wavefronts share one grid)
+
+struct T1Params {
+    int nf[2], N[2], K[2];
+    int n_src, n_freq, n_ant, nchunk, chunk;
+    int gs[2];            // LDS grid extent per axis: nf + W - 1 (halo)
+    int wrap51;           // partials hold sums mod 2^64 whose low 51 bits are exact (FP32 path)
+    long long n_pairs;
+    double A[2][2];
+    double beta;
+    const double *src, *flux, *beam;
+    const double *kturn;  // [n_freq] nu / c
+    const double *dc;     // [N0 + N1] deconvolution factors
+    const int *kc;        // [n_ant][2] lattice coordinates
+    void *part;           // [n_freq][nchunk][nf1][nf0] 64-bit fixed point
+    double *part_scale;   // [n_freq][nchunk] value of one fixed-point unit
+    double2 *T;           // [n_freq][nf1][N0]
+    double2 *modes;       // [n_freq][N1][N0]
+    double *vis;
+};
+
+// ES kernel weight with hardware exp and sqrt in FP32 (about 1 ulp), the
+// exact form in FP64.
+__device__ __forceinline__ float t1_phi(float z, float beta) {
+    const float t = fmaxf(1.0f - z * z, 0.0f);
+    return __expf(beta * (__builtin_amdgcn_sqrtf(t) - 1.0f));
+}
+__device__ __forceinline__ double t1_phi(double z, double beta) { return es_phi(z, beta); }
+
+// Nearest integer of d as a 64-bit integer for |d| < 2^51: adding 1.5 * 2^52
+// leaves the rounded value in the low mantissa bits (two's complement).
+__device__ __forceinline__ long long fix64(double d) {
+    const double m = 6755399441055744.0;
+    return __double_as_longlong(d + m) - __double_as_longlong(m);
+}
+
+// The grid is accumulated in 64-bit fixed point with native LDS integer
+// atomics (LDS float atomics are several times slower).  A product d of
+// weights is turned into an integer by one FMA: d + 1.5 * 2^52 keeps
+// round(d) in the low 52 bits of its bit pattern (|d| < 2^51), whose value is
+// bits(1.5 * 2^52) + round(d).  The FP64 path subtracts that constant before
+// each add and bounds a chunk's sum by 2^62 (resolution about 2^-48 of the
+// chunk's largest strength per source at 16k sources).  The FP32 path adds the
+// raw bit patterns: the constant is a multiple of 2^51, so the low 51 bits of
+// the sum are exact while the chunk's sum stays within 2^50, and the partials
+// are sign-extended from bit 50 when they are read back (resolution about
+// 2^-36 of the largest strength, far below FP32 weights).  The sum does not
+// depend on the order of the additions.
+//
+// Largest |c| of the chunk's sources, reduced over the workgroup;
+// returns the fixed-point scale exponent S (n max|c| 2^S below 2^bound_bits)
+// and stores the value of one unit, 2^-S.  Also clears the LDS grid.
+__device__ int t1_chunk_scale(const T1Params &P, int f, int ch, int s0, int s1, unsigned long long *G, int ncell,
+                              int bound_bits) {
+    __shared__ double red[kT1Threads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double cm = 0.0;
+    for (int s = s0 + (int)threadIdx.x; s < s1; s += kT1Threads) {
+        double c = P.flux[(size_t)f * P.n_src + s];
+        if (P.beam) c *= P.beam[(size_t)f * P.n_src + s];
+        cm = fmax(cm, fabs(c));
+    }
+    for (int off = 32; off > 0; off >>= 1) cm = fmax(cm, __shfl_xor(cm, off, 64));
+    if (lane == 0) red[wave] = cm;
+    for (int i = threadIdx.x; i < ncell; i += kT1Threads) G[i] = 0ull;
+    __syncthreads();
+    cm = red[0];
+    for (int i = 1; i < kT1Threads / 64; ++i) cm = fmax(cm, red[i]);
+    // n cm < 2^e2, with n at least 2^(bound_bits - 50) so that one product
+    // also stays below 2^50 (the range of the FMA rounding)
+    const double n = fmax((double)(s1 - s0), ldexp(1.0, bound_bits - 50));
+    int e2 = 0;
+    frexp(n * cm * 1.0001 + 1e-300, &e2);
+    const int S = min(bound_bits - e2, 1000);  // an all-zero chunk keeps a finite scale
+    if (threadIdx.x == 0) P.part_scale[(size_t)f * P.nchunk + ch] = ldexp(1.0, -S);
+    return S;
+}
+
+// One source per lane: the lane computes its source's first cells and the
+// 2 W kernel weights in registers (c and the scale folded into the axis-1
+// weights) and adds its W x W footprint with W^2 atomic adds.  The LDS grid
+// carries a halo of W - 1 cells per axis, so no add wraps (the footprint's
+// columns are immediate offsets of one address); the halo is folded back when
+// the partial is stored.  Sixteen wavefronts share one LDS grid.
+template <typename R, int W>
+__global__ __launch_bounds__(kT1Threads) void k_t1_spread(T1Params P) {
+    extern __shared__ __align__(16) char smem[];
+    constexpr bool kWrap = sizeof(R) == 4;
+    const int nf0 = P.nf[0], nf1 = P.nf[1], g0 = P.gs[0], g1 = P.gs[1];
+    unsigned long long *G = (unsigned long long *)smem;  // [g1][g0] fixed point
+    const int f = blockIdx.y, ch = blockIdx.x;
+    const int s0 = ch * P.chunk, s1 = min(s0 + P.chunk, P.n_src);
+    const double scale = ldexp(1.0, t1_chunk_scale(P, f, ch, s0, s1, G, g0 * g1, kWrap ? 50 : 62));
+    const double kt = P.kturn[f];
+    const double magic = 6755399441055744.0;  // 1.5 * 2^52
+    const R beta = (R)P.beta, inv_hw = (R)(2.0 / W);
+    for (int s = s0 + (int)threadIdx.x; s < s1; s += kT1Threads) {
+        const double sx = P.src[3 * (size_t)s], sy = P.src[3 * (size_t)s + 1];
+        double c = P.flux[(size_t)f * P.n_src + s];
+        if (P.beam) c *= P.beam[(size_t)f * P.n_src + s];
+        int l[2];
+        double wd[2][W];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const double u = kt * (P.A[0][a] * sx + P.A[1][a] * sy);
+            const double g = (u - floor(u)) * P.nf[a];  // grid coordinate in [0, nf)
+            const double lc = ceil(g - 0.5 * W);         // first cell of the kernel
+            const R off = (R)(g - lc);
+            l[a] = (int)lc < 0 ? (int)lc + P.nf[a] : (int)lc;  // in [0, nf): the footprint ends below nf + W - 1
+            const double sc = a == 0 ? 1.0 : c * scale;
+#pragma unroll
+            for (int i = 0; i < W; ++i) wd[a][i] = sc * (double)t1_phi((R)((R)i - off) * inv_hw, beta);
+        }
+        unsigned long long *base = G + (size_t)l[1] * g0 + l[0];
+#pragma unroll
+        for (int iy = 0; iy < W; ++iy) {
+#pragma unroll
+            for (int ix = 0; ix < W; ++ix) {
+                const long long b = __double_as_longlong(fma(wd[1][iy], wd[0][ix], magic));
+                atomicAdd(&base[ix], (unsigned long long)(kWrap ? b : b - __double_as_longlong(magic)));
+            }
+            base += g0;
+        }
+    }
+    __syncthreads();
+    // fold the halo: cell (y, x) of the periodic grid gathers (y + a nf1, x + b nf0)
+    long long *out = (long long *)P.part + ((size_t)f * P.nchunk + ch) * ((size_t)nf0 * nf1);
+    for (int i = threadIdx.x; i < nf0 * nf1; i += kT1Threads) {
+        const int y = i / nf0, x = i - y * nf0;
+        unsigned long long v = G[(size_t)y * g0 + x];
+        const bool hx = x + nf0 < nf0 + W - 1, hy = y + nf1 < nf1 + W - 1;
+        if (hx) v += G[(size_t)y * g0 + x + nf0];
+        if (hy) v += G[(size_t)(y + nf1) * g0 + x];
+        if (hx && hy) v += G[(size_t)(y + nf1) * g0 + x + nf0];
+        out[i] = (long long)v;
+    }
+}
+
+// exp(-2 pi i m / n), FP64
+__device__ __forceinline__ double2 wneg(int m, int n) {
+    double s, c;
+    sincospi(2.0 * (double)m / (double)n, &s, &c);
+    return make_double2(c, -s);
+}
+
+__global__ __launch_bounds__(256) void k_t1_rows(T1Params P) {
+    extern __shared__ __align__(16) char smem[];
+    const int l1 = blockIdx.x, f = blockIdx.y;
+    const int nf0 = P.nf[0], nf1 = P.nf[1], ncell = nf0 * nf1;
+    double *row = (double *)smem;          // [nf0]
+    double2 *tw = (double2 *)(row + nf0);  // [nf0]
+    for (int l0 = threadIdx.x; l0 < nf0; l0 += 256) {
+        double acc = 0.0;
+        const size_t base = (size_t)f * P.nchunk * ncell + (size_t)l1 * nf0 + l0;
+        const long long *p = (const long long *)P.part + base;
+        const double *sc = P.part_scale + (size_t)f * P.nchunk;
+        for (int ch = 0; ch < P.nchunk; ++ch) {
+            long long v = p[(size_t)ch * ncell];
+            if (P.wrap51) v = (long long)((unsigned long long)v << 13) >> 13;  // sign-extend bit 50
+            acc += (double)v * sc[ch];
+        }
+        row[l0] = acc;
+        tw[l0] = wneg(l0, nf0);
+    }
+    __syncthreads();
+    for (int k0 = threadIdx.x; k0 < P.N[0]; k0 += 256) {
+        int kk = (k0 - P.K[0]) % nf0;
+        if (kk < 0) kk += nf0;
+        double re = 0.0, im = 0.0;
+        int m = 0;
+        for (int l0 = 0; l0 < nf0; ++l0) {
+            const double2 t = tw[m];
+            re += row[l0] * t.x;
+            im += row[l0] * t.y;
+            m += kk;
+            if (m >= nf0) m -= nf0;
+        }
+        P.T[((size_t)f * nf1 + l1) * P.N[0] + k0] = make_double2(re, im);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_t1_cols(T1Params P) {
+    extern __shared__ __align__(16) char smem[];
+    const int k0 = blockIdx.x, f = blockIdx.y;
+    const int nf1 = P.nf[1], N0 = P.N[0];
+    double2 *col = (double2 *)smem;  // [nf1]
+    double2 *tw = col + nf1;         // [nf1]
+    for (int l1 = threadIdx.x; l1 < nf1; l1 += 256) {
+        col[l1] = P.T[((size_t)f * nf1 + l1) * N0 + k0];
+        tw[l1] = wneg(l1, nf1);
+    }
+    __syncthreads();
+    const double d0 = P.dc[k0];
+    for (int k1 = threadIdx.x; k1 < P.N[1]; k1 += 256) {
+        int kk = (k1 - P.K[1]) % nf1;
+        if (kk < 0) kk += nf1;
+        double re = 0.0, im = 0.0;
+        int m = 0;
+        for (int l1 = 0; l1 < nf1; ++l1) {
+            const double2 v = col[l1], t = tw[m];
+            re += v.x * t.x - v.y * t.y;
+            im += v.x * t.y + v.y * t.x;
+            m += kk;
+            if (m >= nf1) m -= nf1;
+        }
+        const double d = d0 * P.dc[N0 + k1];
+        P.modes[((size_t)f * P.N[1] + k1) * N0 + k0] = make_double2(re * d, im * d);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_t1_out(T1Params P) {
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int f = blockIdx.y;
+    if (p >= P.n_pairs) return;
+    int i, j;
+    pair_decode(p, P.n_ant, &i, &j);
+    const int d0 = P.kc[2 * i] - P.kc[2 * j] + P.K[0], d1 = P.kc[2 * i + 1] - P.kc[2 * j + 1] + P.K[1];
+    const double2 v = P.modes[((size_t)f * P.N[1] + d1) * P.N[0] + d0];
+    double *o = P.vis + 2 * ((size_t)f * P.n_pairs + p);
+    o[0] = v.x;
+    o[1] = v.y;
+}
+
+struct T1Shape {
+    int nf[2], N[2], gs[2];
+    int nchunk, chunk;
+    size_t lds;  // spreading workgroup's LDS grid bytes
+    size_t part_bytes, t_bytes, mode_bytes, tab_bytes;
+};
+
+T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w) {
+    T1Shape s;
+    for (int a = 0; a < 2; ++a) {
+        s.N[a] = 2 * lp.K[a] + 1;
+        s.nf[a] = next_smooth_even(std::max<long long>((long long)std::ceil(kSigma * s.N[a]), 2LL * w));
+    }
+    s.gs[0] = s.nf[0] + w - 1;
+    s.gs[1] = s.nf[1] + w - 1;
+    s.lds = (size_t)s.gs[0] * s.gs[1] * 8;
+    // chunks per frequency: about one round of workgroups over the device
+    // (as many per compute unit as their LDS grids allow), at least
+    // kT1MinChunk sources each
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, 160 * 1024 / (s.lds + 1024)));
+    const int slots = kT1Cus * per_cu;
+    s.nchunk = std::max(1, (slots + n_freq / 2) / std::max(n_freq, 1));
+    s.nchunk = std::max(1, std::min(s.nchunk, n_src / kT1MinChunk));
+    s.chunk = std::max(1, (n_src + s.nchunk - 1) / s.nchunk);
+    s.nchunk = std::max(1, (n_src + s.chunk - 1) / s.chunk);
+    const size_t cells = (size_t)s.nf[0] * s.nf[1];
+    s.part_bytes = (size_t)n_freq * s.nchunk * (cells * 8 + 8);
+    s.t_bytes = (size_t)n_freq * s.nf[1] * s.N[0] * sizeof(double2);
+    s.mode_bytes = (size_t)n_freq * s.N[0] * s.N[1] * sizeof(double2);
+    s.tab_bytes = sizeof(double) * ((size_t)n_freq + s.N[0] + s.N[1]) + sizeof(int) * 2 * (size_t)n_ant;
+    return s;
+}
+
+size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+template <typename R, int W>
+void spread_w(dim3 g, size_t lds, hipStream_t st, const T1Params &P) {
+    if (lds > 65536)
+        FV_HIP(hipFuncSetAttribute((const void *)k_t1_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+    hipLaunchKernelGGL((k_t1_spread<R, W>), g, dim3(kT1Threads), lds, st, P);
+}
+
+template <typename R, int... Ws>
+void spread_pick(int w, dim3 g, size_t lds, hipStream_t st, const T1Params &P, std::integer_sequence<int, Ws...>) {
+    bool done = false;
+    ((w == Ws ? (spread_w<R, Ws>(g, lds, st, P), done = true) : false), ...);
+    if (!done) fail(FV_EUNSUPPORTED, "kernel width out of range");
+}
+
+}  // namespace
+
+void lattice_tables(LatticePlan &lp, int w) {
+    const T1Shape sh = t1_shape(lp, 1, 1, 1, 32, w);
+    double qtab[2 * kQuadHalf];
+    quad_table(w, qtab);
+    lp.dc.resize((size_t)sh.N[0] + sh.N[1]);
+    for (int a = 0, o = 0; a < 2; o += sh.N[a], ++a) {
+        const double h = 2.0 * M_PI / sh.nf[a], alpha = w * h / 2.0;
+        for (int k = 0; k < sh.N[a]; ++k) lp.dc[o + k] = h / (alpha * phihat_host(alpha * (k - lp.K[a]), qtab));
+    }
+    lp.w = w;
+}
+
+void lattice_grid(const LatticePlan &lp, int w, int nf[2]) {
+    const T1Shape s = t1_shape(lp, 1, 1, 1, 32, w);
+    nf[0] = s.nf[0];
+    nf[1] = s.nf[1];
+}
+
+bool lattice_fits(const LatticePlan &lp, int prec_bits, int w) {
+    const T1Shape s = t1_shape(lp, 1, 1, 1, prec_bits, w);
+    (void)prec_bits;
+    return s.lds <= kT1MaxLds;  // the fixed-point grid with its halo must fit in LDS
+}
+
+size_t lattice_work_bytes(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w) {
+    const T1Shape s = t1_shape(lp, n_src, n_freq, n_ant, prec_bits, w);
+    return al256(s.part_bytes) + al256(s.t_bytes) + al256(s.mode_bytes) + al256(s.tab_bytes) + 256;
+}
+
+double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_host, int n_freq,
+                      const double *flux_dev, const double *beam_dev, int n_ant, int prec_bits, int w, double *vis_dev,
+                      void *work, PinnedBuf &stage, hipStream_t st, StageTimer *tm) {
+    StageTimer dummy;
+    if (!tm) tm = &dummy;
+    const T1Shape sh = t1_shape(lp, n_src, n_freq, n_ant, prec_bits, w);
+    char *wp = (char *)work;
+    T1Params P;
+    std::memset(&P, 0, sizeof(P));
+    for (int a = 0; a < 2; ++a) {
+        P.nf[a] = sh.nf[a];
+        P.N[a] = sh.N[a];
+        P.K[a] = lp.K[a];
+        P.A[0][a] = lp.A[0][a];
+        P.A[1][a] = lp.A[1][a];
+    }
+    P.n_src = n_src;
+    P.n_freq = n_freq;
+    P.n_ant = n_ant;
+    P.nchunk = sh.nchunk;
+    P.chunk = sh.chunk;
+    P.gs[0] = sh.gs[0];
+    P.gs[1] = sh.gs[1];
+    P.wrap51 = prec_bits == 32;
+    P.n_pairs = (long long)n_ant * (n_ant + 1) / 2;
+    P.beta = 2.3 * w;
+    P.src = src_dev;
+    P.flux = flux_dev;
+    P.beam = beam_dev;
+    P.vis = vis_dev;
+    P.part = wp;
+    P.part_scale = (double *)(wp + (size_t)n_freq * sh.nchunk * ((size_t)sh.nf[0] * sh.nf[1]) * 8);
+    wp += al256(sh.part_bytes);
+    P.T = (double2 *)wp;
+    wp += al256(sh.t_bytes);
+    P.modes = (double2 *)wp;
+    wp += al256(sh.mode_bytes);
+    // tables: nu / c per frequency, deconvolution factors per axis, lattice coordinates
+    char *tab = wp;
+    char *host = (char *)stage.get(sh.tab_bytes);
+    double *hk = (double *)host, *hdc = hk + n_freq;
+    for (int f = 0; f < n_freq; ++f) hk[f] = freq_host[f] / kCLight;
+    if (lp.w != w || lp.dc.size() != (size_t)(sh.N[0] + sh.N[1])) fail(FV_EDEVICE, "lattice tables not prepared");
+    std::memcpy(hdc, lp.dc.data(), sizeof(double) * lp.dc.size());
+    std::memcpy(hdc + sh.N[0] + sh.N[1], lp.k.data(), sizeof(int) * 2 * (size_t)n_ant);
+    FV_HIP(hipMemcpyAsync(tab, host, sh.tab_bytes, hipMemcpyHostToDevice, st));
+    stage.record(st);
+    P.kturn = (const double *)tab;
+    P.dc = P.kturn + n_freq;
+    P.kc = (const int *)(P.dc + sh.N[0] + sh.N[1]);
+
+    const size_t cells = (size_t)sh.nf[0] * sh.nf[1];
+    using WL = std::integer_sequence<int, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
+    tm->begin(FV_STAGE_SPREAD, st);
+    const dim3 gs((unsigned)sh.nchunk, (unsigned)n_freq);
+    if (prec_bits == 32)
+        spread_pick<float>(w, gs, sh.lds, st, P, WL{});
+    else
+        spread_pick<double>(w, gs, sh.lds, st, P, WL{});
+    tm->end(st);
+    tm->add(FV_STAGE_SPREAD,
+            (double)n_freq * ((double)n_src * (16.0 + (beam_dev ? 8.0 : 0.0)) + (double)sh.part_bytes / n_freq), 1);
+    tm->begin(FV_STAGE_FFT_X, st);
+    hipLaunchKernelGGL(k_t1_rows, dim3((unsigned)sh.nf[1], (unsigned)n_freq), dim3(256),
+                       (size_t)sh.nf[0] * (8 + 16), st, P);
+    tm->end(st);
+    tm->add(FV_STAGE_FFT_X, (double)sh.part_bytes + (double)sh.t_bytes, 1);
+    tm->begin(FV_STAGE_FFT_Y, st);
+    hipLaunchKernelGGL(k_t1_cols, dim3((unsigned)sh.N[0], (unsigned)n_freq), dim3(256), (size_t)sh.nf[1] * 32, st,
+                       P);
+    tm->end(st);
+    tm->add(FV_STAGE_FFT_Y, (double)sh.t_bytes + (double)sh.mode_bytes, 1);
+    tm->begin(FV_STAGE_INTERP, st);
+    hipLaunchKernelGGL(k_t1_out, dim3((unsigned)((P.n_pairs + 255) / 256), (unsigned)n_freq), dim3(256), 0, st, P);
+    tm->end(st);
+    tm->add(FV_STAGE_INTERP, (double)n_freq * (double)P.n_pairs * 16.0 + (double)sh.mode_bytes, 1);
+    FV_HIP(hipGetLastError());
+    return (double)sh.part_bytes + 2.0 * sh.t_bytes + 2.0 * sh.mode_bytes + 16.0 * n_freq * P.n_pairs;
+}
+
+}  // namespace fv

@@ -264,4 +264,78 @@ std::vector<int> target_order(const double *ant, const GeomPlan &g) {
     return perm;
 }
 
+bool find_lattice(const double *ant, int n_ant, double tol, LatticePlan *lp) {
+    if (n_ant < 2) return false;
+    // shortest baseline, then the shortest one not parallel to it
+    double b1[2] = {0, 0}, l1 = std::numeric_limits<double>::infinity();
+    for (int i = 0; i < n_ant; ++i)
+        for (int j = i + 1; j < n_ant; ++j) {
+            const double dx = ant[3 * (size_t)i] - ant[3 * (size_t)j], dy = ant[3 * (size_t)i + 1] - ant[3 * (size_t)j + 1];
+            const double l = std::hypot(dx, dy);
+            if (l > tol && l < l1) {
+                l1 = l;
+                b1[0] = dx;
+                b1[1] = dy;
+            }
+        }
+    if (!std::isfinite(l1)) return false;
+    double b2[2] = {0, 0}, l2 = std::numeric_limits<double>::infinity();
+    for (int i = 0; i < n_ant; ++i)
+        for (int j = i + 1; j < n_ant; ++j) {
+            const double dx = ant[3 * (size_t)i] - ant[3 * (size_t)j], dy = ant[3 * (size_t)i + 1] - ant[3 * (size_t)j + 1];
+            const double l = std::hypot(dx, dy);
+            if (l <= tol || l >= l2) continue;
+            if (std::fabs(b1[0] * dy - b1[1] * dx) > 1e-6 * l1 * l) {
+                l2 = l;
+                b2[0] = dx;
+                b2[1] = dy;
+            }
+        }
+    if (!std::isfinite(l2)) return false;  // collinear
+    // Gauss reduction
+    for (int it = 0; it < 64; ++it) {
+        double n1 = b1[0] * b1[0] + b1[1] * b1[1], n2 = b2[0] * b2[0] + b2[1] * b2[1];
+        if (n2 < n1) {
+            std::swap(b1[0], b2[0]);
+            std::swap(b1[1], b2[1]);
+            std::swap(n1, n2);
+        }
+        const double mu = std::nearbyint((b1[0] * b2[0] + b1[1] * b2[1]) / n1);
+        if (mu == 0.0) break;
+        b2[0] -= mu * b1[0];
+        b2[1] -= mu * b1[1];
+    }
+    const double det = b1[0] * b2[1] - b1[1] * b2[0];
+    if (!(std::fabs(det) > 0)) return false;
+    lp->A[0][0] = b1[0];
+    lp->A[1][0] = b1[1];
+    lp->A[0][1] = b2[0];
+    lp->A[1][1] = b2[1];
+    lp->k.assign(2 * (size_t)n_ant, 0);
+    int lo[2] = {0, 0}, hi[2] = {0, 0};
+    for (int i = 0; i < n_ant; ++i) {
+        const double dx = ant[3 * (size_t)i] - ant[0], dy = ant[3 * (size_t)i + 1] - ant[1];
+        // solve A k = d (2 x 2, Cramer), round, check
+        const double k0 = (dx * b2[1] - dy * b2[0]) / det, k1 = (b1[0] * dy - b1[1] * dx) / det;
+        const double r0 = std::nearbyint(k0), r1 = std::nearbyint(k1);
+        const double ex = r0 * b1[0] + r1 * b2[0] - dx, ey = r0 * b1[1] + r1 * b2[1] - dy;
+        if (std::hypot(ex, ey) > tol || std::fabs(r0) > 1e6 || std::fabs(r1) > 1e6) return false;
+        lp->k[2 * (size_t)i] = (int)r0;
+        lp->k[2 * (size_t)i + 1] = (int)r1;
+        for (int a = 0; a < 2; ++a) {
+            lo[a] = std::min(lo[a], lp->k[2 * (size_t)i + a]);
+            hi[a] = std::max(hi[a], lp->k[2 * (size_t)i + a]);
+        }
+    }
+    lp->K[0] = hi[0] - lo[0];
+    lp->K[1] = hi[1] - lo[1];
+    return true;
+}
+
+double phihat_host(double xi, const double *q) {
+    double acc = 0.0;
+    for (int i = 0; i < kQuadHalf; ++i) acc += q[kQuadHalf + i] * std::cos(xi * q[i]);
+    return acc;
+}
+
 }  // namespace fv

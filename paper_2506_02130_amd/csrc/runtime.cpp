@@ -312,6 +312,52 @@ void validate_host(const fv_problem *p) {
     if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6) fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
 }
 
+std::shared_ptr<LatticePlan> ctx_lattice(fv_ctx *ctx, const double *ant_host, int n_ant, double tol, int w) {
+    std::lock_guard<std::mutex> lk(ctx->geo_mu);
+    uint64_t key = fnv1a(ant_host, sizeof(double) * 3 * (size_t)n_ant);
+    key = fnv1a(&tol, sizeof(tol), key);
+    key = fnv1a(&w, sizeof(w), key);
+    for (auto &e : ctx->lattices)
+        if (e.first == key) return e.second;
+    std::shared_ptr<LatticePlan> lp(new LatticePlan);
+    if (!find_lattice(ant_host, n_ant, tol, lp.get()))
+        lp.reset();
+    else if (lattice_fits(*lp, 64, w))
+        lattice_tables(*lp, w);
+    ctx->lattices.push_back({key, lp});
+    if (ctx->lattices.size() > 64) ctx->lattices.erase(ctx->lattices.begin());
+    return lp;
+}
+
+bool run_lattice(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int prec,
+                 StageTimer *tm, fv_report &r) {
+    double numax = 0.0;
+    for (int f = 0; f < p.n_freq; ++f) numax = std::max(numax, p.freq_hz[f]);
+    const double tol = p.eps * kCLight / (20.0 * M_PI * numax);
+    const int w = kernel_width(p.eps);
+    std::shared_ptr<LatticePlan> lp = ctx_lattice(ctx, p.ant_enu, p.n_ant, tol, w);
+    if (!lp) return false;
+    if (!lattice_fits(*lp, prec, w)) return false;
+    int nf[2];
+    lattice_grid(*lp, w, nf);
+    GeomPlan g = ctx_geometry(ctx, p.ant_enu, p.n_ant, 2, p.eps, in.s_c, in.S, !(p.flags & FV_NO_FOLD));
+    const SnapPlan top = plan_snapshot(g, numax);
+    if ((double)nf[0] * nf[1] > (double)top.n1[0] * top.n1[1]) return false;
+    const size_t need = lattice_work_bytes(*lp, p.n_src, p.n_freq, p.n_ant, prec, w);
+    slot.arena.ensure(need);
+    slot.arena.reset();
+    void *work = slot.arena.take(need);
+    r.model_bytes += launch_lattice(*lp, in.src, p.n_src, p.freq_hz, p.n_freq, in.flux, in.beam, p.n_ant, prec, w,
+                                    vis_dev, work, slot.arena.host, slot.stream, tm);
+    r.lattice = 1;
+    r.w = w;
+    r.n1[0] = nf[0];
+    r.n1[1] = nf[1];
+    r.n2[0] = nf[0];
+    r.n2[1] = nf[1];
+    return true;
+}
+
 // NUFFT jobs (one per frequency) of one problem whose inputs are on the
 // device; keeps the target table alive through `hold`.
 NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in, double *vis_dev, hipStream_t st,
@@ -432,6 +478,8 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
         launch_zero_c128(vis_dev, n_pairs * n_freq, st);
     } else if (method != FV_METHOD_NUFFT) {
         run_direct(ctx, slot, *p, in, vis_dev, dim, prec, &tm);
+    } else if (dim == 2 && !(p->flags & FV_NO_LATTICE) && run_lattice(ctx, slot, *p, in, vis_dev, prec, &tm, r)) {
+        // type-1 path done
     } else {
         std::vector<SnapJob> jobs;
         std::vector<std::shared_ptr<TargetTable>> hold;

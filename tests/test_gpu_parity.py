@@ -22,26 +22,34 @@ def ctx(gpu_lib):
 
 
 # ---------------------------------------------------------------- end to end
-def test_config1_full_output_fp64(gpu_lib, ctx):
+@pytest.mark.parametrize("no_lattice", [False, True])
+def test_config1_full_output_fp64(gpu_lib, ctx, no_lattice):
+    # the 37-antenna hex array is a lattice: the type-1 path by default, the
+    # type-3 path when it is switched off
     p = synth.config1()
-    v, rep = _run(gpu_lib, ctx, p)
+    v, rep = _run(gpu_lib, ctx, p, flags=gpu_lib.NO_LATTICE if no_lattice else 0)
     ref = oracle.direct_problem(p)
-    assert rep["prec_bits"] == 64 and rep["dim"] == 2
+    assert rep["prec_bits"] == 64 and rep["dim"] == 2 and rep["lattice"] == (0 if no_lattice else 1)
     assert oracle.rel_l2(v, ref) <= p.eps
 
 
+@pytest.mark.parametrize("no_lattice", [False, True])
 @pytest.mark.parametrize("eps", [1e-4, 1e-5, 1e-6, 1e-8, 1e-10, 1e-12])
-def test_small_2d_eps_sweep(gpu_lib, ctx, eps):
+def test_small_2d_eps_sweep(gpu_lib, ctx, eps, no_lattice):
+    # hex array: type-1 lattice path by default, type-3 with it switched off
     p = synth.small_problem(31, n_ant=40, n_src=700, n_freq=3, hex_layout=True)
-    v, rep = _run(gpu_lib, ctx, p, eps=eps)
+    v, rep = _run(gpu_lib, ctx, p, eps=eps, flags=gpu_lib.NO_LATTICE if no_lattice else 0)
+    assert rep["lattice"] == (0 if no_lattice else 1)
     ref = oracle.direct_problem(p)
     assert oracle.rel_l2(v, ref) <= eps
 
 
-def test_eps_sweep_error_is_monotone(gpu_lib, ctx):
+@pytest.mark.parametrize("no_lattice", [False, True])
+def test_eps_sweep_error_is_monotone(gpu_lib, ctx, no_lattice):
     p = synth.small_problem(32, n_ant=30, n_src=500, n_freq=2, hex_layout=True)
     ref = oracle.direct_problem(p)
-    errs = [oracle.rel_l2(_run(gpu_lib, ctx, p, eps=e)[0], ref) for e in (1e-3, 1e-5, 1e-7, 1e-9, 1e-11)]
+    fl = gpu_lib.NO_LATTICE if no_lattice else 0
+    errs = [oracle.rel_l2(_run(gpu_lib, ctx, p, eps=e, flags=fl)[0], ref) for e in (1e-3, 1e-5, 1e-7, 1e-9, 1e-11)]
     assert all(b < a for a, b in zip(errs, errs[1:])), errs
 
 
@@ -231,12 +239,12 @@ def test_device_pointer_path_matches_host_path(gpu_lib, ctx):
 
 def test_fp32_single_frequency(gpu_lib, ctx):
     p = synth.small_problem(31, n_ant=40, n_src=700, n_freq=1, hex_layout=True)
-    v, rep = _run(gpu_lib, ctx, p, eps=1e-4)
+    v, rep = _run(gpu_lib, ctx, p, eps=1e-4, flags=gpu_lib.NO_LATTICE)
     assert oracle.rel_l2(v, oracle.direct_problem(p)) <= 1e-4
 
 
 def test_fp64_multi_frequency(gpu_lib, ctx):
     p = synth.small_problem(31, n_ant=40, n_src=700, n_freq=3, hex_layout=True)
-    v, rep = _run(gpu_lib, ctx, p, eps=1e-10)
+    v, rep = _run(gpu_lib, ctx, p, eps=1e-10, flags=gpu_lib.NO_LATTICE)
     errs = [oracle.rel_l2(v[f], oracle.direct_problem(p)[f]) for f in range(3)]
     assert max(errs) <= 1e-10, errs
