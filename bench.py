@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+LDS_PEAK_GBS = 256 * 128 * 2.4  # MI355X LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (packed)
 FP32_MATRIX_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix cores
 METRIC = "src×baseline pairs/s at 1e-6 rel err, NUFFT vs direct DFT; p99 latency"
@@ -42,20 +43,28 @@ def _pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def _kernel_source_hash() -> str:
+# device sources of the kernels of each path (the byte counters of a path stay
+# valid while these files are unchanged)
+PATH_SOURCES = {"type1": ["lattice.hip", "dev_common.h"],
+                "type3": ["nufft_impl.h", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip", "nufft_f64_2d.hip",
+                          "nufft_f64_3d.hip", "dev_common.h"]}
+
+
+def _kernel_source_hash(files=None) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2506_02130_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, fn), "rb").read())
+    names = files if files is not None else sorted(fn for fn in os.listdir(csrc) if fn.endswith((".hip", ".h", ".cpp")))
+    for fn in names:
+        h.update(fn.encode())
+        h.update(open(os.path.join(csrc, fn), "rb").read())
     return h.hexdigest()[:16]
 
 
-def _traffic_from_profiles(stage: str):
+def _traffic_from_profiles(stage: str, path_name: str):
     """HBM bytes per launch of a stage, from a committed pair of rocprofv3
     --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the calibration copy
-    (profiles/traffic_c2.json), only if they were taken on the current kernel
-    sources."""
+    (profiles/traffic_c2.json), only while the device sources of the path they
+    were taken on are unchanged."""
     path = os.path.join(ROOT, "profiles", "traffic_c2.json")
     if not os.path.exists(path):
         return None
@@ -63,7 +72,8 @@ def _traffic_from_profiles(stage: str):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_hash") != _kernel_source_hash():
+    files = d.get("sources")
+    if d.get("path") != path_name or not files or d.get("source_hash") != _kernel_source_hash(files):
         return None
     k = d.get("stages", {}).get(stage)
     return None if k is None else k.get("bytes_per_launch")
@@ -84,8 +94,8 @@ def reduce_traffic(fetch_csv: str, write_csv: str, calib_mib: int, cmd: str, wor
     KiB per dispatch), each scaled by what the same counter reads for the M MiB
     device copy issued after the timed steps.  Rows are the dispatches of the
     last step (from its input-check kernel to the copy).  Writes
-    profiles/traffic_c2.json (read back by the roofline, tagged with the kernel
-    source hash) and prints a markdown table."""
+    profiles/traffic_c2.json (read back by the roofline, tagged with a hash of
+    the path's device sources) and prints a markdown table."""
     import csv
 
     def load(path):
@@ -122,7 +132,9 @@ def reduce_traffic(fetch_csv: str, write_csv: str, calib_mib: int, cmd: str, wor
         e["launches"] += 1
     for e in stages.values():
         e["bytes_per_launch"] = (e["fetch_bytes"] + e["write_bytes"]) / e["launches"]
-    d = {"source_hash": _kernel_source_hash(), "command": cmd, "workload": workload,
+    path = "type1" if any(x[0].startswith("k_t1_") for x in fetch) else "type3"
+    d = {"path": path, "sources": PATH_SOURCES[path], "source_hash": _kernel_source_hash(PATH_SOURCES[path]),
+         "command": cmd, "workload": workload,
          "calibration": {"copy_MiB": calib_mib, "FETCH_SIZE_KiB": fetch[ci][1], "WRITE_SIZE_KiB": write[ci][1],
                          "fetch_scale": f_scale, "write_scale": w_scale},
          "stages": stages}
@@ -134,6 +146,21 @@ def reduce_traffic(fetch_csv: str, write_csv: str, calib_mib: int, cmd: str, wor
     print("|---|---|---|---|---|---|")
     for name, st, fk, wk, fb, wb in rows:
         print(f"| `{name}` | {st or '-'} | {fk:.0f} | {wk:.0f} | {fb / 1e6:.2f} | {wb / 1e6:.2f} |")
+
+
+def stats_md(path: str):
+    """Markdown table (kernel, calls, average, total, share) of a rocprofv3
+    --kernel-trace --stats kernel summary CSV."""
+    import csv
+    import re
+
+    rows = list(csv.DictReader(open(path)))
+    tot = sum(int(r["TotalDurationNs"]) for r in rows)
+    print("| kernel | calls | avg us | total us | % |\n|---|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -int(r["TotalDurationNs"])):
+        name = re.sub(r"\(.*$", "", re.sub(r"fv::\(anonymous namespace\)::", "", re.sub(r"^void ", "", r["Name"])))
+        print(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {int(r['TotalDurationNs']) / 1e3:.1f} | "
+              f"{100 * int(r['TotalDurationNs']) / tot:.1f} |")
 
 
 def serving_leg(fv, synth, np, n_req: int) -> dict:
@@ -227,9 +254,16 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving mix leg")
+    ap.add_argument("--path", choices=("auto", "type3"), default="auto",
+                    help="auto: the library's choice (type 1 for lattice arrays); type3: force the type-3 path")
+    ap.add_argument("--stats-md", metavar="KERNEL_STATS_CSV",
+                    help="no run: print a markdown table of a rocprofv3 --stats kernel summary")
     ap.add_argument("--reduce-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no run: reduce two counter-collection CSVs of a --profile --calib-copy-mib run")
     args = ap.parse_args()
+    if args.stats_md:
+        stats_md(args.stats_md)
+        return
     if args.reduce_traffic:
         cmd = ("rocprofv3 --pmc COUNTER --output-format csv -d <out> -o run -- python3 bench.py --profile "
                f"--steps 2 --warmup 1 --calib-copy-mib {args.calib_copy_mib or 256}")
@@ -265,7 +299,7 @@ def main():
     pairs_per_step = float(p.n_src) * p.n_pairs * p.n_freq
     # with --autotune the FFT launch shape is tuned on the first warm-up call (cached after)
     tune = fv.AUTOTUNE if args.autotune else 0
-    flags = fv.TIMING | tune
+    flags = fv.TIMING | tune | (fv.NO_LATTICE if args.path == "type3" else 0)
 
     def step(fl=flags):
         return ctx.simulate_dev(ant, src, freq, flux, beam, vis, eps=p.eps, flags=fl, stream=stream)
@@ -306,11 +340,26 @@ def main():
     per_launch_ms = stage_ms[dom] / max(stage_launch[dom], 1)
     per_launch_bytes = stage_bytes[dom] / max(stage_launch[dom], 1)
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-    kernels = KERNEL_OF_STAGE_T1 if reps[-1].get("lattice") else KERNEL_OF_STAGE
-    roofline = {"bound": "hbm", "kernel": kernels.get(dom, dom), "stage": dom, "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": _traffic_from_profiles(dom),
-                "avg_launch_ms": per_launch_ms, "bytes_per_launch": per_launch_bytes}
+    lattice = bool(reps[-1].get("lattice"))
+    kernels = KERNEL_OF_STAGE_T1 if lattice else KERNEL_OF_STAGE
+    traffic = _traffic_from_profiles(dom, "type1" if lattice else "type3")
+    if lattice and dom == "spread":
+        # The type-1 spread is bound by LDS atomic adds, not HBM: its
+        # algorithmic LDS bytes are one 8-byte read-modify-write per source,
+        # frequency and footprint cell (n_freq n_src w^2), against the LDS
+        # bandwidth of the chip; its HBM bytes per launch are kept beside.
+        w = reps[-1]["w"]
+        lds_bytes = float(p.n_freq) * p.n_src * w * w * 8.0
+        lds_achieved = lds_bytes / (per_launch_ms * 1e-3) / 1e9
+        roofline = {"bound": "alu", "resource": "LDS (64-bit integer atomic adds)", "kernel": kernels[dom],
+                    "stage": dom, "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                    "frac": lds_achieved / LDS_PEAK_GBS, "traffic": traffic, "avg_launch_ms": per_launch_ms,
+                    "lds_bytes_per_launch": lds_bytes, "hbm_bytes_per_launch": per_launch_bytes,
+                    "hbm_achieved": achieved}
+    else:
+        roofline = {"bound": "hbm", "kernel": kernels.get(dom, dom), "stage": dom, "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "avg_launch_ms": per_launch_ms, "bytes_per_launch": per_launch_bytes}
     stages = {n: {"ms": round(stage_ms[n], 4), "launches": stage_launch[n],
                   "GBps": (stage_bytes[n] / max(stage_launch[n], 1)) / (stage_ms[n] / max(stage_launch[n], 1) * 1e-3)
                   / 1e9 if stage_ms[n] > 0 else None}

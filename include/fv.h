@@ -137,7 +137,10 @@ fv_status fv_simulate(fv_ctx *ctx, const fv_problem *p, double *vis, fv_report *
  * pointers on the context's device.  The work is enqueued on `stream`
  * (a hipStream_t; NULL = the null stream).  The call blocks only for the few
  * scalars planning needs (antenna positions, frequencies, the source box);
- * the buffers must stay alive until the stream has completed the work. */
+ * the buffers must stay alive until the stream has completed the work.
+ * Successive calls on one context are ordered: a call made on another stream
+ * first waits (on the device) for the previous call's work, whose workspace it
+ * reuses. */
 fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *stream, fv_report *rep);
 
 /* Many snapshots (each a problem with its own sources, frequencies and

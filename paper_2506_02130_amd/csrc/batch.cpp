@@ -70,6 +70,7 @@ void simulate_batch(fv_ctx *ctx, Slot &slot, int n, const fv_problem *ps, double
     }
     FV_HIP(hipSetDevice(ctx->device));
     hipStream_t st = slot.stream;
+    if (slot.done) FV_HIP(hipStreamWaitEvent(st, slot.done, 0));  // a device-entry call's work
     std::vector<BatchInputs> bi = upload_batch(slot, n, ps);
     fv_report r;
     std::memset(&r, 0, sizeof(r));

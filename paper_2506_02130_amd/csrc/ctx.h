@@ -21,6 +21,10 @@ struct DevInputs {
     const double *ant = nullptr, *src = nullptr, *flux = nullptr, *beam = nullptr;
     double *vis = nullptr;
     double s_c[3] = {0, 0, 0}, S[3] = {0, 0, 0};
+    // device input check's block partials (largest |flux beam| per flat range
+    // of cmax_span values), or null
+    const double *cmax = nullptr;
+    long long cmax_span = 0;
 };
 
 // A stream with its own workspace and input arenas.
@@ -31,6 +35,10 @@ struct Slot {
     Arena inputs;  // uploaded inputs and the device output
     StageTimer timer;
     GraphCache graphs;  // launch graphs captured on this slot's workspace
+    // end of the last call's work on the caller's stream (device entry
+    // point): the next call, on any stream, waits for it before it reuses the
+    // workspace
+    hipEvent_t done = nullptr;
     ~Slot();
 };
 

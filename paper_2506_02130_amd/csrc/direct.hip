@@ -62,30 +62,41 @@ __global__ __launch_bounds__(256) void k_direct(const double *ant, int n_ant, lo
 
 // Input check of the device entry point, one pass over the inputs: per block,
 // min and max of each direction component, the count of non-unit or
-// non-finite directions and the count of non-finite strengths (flux and beam,
-// 16-byte loads when aligned); k_validate_reduce folds the block partials and
+// non-finite directions, and over the block's contiguous range of the
+// strengths the count of non-finite flux and beam values (16-byte loads when
+// aligned) and the largest |flux beam|; k_validate_reduce folds the block partials and
 // gathers the frequencies and antenna positions behind them, so that the host
 // fetches every planning scalar with one copy.
-__device__ __forceinline__ int count_nonfinite(const double *x, long long n, long long tid, long long nth) {
-    int bad = 0;
+// Non-finite flux and beam values of x[0..n) (beam b may be null) and the
+// largest |x b|; 16-byte loads when both arrays are 16-byte aligned.
+__device__ __forceinline__ void check_strengths(const double *x, const double *b, long long n, int t, int nth,
+                                                int &bad, double &cm) {
     long long done = 0;
-    if (((uintptr_t)x & 15) == 0) {
-        const double2 *x2 = (const double2 *)x;
+    if (((uintptr_t)x & 15) == 0 && ((uintptr_t)b & 15) == 0) {
         const long long n2 = n / 2;
-        for (long long i = tid; i < n2; i += nth) {
-            const double2 v = x2[i];
+        for (long long i = t; i < n2; i += nth) {
+            const double2 v = ((const double2 *)x)[i];
+            double2 g = make_double2(1.0, 1.0);
+            if (b) {
+                g = ((const double2 *)b)[i];
+                bad += !isfinite(g.x);
+                bad += !isfinite(g.y);
+            }
             bad += !isfinite(v.x);
             bad += !isfinite(v.y);
+            cm = fmax(cm, fmax(fabs(v.x * g.x), fabs(v.y * g.y)));
         }
         done = 2 * n2;
     }
-    for (long long i = done + tid; i < n; i += nth)
-        if (!isfinite(x[i])) ++bad;
-    return bad;
+    for (long long i = done + t; i < n; i += nth) {
+        const double g = b ? b[i] : 1.0;
+        bad += !isfinite(x[i]) + (b ? !isfinite(g) : 0);
+        cm = fmax(cm, fabs(x[i] * g));
+    }
 }
 
 __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, const double *flux,
-                                                  const double *beam, long long n_fs, double *part) {
+                                                  const double *beam, long long n_fs, long long span, double *part) {
     __shared__ double red[6][256];
     __shared__ int bsh[2][256];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -101,8 +112,15 @@ __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, 
         lo[2] = fmin(lo[2], c);
         hi[2] = fmax(hi[2], c);
     }
-    int badv = n_fs ? count_nonfinite(flux, n_fs, tid, nth) : 0;
-    if (beam && n_fs) badv += count_nonfinite(beam, n_fs, tid, nth);
+    // this block's contiguous range of the strengths: non-finite count and
+    // the largest |flux beam|
+    const long long f0 = min((long long)blockIdx.x * span, n_fs), f1 = min(f0 + span, n_fs);
+    int badv = 0;
+    double cm = 0.0;
+    if (f1 > f0) check_strengths(flux + f0, beam ? beam + f0 : nullptr, f1 - f0, threadIdx.x, 256, badv, cm);
+    for (int off = 32; off > 0; off >>= 1) cm = fmax(cm, __shfl_xor(cm, off, 64));
+    __shared__ double wcm[4];
+    if ((threadIdx.x & 63) == 0) wcm[threadIdx.x >> 6] = cm;
     for (int a = 0; a < 3; ++a) {
         red[2 * a][threadIdx.x] = lo[a];
         red[2 * a + 1][threadIdx.x] = hi[a];
@@ -122,9 +140,12 @@ __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 6; ++k) part[8 * blockIdx.x + k] = red[k][0];
-        part[8 * blockIdx.x + 6] = (double)bsh[0][0];
-        part[8 * blockIdx.x + 7] = (double)bsh[1][0];
+        double *q = part + (size_t)kValStride * blockIdx.x;
+        for (int k = 0; k < 6; ++k) q[k] = red[k][0];
+        q[6] = (double)bsh[0][0];
+        q[7] = (double)bsh[1][0];
+        q[kValCmax] = fmax(fmax(wcm[0], wcm[1]), fmax(wcm[2], wcm[3]));
+        q[9] = 0.0;
     }
 }
 
@@ -139,7 +160,7 @@ __global__ __launch_bounds__(256) void k_validate_reduce(const double *part, int
     double v[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0, 0.0};
 #pragma unroll 4
     for (int b = t; b < nblk; b += 256) {
-        const double *q = part + 8 * (size_t)b;
+        const double *q = part + (size_t)kValStride * b;
         for (int k = 0; k < 6; k += 2) {
             v[k] = fmin(v[k], q[k]);
             v[k + 1] = fmax(v[k + 1], q[k + 1]);
@@ -214,7 +235,7 @@ void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int 
 }
 
 size_t validate_doubles(int n_ant, int n_freq) {
-    return 8 + (size_t)n_freq + 3 * (size_t)n_ant + 8 * (size_t)kSrcCheckBlocks;
+    return 8 + (size_t)n_freq + 3 * (size_t)n_ant + (size_t)kValStride * kSrcCheckBlocks;
 }
 
 void launch_validate(const double *src, int n_src, const double *flux, const double *beam, int n_freq,
@@ -222,7 +243,7 @@ void launch_validate(const double *src, int n_src, const double *flux, const dou
     double *part = out + 8 + n_freq + 3 * (size_t)n_ant;
     const long long n_fs = n_src > 0 ? (long long)n_src * n_freq : 0;
     hipLaunchKernelGGL(k_validate, dim3(kSrcCheckBlocks), dim3(256), 0, st, n_src > 0 ? src : nullptr, n_src,
-                       n_src > 0 ? flux : nullptr, n_src > 0 ? beam : nullptr, n_fs, part);
+                       n_src > 0 ? flux : nullptr, n_src > 0 ? beam : nullptr, n_fs, validate_span(n_fs), part);
     hipLaunchKernelGGL(k_validate_reduce, dim3(1), dim3(256), 0, st, (const double *)part, kSrcCheckBlocks, freq,
                        n_freq, ant, n_ant, out);
     FV_HIP(hipGetLastError());

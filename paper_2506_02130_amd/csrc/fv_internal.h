@@ -264,9 +264,13 @@ size_t lattice_work_bytes(const LatticePlan &lp, int n_src, int n_freq, int n_an
 bool lattice_fits(const LatticePlan &lp, int prec_bits, int w);  // LDS limits of the kernels
 void lattice_tables(LatticePlan &lp, int w);  // fills lp.w and lp.dc (host, once per plan)
 void lattice_grid(const LatticePlan &lp, int w, int nf[2]);       // fine periodic grid per axis
+// cmax_part / cmax_span: the device input check's block partials (each
+// holds the largest |flux beam| of a flat range of cmax_span values), or null
+// to have the spreading kernel find each chunk's largest strength itself.
 double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_host, int n_freq,
-                      const double *flux_dev, const double *beam_dev, int n_ant, int prec_bits, int w, double *vis_dev,
-                      void *work, PinnedBuf &stage, hipStream_t st, StageTimer *timer);
+                      const double *flux_dev, const double *beam_dev, const double *cmax_part, long long cmax_span,
+                      int n_ant, int prec_bits, int w, double *vis_dev, void *work, PinnedBuf &stage, hipStream_t st,
+                      StageTimer *timer);
 
 // Enqueue the whole type-3 pipeline for jobs that share (dim, precision, w).
 // Allocates its workspace from `arena` (which must be idle); returns the
@@ -287,7 +291,17 @@ std::vector<int> target_order(const double *ant_host, const GeomPlan &g);
 // buffer `out` of validate_doubles() doubles): out[0..5] = min/max of l, m, n;
 // out[6] = count of non-unit or non-finite directions; out[7] = count of
 // non-finite flux and beam values; out[8 .. 8 + n_freq) = frequencies; then
-// the 3 n_ant antenna coordinates; then block partials (scratch).
+// the 3 n_ant antenna coordinates; then kSrcCheckBlocks block partials of
+// kValStride doubles.  Block b checks the flat strength range
+// [b span, (b + 1) span) of the [n_freq][n_src] arrays (span =
+// validate_span(n_src n_freq)), and its partial's slot kValCmax holds the
+// largest |flux beam| of that range.
+constexpr int kValStride = 10;
+constexpr int kValCmax = 8;
+inline long long validate_span(long long n_fs) { return ((n_fs + kSrcCheckBlocks - 1) / kSrcCheckBlocks + 1) & ~1LL; }
+inline const double *validate_partials(const double *out, int n_ant, int n_freq) {
+    return out + 8 + n_freq + 3 * (size_t)n_ant;
+}
 size_t validate_doubles(int n_ant, int n_freq);
 void launch_validate(const double *src, int n_src, const double *flux, const double *beam, int n_freq,
                      const double *ant, int n_ant, const double *freq, double *out, hipStream_t s);

@@ -44,6 +44,8 @@ struct T1Params {
     double A[2][2];
     double beta;
     const double *src, *flux, *beam;
+    const double *cmax;   // input-check partials (largest |c| per flat range of cspan values), or null
+    long long cspan;
     const double *kturn;  // [n_freq] nu / c
     const double *dc;     // [N0 + N1] deconvolution factors
     const int *kc;        // [n_ant][2] lattice coordinates
@@ -90,10 +92,15 @@ __device__ int t1_chunk_scale(const T1Params &P, int f, int ch, int s0, int s1, 
     __shared__ double red[kT1Threads / 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double cm = 0.0;
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += kT1Threads) {
-        double c = P.flux[(size_t)f * P.n_src + s];
-        if (P.beam) c *= P.beam[(size_t)f * P.n_src + s];
-        cm = fmax(cm, fabs(c));
+    if (P.cmax) {  // from the input check: the partials whose ranges cover the chunk
+        const long long a = ((long long)f * P.n_src + s0) / P.cspan, b = ((long long)f * P.n_src + s1 - 1) / P.cspan;
+        for (long long q = a + threadIdx.x; q <= b; q += kT1Threads) cm = fmax(cm, P.cmax[kValStride * q + kValCmax]);
+    } else {
+        for (int s = s0 + (int)threadIdx.x; s < s1; s += kT1Threads) {
+            double c = P.flux[(size_t)f * P.n_src + s];
+            if (P.beam) c *= P.beam[(size_t)f * P.n_src + s];
+            cm = fmax(cm, fabs(c));
+        }
     }
     for (int off = 32; off > 0; off >>= 1) cm = fmax(cm, __shfl_xor(cm, off, 64));
     if (lane == 0) red[wave] = cm;
@@ -338,8 +345,9 @@ size_t lattice_work_bytes(const LatticePlan &lp, int n_src, int n_freq, int n_an
 }
 
 double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_host, int n_freq,
-                      const double *flux_dev, const double *beam_dev, int n_ant, int prec_bits, int w, double *vis_dev,
-                      void *work, PinnedBuf &stage, hipStream_t st, StageTimer *tm) {
+                      const double *flux_dev, const double *beam_dev, const double *cmax_part, long long cmax_span,
+                      int n_ant, int prec_bits, int w, double *vis_dev, void *work, PinnedBuf &stage, hipStream_t st,
+                      StageTimer *tm) {
     StageTimer dummy;
     if (!tm) tm = &dummy;
     const T1Shape sh = t1_shape(lp, n_src, n_freq, n_ant, prec_bits, w);
@@ -366,6 +374,8 @@ double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, c
     P.src = src_dev;
     P.flux = flux_dev;
     P.beam = beam_dev;
+    P.cmax = cmax_part;
+    P.cspan = cmax_span;
     P.vis = vis_dev;
     P.part = wp;
     P.part_scale = (double *)(wp + (size_t)n_freq * sh.nchunk * ((size_t)sh.nf[0] * sh.nf[1]) * 8);
@@ -397,8 +407,10 @@ double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, c
     else
         spread_pick<double>(w, gs, sh.lds, st, P, WL{});
     tm->end(st);
+    // algorithmic bytes: the directions once, strengths (and beam) once per
+    // frequency, the partial grids once
     tm->add(FV_STAGE_SPREAD,
-            (double)n_freq * ((double)n_src * (16.0 + (beam_dev ? 8.0 : 0.0)) + (double)sh.part_bytes / n_freq), 1);
+            24.0 * n_src + (double)n_freq * n_src * (beam_dev ? 16.0 : 8.0) + (double)sh.part_bytes, 1);
     tm->begin(FV_STAGE_FFT_X, st);
     hipLaunchKernelGGL(k_t1_rows, dim3((unsigned)sh.nf[1], (unsigned)n_freq), dim3(256),
                        (size_t)sh.nf[0] * (8 + 16), st, P);

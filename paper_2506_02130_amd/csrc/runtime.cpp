@@ -178,6 +178,7 @@ Slot::~Slot() {
     inputs.host.release();
     arena.release();
     inputs.release();
+    if (done) (void)hipEventDestroy(done);
     if (stream && own_stream) (void)hipStreamDestroy(stream);
 }
 
@@ -347,8 +348,8 @@ bool run_lattice(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &
     slot.arena.ensure(need);
     slot.arena.reset();
     void *work = slot.arena.take(need);
-    r.model_bytes += launch_lattice(*lp, in.src, p.n_src, p.freq_hz, p.n_freq, in.flux, in.beam, p.n_ant, prec, w,
-                                    vis_dev, work, slot.arena.host, slot.stream, tm);
+    r.model_bytes += launch_lattice(*lp, in.src, p.n_src, p.freq_hz, p.n_freq, in.flux, in.beam, in.cmax,
+                                    in.cmax_span, p.n_ant, prec, w, vis_dev, work, slot.arena.host, slot.stream, tm);
     r.lattice = 1;
     r.w = w;
     r.n1[0] = nf[0];
@@ -532,6 +533,7 @@ void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv
     auto t0 = std::chrono::steady_clock::now();
     validate_host(p);
     FV_HIP(hipSetDevice(ctx->device));
+    if (slot.done) FV_HIP(hipStreamWaitEvent(slot.stream, slot.done, 0));  // a device-entry call's work
     double s_c[3], S[3];
     DevInputs in = upload(slot, p, s_c, S);
     fv_report r;
@@ -633,6 +635,9 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     // staging: [check 8][freq][ant]
     const size_t n_ant3 = 3 * (size_t)p->n_ant;
     const size_t nscal = 8 + (size_t)p->n_freq + n_ant3;
+    fv::Slot &slot = ctx->main;
+    if (!slot.done) FV_HIP(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
+    FV_HIP(hipStreamWaitEvent(st, slot.done, 0));  // the previous call (any stream) is done with the workspace
     double *pin = (double *)ctx->plan_pin.get(nscal * sizeof(double));
     double *dev = ctx->scalars(fv::validate_doubles(p->n_ant, p->n_freq));
     fv::launch_validate(p->src_lmn, p->n_src, p->flux, p->beam, p->n_freq, p->ant_enu, p->n_ant, p->freq_hz, dev,
@@ -668,7 +673,8 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
             in.S[a] = 0.5 * (host_chk[2 * a + 1] - host_chk[2 * a]);
         }
     in.ant = p->ant_enu;
-    fv::Slot &slot = ctx->main;
+    in.cmax = fv::validate_partials(dev, p->n_ant, p->n_freq);
+    in.cmax_span = fv::validate_span((long long)p->n_src * p->n_freq);
     hipStream_t keep = slot.stream;
     slot.stream = st;
     try {
@@ -678,6 +684,7 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
         throw;
     }
     slot.stream = keep;
+    FV_HIP(hipEventRecord(slot.done, st));
     if (rep) rep->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return FV_OK;
     FV_GUARD_END

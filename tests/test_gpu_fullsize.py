@@ -62,3 +62,33 @@ def test_batched_1032_snapshots_full_size(gpu_lib):
         outs = c.simulate_batch([fv.HostProblem.of(q) for q in probs])
     for k in (0, 7, 13, 23):
         assert _sample_check(outs[k], probs[k], n_pairs=256, n_freq=3, seed=20 + k) <= probs[k].eps, probs[k].name
+
+
+def test_successive_device_calls_on_different_streams_are_ordered(gpu_lib):
+    """A large call on one stream, then a small one on another stream and a
+    host-buffer call, with no synchronisation between them: the later calls
+    reuse the context's workspace and must wait for the first one."""
+    import torch
+    fv = gpu_lib
+    dev = torch.device("cuda:0")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    big = synth.config2(n_src=30000, n_freq=16)
+    small = synth.small_problem(140, n_ant=37, n_src=500, n_freq=2, hex_layout=True)
+    other = synth.small_problem(141, n_ant=20, n_src=300, n_freq=2)
+    args_b = [d(x) for x in (big.ant_enu, big.src_lmn, big.freq_hz, big.flux, big.beam)]
+    args_s = [d(x) for x in (small.ant_enu, small.src_lmn, small.freq_hz, small.flux, small.beam)]
+    vis_b = torch.empty((big.n_freq, big.n_pairs, 2), dtype=torch.float64, device=dev)
+    vis_s = torch.empty((small.n_freq, small.n_pairs, 2), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    with fv.Context(0) as c:
+        for _ in range(2):
+            c.simulate_dev(*args_b, vis_b, eps=big.eps, stream=s1)
+            c.simulate_dev(*args_s, vis_s, eps=small.eps, stream=s2)
+            v_o = c.simulate_problem(fv.HostProblem.of(other))
+            torch.cuda.synchronize()
+            o = vis_b.cpu().numpy()
+            assert _sample_check(o[..., 0] + 1j * o[..., 1], big, n_pairs=128, n_freq=2) <= big.eps
+            o = vis_s.cpu().numpy()
+            assert oracle.rel_l2(o[..., 0] + 1j * o[..., 1], oracle.direct_problem(small)) <= small.eps
+            assert oracle.rel_l2(v_o, oracle.direct_problem(other)) <= other.eps
