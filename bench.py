@@ -63,9 +63,9 @@ def _kernel_source_hash(files=None) -> str:
 def _traffic_from_profiles(stage: str, path_name: str):
     """HBM bytes per launch of a stage, from a committed pair of rocprofv3
     --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the calibration copy
-    (profiles/traffic_c2.json), only while the device sources of the path they
-    were taken on are unchanged."""
-    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    (profiles/traffic_c2_<path>.json), only while the device sources of the
+    path they were taken on are unchanged."""
+    path = os.path.join(ROOT, "profiles", f"traffic_c2_{path_name}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -94,8 +94,8 @@ def reduce_traffic(fetch_csv: str, write_csv: str, calib_mib: int, cmd: str, wor
     KiB per dispatch), each scaled by what the same counter reads for the M MiB
     device copy issued after the timed steps.  Rows are the dispatches of the
     last step (from its input-check kernel to the copy).  Writes
-    profiles/traffic_c2.json (read back by the roofline, tagged with a hash of
-    the path's device sources) and prints a markdown table."""
+    profiles/traffic_c2_<path>.json (read back by the roofline, tagged with a
+    hash of the path's device sources) and prints a markdown table."""
     import csv
 
     def load(path):
@@ -138,7 +138,7 @@ def reduce_traffic(fetch_csv: str, write_csv: str, calib_mib: int, cmd: str, wor
          "calibration": {"copy_MiB": calib_mib, "FETCH_SIZE_KiB": fetch[ci][1], "WRITE_SIZE_KiB": write[ci][1],
                          "fetch_scale": f_scale, "write_scale": w_scale},
          "stages": stages}
-    json.dump(d, open(os.path.join(ROOT, "profiles", "traffic_c2.json"), "w"), indent=1)
+    json.dump(d, open(os.path.join(ROOT, "profiles", f"traffic_c2_{path}.json"), "w"), indent=1)
     print(f"Calibration: the {calib_mib} MiB device copy after the steps reads FETCH_SIZE {fetch[ci][1]:.1f} KiB "
           f"and WRITE_SIZE {write[ci][1]:.1f} KiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by "
           f"{w_scale:.3f}.  Rows are the dispatches of the last step.\n")
@@ -266,7 +266,8 @@ def main():
         return
     if args.reduce_traffic:
         cmd = ("rocprofv3 --pmc COUNTER --output-format csv -d <out> -o run -- python3 bench.py --profile "
-               f"--steps 2 --warmup 1 --calib-copy-mib {args.calib_copy_mib or 256}")
+               f"--steps 2 --warmup 1 --calib-copy-mib {args.calib_copy_mib or 256}"
+               + (" --path type3" if args.path == "type3" else ""))
         reduce_traffic(args.reduce_traffic[0], args.reduce_traffic[1], args.calib_copy_mib or 256, cmd,
                        "hex350 14.6 m, 1e5 sources, 64 frequencies, eps 1e-6")
         return

@@ -45,7 +45,7 @@ def test_reduce_traffic_scales_by_the_copy_and_keeps_the_last_step(tmp_path, mon
     for fn in bench.PATH_SOURCES["type1"]:
         (csrc / fn).write_text("kernel source " + fn)
     bench.reduce_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 256, "cmd", "w")
-    d = json.load(open(prof / "traffic_c2.json"))
+    d = json.load(open(prof / "traffic_c2_type1.json"))
     assert d["path"] == "type1"
     assert d["calibration"]["fetch_scale"] == pytest.approx(2.0)
     sp = d["stages"]["spread"]
