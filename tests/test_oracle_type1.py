@@ -65,3 +65,28 @@ def test_type1_zenith_source_is_constant():
     src = np.array([[0.0, 0.0, 1.0]])
     v = type1.type1_vis(ant, src, np.array([150e6]), np.array([[3.0]]), 1e-10)
     assert np.allclose(v, 3.0, rtol=1e-10, atol=1e-10)
+
+
+def test_rotated_hex_array_is_a_lattice_and_modes_reproduce_every_baseline():
+    # a joint rotation of the array keeps it a lattice (the basis rotates with
+    # it), and A (k_i - k_j) is the baseline of every pair i <= j
+    th = 0.37
+    R = np.array([[math.cos(th), -math.sin(th), 0.0], [math.sin(th), math.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    ant = synth.hex_array(61) @ R.T + np.array([3.0, -7.0, 0.0])
+    lat = type1.find_lattice(ant, 1e-9)
+    assert lat is not None
+    iu, ju = np.triu_indices(ant.shape[0])
+    b = ant[iu, :2] - ant[ju, :2]
+    dk = lat.k[iu] - lat.k[ju]
+    assert np.abs(dk @ lat.A.T - b).max() < 1e-9
+    assert np.all(np.abs(dk) <= lat.K[None, :])
+
+
+def test_type1_on_rotated_array_matches_direct_sum():
+    th = 1.1
+    R = np.array([[math.cos(th), -math.sin(th), 0.0], [math.sin(th), math.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    p = synth.small_problem(122, n_ant=19, n_src=60, n_freq=2, hex_layout=True)
+    ant = p.ant_enu @ R.T
+    got = type1.type1_vis(ant, p.src_lmn, p.freq_hz, p.strengths(), 1e-8)
+    ref = oracle.direct_vis(ant, p.src_lmn, p.freq_hz, p.flux, p.beam)
+    assert oracle.rel_l2(got, ref) <= 1e-8
