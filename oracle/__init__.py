@@ -12,6 +12,11 @@ Contents
   * ``es_kernel``   -- the ES kernel and its Fourier transform by quadrature.
   * ``type3``       -- the type-3 transform taken step by step in numpy FP64
     (spread, oversampled FFT, deconvolve + interpolate), for per-stage checks.
+  * ``type1``       -- lattice detection and the type-1 steps for gridded
+    arrays (section 2.2.1).
+  * ``frontend``    -- drift-scan front end: rotation of equatorial directions
+    to ENU per sidereal time (section 2.3) and an analytic Gaussian power beam
+    (section 2.4).
 """
 from __future__ import annotations
 
