@@ -149,6 +149,42 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
 fv_status fv_simulate_batch(fv_ctx *ctx, int n_snap, const fv_problem *snaps, double *const *vis,
                             fv_report *rep);
 
+/* Drift scan with the front end on the device (paper section 2.3: between
+ * astrometric pre-corrections, a rigid rotation set by the local sidereal
+ * time and the latitude takes pre-corrected equatorial positions to the local
+ * East-North-Up frame; section 2.4: analytic beams evaluated in closed form at
+ * the source positions).  For each time t and frequency f:
+ *   s_t = R(lst[t], latitude) src_eq              (ENU unit vectors, FP64)
+ *   beam = 2^(-(2 theta / F_f)^2), theta = zenith angle of s_t,
+ *          F_f = beam_fwhm * beam_nu_ref / freq_hz[f]; 0 where Up <= 0
+ *          (beam_fwhm = 0: 1 above the horizon, 0 at and below it)
+ *   vis[t][f] = the visibilities of (ant_enu, s_t, freq_hz[f], flux[f], beam)
+ * as fv_simulate_dev computes them (same eps contract, same path choice).
+ * The sky stays on the device: no per-(time, frequency, source) array crosses
+ * the bus. */
+typedef struct {
+    int n_ant;  const double *ant_enu;   /* HOST [n_ant][3] metres (E, N, U) */
+    int n_src;  const double *src_eq;    /* DEVICE [n_src][3] unit vectors, equatorial (x: RA 0 on the
+                                            equator, z: north celestial pole), pre-corrected */
+    int n_freq; const double *freq_hz;   /* HOST [n_freq] */
+    const double *flux;                  /* DEVICE [n_freq][n_src] */
+    int n_time; const double *lst;       /* HOST [n_time] local sidereal times, radians */
+    double latitude;                     /* radians, in [-pi/2, pi/2] */
+    double beam_fwhm;                    /* radians at beam_nu_ref; 0 = unit beam above the horizon */
+    double beam_nu_ref;                  /* Hz (> 0 when beam_fwhm > 0) */
+    double eps;
+    unsigned flags;                      /* FV_* flags as in fv_problem; the NUFFT method only */
+} fv_drift;
+
+/* vis: DEVICE [n_time][n_freq][n_pairs] complex128 (interleaved re, im).
+ * Work is enqueued on `stream`; the call blocks once per group of times for
+ * the planning scalars (source box and input checks of each rotated
+ * snapshot).  Workspace: the rotated directions and beam values of a group of
+ * times, sized to a quarter of the context's HBM budget.  Errors: FV_EINVAL
+ * for bad sizes, non-finite or out-of-range scalars, non-unit source vectors
+ * or non-finite fluxes (the output is then undefined). */
+fv_status fv_simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, void *stream, fv_report *rep);
+
 /* Serving loop: a worker thread admits submitted requests while HBM (the
  * context budget) and one of max_slots slots are free, and runs admitted
  * requests concurrently on per-slot streams.  Host buffers, which must stay

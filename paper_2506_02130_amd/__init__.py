@@ -34,7 +34,8 @@ NO_LATTICE = 0x1000
 STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
-               "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages")
+               "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
+               "fv_simulate_drift")
 
 
 class FvError(RuntimeError):
@@ -48,6 +49,15 @@ class Problem(ctypes.Structure):
                 ("n_src", ctypes.c_int), ("src_lmn", ctypes.c_void_p),
                 ("n_freq", ctypes.c_int), ("freq_hz", ctypes.c_void_p),
                 ("flux", ctypes.c_void_p), ("beam", ctypes.c_void_p),
+                ("eps", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+class Drift(ctypes.Structure):
+    """fv_drift: drift scan with the rotation and beam on the device."""
+    _fields_ = [("n_ant", ctypes.c_int), ("ant_enu", ctypes.c_void_p), ("n_src", ctypes.c_int),
+                ("src_eq", ctypes.c_void_p), ("n_freq", ctypes.c_int), ("freq_hz", ctypes.c_void_p),
+                ("flux", ctypes.c_void_p), ("n_time", ctypes.c_int), ("lst", ctypes.c_void_p),
+                ("latitude", ctypes.c_double), ("beam_fwhm", ctypes.c_double), ("beam_nu_ref", ctypes.c_double),
                 ("eps", ctypes.c_double), ("flags", ctypes.c_uint)]
 
 
@@ -87,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_server_stop.argtypes = [vp]
     lib.fv_debug_stages.argtypes = [vp, P(Problem), ctypes.c_int, dp, vp, ctypes.c_size_t, vp, ctypes.c_size_t]
     lib.fv_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
+    lib.fv_simulate_drift.argtypes = [vp, P(Drift), vp, vp, P(Report)]
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
@@ -194,6 +205,38 @@ class Context:
         rep = Report()
         _check(_lib.fv_simulate_dev(self._h, ctypes.byref(c), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
                                     ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return self.last_report
+
+    def simulate_drift(self, ant_enu, src_eq, freq_hz, flux, lst, latitude: float, beam_fwhm: float,
+                       beam_nu_ref: float, vis, eps: float = 1e-6, flags: int = 0, stream=None) -> dict:
+        """Drift scan with the front end on the device.  ``ant_enu`` [n_ant, 3],
+        ``freq_hz`` [n_freq] and ``lst`` [n_time] are host arrays; ``src_eq``
+        [n_src, 3] (equatorial unit vectors), ``flux`` [n_freq, n_src] and
+        ``vis`` [n_time, n_freq, n_pairs, 2] are contiguous float64 torch
+        tensors on this context's device.  Returns the report (summed over
+        times)."""
+        import torch
+        ant = np.ascontiguousarray(ant_enu, dtype=np.float64).reshape(-1, 3)
+        freq = np.ascontiguousarray(freq_hz, dtype=np.float64).reshape(-1)
+        lsts = np.ascontiguousarray(lst, dtype=np.float64).reshape(-1)
+        for name, t in (("src_eq", src_eq), ("flux", flux), ("vis", vis)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
+        n_ant, n_freq, n_time = ant.shape[0], freq.shape[0], lsts.shape[0]
+        n_src = src_eq.shape[0] if src_eq.dim() == 2 else src_eq.numel() // 3
+        n_pairs = n_ant * (n_ant + 1) // 2
+        for name, t, want in (("src_eq", src_eq, 3 * n_src), ("flux", flux, n_freq * n_src),
+                              ("vis", vis, 2 * n_time * n_freq * n_pairs)):
+            if t.numel() != want:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {want}")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        d = Drift(n_ant, ant.ctypes.data, n_src, src_eq.data_ptr() if n_src else None, n_freq, freq.ctypes.data,
+                  flux.data_ptr() if n_src else None, n_time, lsts.ctypes.data, float(latitude), float(beam_fwhm),
+                  float(beam_nu_ref), float(eps), int(flags))
+        rep = Report()
+        _check(_lib.fv_simulate_drift(self._h, ctypes.byref(d), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
+                                      ctypes.byref(rep)))
         self.last_report = rep.as_dict()
         return self.last_report
 

@@ -28,7 +28,8 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-m
 HOST_ONLY_FLAGS = ["-ffp-contract=off"]
 
 SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp", "server.cpp", "tune.cpp", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip",
-           "nufft_f64_2d.hip", "nufft_f64_3d.hip", "direct.hip", "zz.hip", "lattice.hip"]
+           "nufft_f64_2d.hip", "nufft_f64_3d.hip", "direct.hip", "zz.hip", "lattice.hip", "frontend.hip",
+           "drift.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -1,0 +1,190 @@
+// Drift scan with the front end on the device: the sky (equatorial unit
+// vectors and fluxes) stays in HBM; per group of times one launch rotates it
+// to ENU and evaluates the beam (paper sections 2.3 and 2.4), one input-check
+// pass per time gathers the planning scalars, one copy brings them all to the
+// host, and each time then runs the device path of fv_simulate_dev.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+#include "fv_internal.h"
+
+namespace fv {
+namespace {
+
+void validate_drift(const fv_drift *d) {
+    if (!d) fail(FV_EINVAL, "null argument");
+    if (d->n_ant < 1 || d->n_src < 0 || d->n_freq < 1 || d->n_time < 1) fail(FV_EINVAL, "bad sizes");
+    if (!d->ant_enu || !d->freq_hz || !d->lst) fail(FV_EINVAL, "null antenna, frequency or time array");
+    if (d->n_src > 0 && (!d->src_eq || !d->flux)) fail(FV_EINVAL, "null source or flux array");
+    if (!(d->eps >= 1e-14 && d->eps <= 1e-1)) fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
+    for (long long i = 0; i < 3LL * d->n_ant; ++i)
+        if (!std::isfinite(d->ant_enu[i])) fail(FV_EINVAL, "non-finite antenna position");
+    for (int f = 0; f < d->n_freq; ++f)
+        if (!(std::isfinite(d->freq_hz[f]) && d->freq_hz[f] > 0)) fail(FV_EINVAL, "frequency must be finite and > 0");
+    for (int t = 0; t < d->n_time; ++t)
+        if (!std::isfinite(d->lst[t])) fail(FV_EINVAL, "non-finite sidereal time");
+    if (!(std::isfinite(d->latitude) && std::fabs(d->latitude) <= M_PI / 2)) fail(FV_EINVAL, "latitude out of range");
+    if (!(std::isfinite(d->beam_fwhm) && d->beam_fwhm >= 0)) fail(FV_EINVAL, "beam width must be finite and >= 0");
+    if (d->beam_fwhm > 0 && !(std::isfinite(d->beam_nu_ref) && d->beam_nu_ref > 0))
+        fail(FV_EINVAL, "beam reference frequency must be finite and > 0");
+    if ((d->flags & FV_METHOD_MASK) != FV_METHOD_NUFFT) fail(FV_EINVAL, "the drift entry point runs the NUFFT");
+    if ((d->flags & FV_DIM_MASK) == FV_DIM_MASK) fail(FV_EINVAL, "both 2-D and 3-D forced");
+    if ((d->flags & FV_PREC_MASK) == FV_PREC_MASK) fail(FV_EINVAL, "both FP32 and FP64 forced");
+    if ((d->flags & FV_PREC_MASK) == FV_PREC_FP32 && d->eps < 1e-6) fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
+}
+
+// Rows E, N, U of the rotation taking equatorial unit vectors to ENU at
+// sidereal time lst and latitude lat: a turn by -lst about the polar axis
+// (hour angle), then the tilt of the polar axis to the local vertical.
+void rotation(double lst, double lat, double *R) {
+    const double cl = std::cos(lst), sl = std::sin(lst), cp = std::cos(lat), sp = std::sin(lat);
+    const double m[9] = {-sl, cl, 0.0, -sp * cl, -sp * sl, cp, cp * cl, cp * sl, sp};
+    std::memcpy(R, m, sizeof(m));
+}
+
+void add_report(const fv_report &a, fv_report &r, bool first) {
+    if (first) {
+        const double keep_pairs = r.src_pairs;
+        r = a;
+        r.src_pairs = keep_pairs + a.src_pairs;
+        return;
+    }
+    r.src_pairs += a.src_pairs;
+    r.model_bytes += a.model_bytes;
+    for (int i = 0; i < FV_NSTAGE; ++i) {
+        r.t_stage_ms[i] += a.t_stage_ms[i];
+        r.stage_bytes[i] += a.stage_bytes[i];
+        r.stage_launches[i] += a.stage_launches[i];
+    }
+    r.lattice = std::max(r.lattice, a.lattice);
+}
+
+}  // namespace
+
+void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st, fv_report *rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    validate_drift(d);
+    FV_HIP(hipSetDevice(ctx->device));
+    Slot &slot = ctx->main;
+    if (!slot.done) FV_HIP(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
+    FV_HIP(hipStreamWaitEvent(st, slot.done, 0));  // the previous call (any stream) is done with the workspace
+    const int n_ant = d->n_ant, n_src = d->n_src, n_freq = d->n_freq, n_time = d->n_time;
+    const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
+    const size_t nvd = validate_doubles(n_ant, n_freq);
+    // per-time workspace: rotated directions, beam values, input-check buffer
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t per_time = std::max<size_t>(256, al(24 * (size_t)n_src) + al(8 * (size_t)n_freq * n_src));
+    const size_t fixed = al(24 * (size_t)n_ant) + al(8 * (size_t)n_freq) * 2;
+    const size_t cap = std::max<size_t>(ctx->budget / 4, per_time + fixed);
+    const int group = (int)std::max<size_t>(1, std::min<size_t>({(size_t)n_time, (cap - fixed) / per_time, 65535}));
+
+    fv_problem meta;
+    std::memset(&meta, 0, sizeof(meta));
+    meta.n_ant = n_ant;
+    meta.ant_enu = d->ant_enu;
+    meta.n_src = n_src;
+    meta.n_freq = n_freq;
+    meta.freq_hz = d->freq_hz;
+    meta.eps = d->eps;
+    meta.flags = d->flags & ~FV_GRAPH;  // each time reads its own rotated directions: no replay
+    const bool unit_beam = d->beam_fwhm == 0.0;
+    fv_report total;
+    std::memset(&total, 0, sizeof(total));
+    hipStream_t keep = slot.stream;
+    slot.stream = st;
+    try {
+        for (int t0g = 0; t0g < n_time; t0g += group) {
+            const int nt = std::min(group, n_time - t0g);
+            // device buffers of this group (the inputs arena is not used by run_device)
+            slot.inputs.ensure(fixed + (size_t)nt * per_time + al(72 * (size_t)nt) + 1024);
+            slot.inputs.reset();
+            double *ant_dev = (double *)slot.inputs.take(24 * (size_t)n_ant);
+            double *freq_dev = (double *)slot.inputs.take(8 * (size_t)n_freq);
+            double *kb_dev = (double *)slot.inputs.take(8 * (size_t)n_freq);
+            double *rot_dev = (double *)slot.inputs.take(72 * (size_t)nt);
+            double *dir = (double *)slot.inputs.take((size_t)nt * per_time);
+            const long long dir_stride = (long long)(al(24 * (size_t)n_src) / 8);
+            double *beam = dir + (size_t)nt * dir_stride;
+            const long long beam_stride = (long long)(al(8 * (size_t)n_freq * n_src) / 8);
+            // host tables through pinned staging: antennas, frequencies, beam factors, rotations
+            const size_t tab = 3 * (size_t)n_ant + 2 * (size_t)n_freq + 9 * (size_t)nt;
+            double *h = (double *)slot.inputs.host.get(tab * sizeof(double));
+            std::memcpy(h, d->ant_enu, 24 * (size_t)n_ant);
+            std::memcpy(h + 3 * n_ant, d->freq_hz, 8 * (size_t)n_freq);
+            for (int f = 0; f < n_freq; ++f) {
+                const double F = unit_beam ? 1.0 : d->beam_fwhm * d->beam_nu_ref / d->freq_hz[f];
+                h[3 * n_ant + n_freq + f] = 4.0 / (F * F);
+            }
+            for (int t = 0; t < nt; ++t) rotation(d->lst[t0g + t], d->latitude, h + 3 * n_ant + 2 * n_freq + 9 * t);
+            FV_HIP(hipMemcpyAsync(ant_dev, h, 24 * (size_t)n_ant, hipMemcpyHostToDevice, st));
+            FV_HIP(hipMemcpyAsync(freq_dev, h + 3 * n_ant, 8 * (size_t)n_freq, hipMemcpyHostToDevice, st));
+            FV_HIP(hipMemcpyAsync(kb_dev, h + 3 * n_ant + n_freq, 8 * (size_t)n_freq, hipMemcpyHostToDevice, st));
+            FV_HIP(hipMemcpyAsync(rot_dev, h + 3 * n_ant + 2 * n_freq, 72 * (size_t)nt, hipMemcpyHostToDevice, st));
+            slot.inputs.host.record(st);
+            launch_frontend(d->src_eq, n_src, nt, rot_dev, n_freq, kb_dev, unit_beam, dir, dir_stride, beam,
+                            beam_stride, st);
+            // input check of every rotated snapshot, then one copy of all the checks
+            double *scal = ctx->scalars(nvd * (size_t)nt);
+            for (int t = 0; t < nt; ++t)
+                launch_validate(dir + t * dir_stride, n_src, d->flux, beam + t * beam_stride, n_freq, ant_dev, n_ant,
+                                freq_dev, scal + (size_t)t * nvd, st);
+            double *pin = (double *)ctx->plan_pin.get(8 * sizeof(double) * (size_t)nt);
+            for (int t = 0; t < nt; ++t)
+                FV_HIP(hipMemcpyAsync(pin + 8 * t, scal + (size_t)t * nvd, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                                      st));
+            FV_HIP(hipStreamSynchronize(st));
+            for (int t = 0; t < nt; ++t) {
+                const double *chk = pin + 8 * t;
+                if (n_src > 0 && (chk[6] != 0.0 || chk[7] != 0.0))
+                    fail(FV_EINVAL, "invalid source vectors or fluxes (directions must be unit vectors)");
+                DevInputs in;
+                in.ant = ant_dev;
+                in.src = dir + t * dir_stride;
+                in.flux = d->flux;
+                in.beam = beam + t * beam_stride;
+                in.vis = vis + 2 * (size_t)(t0g + t) * n_freq * n_pairs;
+                const int dim = choose_dim(d->ant_enu, n_ant, d->eps, d->freq_hz, n_freq, d->flags);
+                if (n_src > 0)
+                    for (int a = 0; a < dim; ++a) {
+                        in.s_c[a] = 0.5 * (chk[2 * a] + chk[2 * a + 1]);
+                        in.S[a] = 0.5 * (chk[2 * a + 1] - chk[2 * a]);
+                    }
+                in.cmax = validate_partials(scal + (size_t)t * nvd, n_ant, n_freq);
+                in.cmax_span = validate_span((long long)n_src * n_freq);
+                fv_report r;
+                run_device(ctx, slot, meta, in, in.vis, &r);
+                add_report(r, total, t0g == 0 && t == 0);
+            }
+        }
+    } catch (...) {
+        slot.stream = keep;
+        throw;
+    }
+    slot.stream = keep;
+    FV_HIP(hipEventRecord(slot.done, st));
+    total.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = total;
+}
+
+}  // namespace fv
+
+extern "C" fv_status fv_simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, void *stream, fv_report *rep) {
+    try {
+        if (!ctx || !d || !vis) fv::fail(FV_EINVAL, "null argument");
+        fv::simulate_drift(ctx, d, vis, (hipStream_t)stream, rep);
+        return FV_OK;
+    } catch (const fv::Error &e) {
+        fv::set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        fv::set_last_error("host allocation failed");
+        return FV_ENOMEM;
+    } catch (const std::exception &e) {
+        fv::set_last_error(e.what());
+        return FV_EDEVICE;
+    }
+}

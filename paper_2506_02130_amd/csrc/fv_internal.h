@@ -307,6 +307,14 @@ void launch_validate(const double *src, int n_src, const double *flux, const dou
                      const double *ant, int n_ant, const double *freq, double *out, hipStream_t s);
 void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
 
+// Drift-scan front end: for each of n_time rotations rot_dev [n_time][9]
+// (rows E, N, U), dir + t dir_stride [n_src][3] = R_t src_eq and
+// beam + t beam_stride [n_freq][n_src] = 2^(-kbeam[f] theta^2) (1 if unit_beam),
+// zero at and below the horizon.
+void launch_frontend(const double *src_eq, int n_src, int n_time, const double *rot_dev, int n_freq,
+                     const double *kbeam_dev, bool unit_beam, double *dir, long long dir_stride, double *beam,
+                     long long beam_stride, hipStream_t st);
+
 // Direct sums.
 void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
                    int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits,

@@ -240,6 +240,72 @@ def config4(n_lst: int = 24, n_freq: int = 43, n_cap: int = 100_000, n_iso: int 
 
 
 @dataclasses.dataclass
+class DriftScan:
+    """A drift scan: the array, an equatorial sky (unit vectors, x towards RA 0
+    on the equator, z to the north pole), fluxes per frequency, sidereal times,
+    the latitude and a Gaussian power beam's FWHM at a reference frequency."""
+    name: str
+    ant_enu: np.ndarray     # [n_ant, 3]
+    src_eq: np.ndarray      # [n_src, 3]
+    freq_hz: np.ndarray     # [n_freq]
+    flux: np.ndarray        # [n_freq, n_src]
+    lst: np.ndarray         # [n_time] radians
+    latitude: float         # radians
+    beam_fwhm: float        # radians at beam_nu_ref
+    beam_nu_ref: float
+    eps: float
+
+    @property
+    def n_pairs(self) -> int:
+        n = self.ant_enu.shape[0]
+        return n * (n + 1) // 2
+
+
+def _eq_unit(ra: np.ndarray, dec: np.ndarray) -> np.ndarray:
+    return np.stack([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)], axis=1)
+
+
+def config4_drift(n_lst: int = 24, n_freq: int = 43, n_cap: int = 100_000, n_iso: int = 2000,
+                  n_ant: int = 127) -> DriftScan:
+    """The sky of config4 (25-degree power-law cap at Dec -30.72 deg plus
+    isotropic sources, spectral index N(-0.8, 0.2), 100-200 MHz) left in
+    equatorial form with the hourly sidereal times, for the device front end;
+    beam FWHM 10 degrees at 150 MHz."""
+    rng = np.random.default_rng(np.random.PCG64(SEED_BASE + 40))
+    lat = math.radians(HERA_LAT_DEG)
+    c = _eq_unit(np.array([0.0]), np.array([lat]))[0]
+    e1 = np.cross([0.0, 0.0, 1.0], c); e1 /= np.linalg.norm(e1)
+    e2 = np.cross(c, e1)
+    ct = rng.uniform(math.cos(math.radians(25.0)), 1.0, n_cap)
+    st = np.sqrt(1 - ct * ct)
+    psi = 2 * np.pi * rng.random(n_cap)
+    cap = ct[:, None] * c + st[:, None] * (np.cos(psi)[:, None] * e1 + np.sin(psi)[:, None] * e2)
+    iso = _eq_unit(2 * np.pi * rng.random(n_iso), np.arcsin(rng.uniform(-1, 1, n_iso)))
+    src = _renorm(np.concatenate([cap, iso]))
+    s150 = powerlaw_fluxes(rng, n_cap + n_iso)
+    alpha = rng.normal(-0.8, 0.2, n_cap + n_iso)
+    freq = np.linspace(100e6, 200e6, n_freq)
+    flux = s150[None, :] * (freq[:, None] / 150e6) ** alpha[None, :]
+    lst = 2 * np.pi * np.arange(n_lst) / n_lst
+    return DriftScan(f"hex{n_ant}_drift{n_lst}x{n_freq}_src{n_cap + n_iso}", hex_array(n_ant), src, freq, flux, lst,
+                     lat, math.radians(10.0), 150e6, 1e-6)
+
+
+def small_drift(seed: int, n_ant: int = 19, n_src: int = 300, n_freq: int = 2, n_time: int = 3,
+                hex_layout: bool = True, three_d: bool = False, eps: float = 1e-6) -> DriftScan:
+    """A small drift scan for tests: isotropic equatorial sky, power-law fluxes."""
+    rng = np.random.default_rng(np.random.PCG64(SEED_BASE + 500 + seed))
+    ant = hex_array(n_ant) if hex_layout else disk_array(rng, n_ant, 60.0, 2.0 if three_d else 0.0)
+    src = _renorm(_eq_unit(2 * np.pi * rng.random(n_src), np.arcsin(rng.uniform(-1, 1, n_src)))) if n_src else \
+        np.zeros((0, 3))
+    freq = np.linspace(110e6, 190e6, n_freq)
+    flux = _spectral(rng, powerlaw_fluxes(rng, n_src), freq) if n_src else np.zeros((n_freq, 0))
+    lst = np.sort(rng.uniform(0, 2 * np.pi, n_time))
+    return DriftScan(f"drift{seed}", ant, src, freq, flux, lst, math.radians(HERA_LAT_DEG), math.radians(12.0),
+                     150e6, eps)
+
+
+@dataclasses.dataclass
 class Request:
     rid: int
     arrival_s: float
