@@ -239,6 +239,39 @@ def disk3d_leg(fv, synth, np, torch, stream) -> dict:
                           if rep["stage_launches"][i] > 0}}
 
 
+def drift_leg(fv, synth, np, torch, stream) -> dict:
+    """The config4 drift scan (hex127, 24 hourly LSTs x 43 frequencies, a
+    102k-source equatorial sky) through the device front end: sky resident in
+    HBM, rotation, beam and horizon cut on the device; two timed calls after one
+    warm-up call.  Pairs count the sources above the horizon."""
+    d = synth.config4_drift()
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    src, flux = g(d.src_eq), g(d.flux)
+    vis = torch.empty((len(d.lst), len(d.freq_hz), d.n_pairs, 2), dtype=torch.float64, device=dev)
+    with fv.Context(0) as c:
+        run = lambda fl: c.simulate_drift(d.ant_enu, src, d.freq_hz, flux, d.lst, d.latitude, d.beam_fwhm,
+                                          d.beam_nu_ref, vis, eps=d.eps, flags=fl, stream=stream)
+        run(0)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            rep = run(0)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        rep_t = run(fv.TIMING)
+        torch.cuda.synchronize()
+    t = min(ts)
+    n_snap = len(d.lst) * len(d.freq_hz)
+    return {"workload": f"hex{d.ant_enu.shape[0]}, {len(d.lst)} LSTs x {len(d.freq_hz)} freqs = {n_snap} snapshots, "
+                        f"{d.src_eq.shape[0]}-source equatorial sky in HBM, rotation + beam + horizon cut on the "
+                        f"device, eps {d.eps:g}",
+            "ms": t * 1e3, "pairs_per_s": rep["src_pairs"] / t,
+            "visible_sources_per_snapshot": rep["src_pairs"] / (n_snap * d.n_pairs),
+            "lattice": rep["lattice"], "gpu_stage_ms": sum(rep_t["t_stage_ms"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -464,6 +497,9 @@ def main():
               f"{tb * 1e3:.1f} ms", file=sys.stderr, flush=True)
         extras["serving"] = serving_leg(fv, synth, np, args.serve_requests)
         extras["disk1000_3d"] = disk3d_leg(fv, synth, np, torch, stream)
+        extras["drift_config4"] = drift_leg(fv, synth, np, torch, stream)
+        print(f"bench: drift scan {extras['drift_config4']['ms']:.1f} ms "
+              f"({extras['drift_config4']['pairs_per_s']:.3e} pairs/s)", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC,

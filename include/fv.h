@@ -161,7 +161,8 @@ fv_status fv_simulate_batch(fv_ctx *ctx, int n_snap, const fv_problem *snaps, do
  *   vis[t][f] = the visibilities of (ant_enu, s_t, freq_hz[f], flux[f], beam)
  * as fv_simulate_dev computes them (same eps contract, same path choice).
  * The sky stays on the device: no per-(time, frequency, source) array crosses
- * the bus. */
+ * the bus.  Sources at or below the horizon (zero beam) are dropped before
+ * the transform; fv_report.src_pairs counts the visible ones. */
 typedef struct {
     int n_ant;  const double *ant_enu;   /* HOST [n_ant][3] metres (E, N, U) */
     int n_src;  const double *src_eq;    /* DEVICE [n_src][3] unit vectors, equatorial (x: RA 0 on the

@@ -1,8 +1,11 @@
 // Drift scan with the front end on the device: the sky (equatorial unit
-// vectors and fluxes) stays in HBM; per group of times one launch rotates it
-// to ENU and evaluates the beam (paper sections 2.3 and 2.4), one input-check
-// pass per time gathers the planning scalars, one copy brings them all to the
-// host, and each time then runs the device path of fv_simulate_dev.
+// vectors and fluxes) stays in HBM.  Per group of times: one launch counts
+// the sources above the horizon at each time (and checks the inputs), one copy
+// brings the counts to the host, one launch rotates the visible sources to ENU
+// and forms their strengths with the beam (paper sections 2.3 and 2.4), packed;
+// one input-check pass per time gathers the planning scalars, one copy brings
+// them all to the host, and each time then runs the device path of
+// fv_simulate_dev on its visible sky.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -75,10 +78,13 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
     const int n_ant = d->n_ant, n_src = d->n_src, n_freq = d->n_freq, n_time = d->n_time;
     const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
     const size_t nvd = validate_doubles(n_ant, n_freq);
-    // per-time workspace: rotated directions, beam values, input-check buffer
+    // per-time workspace: packed directions and strengths of the visible
+    // sources, block offsets
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t per_time = std::max<size_t>(256, al(24 * (size_t)n_src) + al(8 * (size_t)n_freq * n_src));
-    const size_t fixed = al(24 * (size_t)n_ant) + al(8 * (size_t)n_freq) * 2;
+    const int nb = frontend_blocks(n_src);
+    const size_t per_time =
+        std::max<size_t>(256, al(24 * (size_t)n_src) + al(8 * (size_t)n_freq * n_src) + al(4 * (size_t)nb));
+    const size_t fixed = al(24 * (size_t)n_ant) + al(8 * (size_t)n_freq) * 2 + al(4 * (size_t)nb);
     const size_t cap = std::max<size_t>(ctx->budget / 4, per_time + fixed);
     const int group = (int)std::max<size_t>(1, std::min<size_t>({(size_t)n_time, (cap - fixed) / per_time, 65535}));
 
@@ -100,16 +106,19 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
         for (int t0g = 0; t0g < n_time; t0g += group) {
             const int nt = std::min(group, n_time - t0g);
             // device buffers of this group (the inputs arena is not used by run_device)
-            slot.inputs.ensure(fixed + (size_t)nt * per_time + al(72 * (size_t)nt) + 1024);
+            slot.inputs.ensure(fixed + (size_t)nt * per_time + al(72 * (size_t)nt) + al(4 * (size_t)nt + 4) + 4096);
             slot.inputs.reset();
             double *ant_dev = (double *)slot.inputs.take(24 * (size_t)n_ant);
             double *freq_dev = (double *)slot.inputs.take(8 * (size_t)n_freq);
             double *kb_dev = (double *)slot.inputs.take(8 * (size_t)n_freq);
             double *rot_dev = (double *)slot.inputs.take(72 * (size_t)nt);
-            double *dir = (double *)slot.inputs.take((size_t)nt * per_time);
+            int *bbad = (int *)slot.inputs.take(4 * (size_t)nb + 4);
+            int *tot = (int *)slot.inputs.take(4 * (size_t)nt + 4);
+            int *bcnt = (int *)slot.inputs.take(4 * (size_t)nb * nt + 4);
             const long long dir_stride = (long long)(al(24 * (size_t)n_src) / 8);
-            double *beam = dir + (size_t)nt * dir_stride;
-            const long long beam_stride = (long long)(al(8 * (size_t)n_freq * n_src) / 8);
+            const long long str_stride = (long long)(al(8 * (size_t)n_freq * n_src) / 8);
+            double *dir = (double *)slot.inputs.take(8 * (size_t)nt * dir_stride + 8);
+            double *str = (double *)slot.inputs.take(8 * (size_t)nt * str_stride + 8);
             // host tables through pinned staging: antennas, frequencies, beam factors, rotations
             const size_t tab = 3 * (size_t)n_ant + 2 * (size_t)n_freq + 9 * (size_t)nt;
             double *h = (double *)slot.inputs.host.get(tab * sizeof(double));
@@ -125,12 +134,19 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
             FV_HIP(hipMemcpyAsync(kb_dev, h + 3 * n_ant + n_freq, 8 * (size_t)n_freq, hipMemcpyHostToDevice, st));
             FV_HIP(hipMemcpyAsync(rot_dev, h + 3 * n_ant + 2 * n_freq, 72 * (size_t)nt, hipMemcpyHostToDevice, st));
             slot.inputs.host.record(st);
-            launch_frontend(d->src_eq, n_src, nt, rot_dev, n_freq, kb_dev, unit_beam, dir, dir_stride, beam,
-                            beam_stride, st);
-            // input check of every rotated snapshot, then one copy of all the checks
+            // visible counts and input checks, brought to the host in one copy
+            launch_frontend_count(d->src_eq, n_src, nt, rot_dev, d->flux, n_freq, bcnt, bbad, tot, st);
+            int *cnt = (int *)ctx->plan_pin.get(sizeof(int) * ((size_t)nt + 1));
+            FV_HIP(hipMemcpyAsync(cnt, tot, sizeof(int) * ((size_t)nt + 1), hipMemcpyDeviceToHost, st));
+            FV_HIP(hipStreamSynchronize(st));
+            if (cnt[nt] != 0) fail(FV_EINVAL, "invalid source vectors or fluxes (directions must be unit vectors)");
+            const std::vector<int> vis_src(cnt, cnt + nt);
+            launch_frontend(d->src_eq, n_src, nt, rot_dev, d->flux, n_freq, kb_dev, unit_beam, bcnt, tot, dir,
+                            dir_stride, str, str_stride, st);
+            // planning scalars of every visible snapshot, then one copy of all of them
             double *scal = ctx->scalars(nvd * (size_t)nt);
             for (int t = 0; t < nt; ++t)
-                launch_validate(dir + t * dir_stride, n_src, d->flux, beam + t * beam_stride, n_freq, ant_dev, n_ant,
+                launch_validate(dir + t * dir_stride, vis_src[t], str + t * str_stride, nullptr, n_freq, ant_dev, n_ant,
                                 freq_dev, scal + (size_t)t * nvd, st);
             double *pin = (double *)ctx->plan_pin.get(8 * sizeof(double) * (size_t)nt);
             for (int t = 0; t < nt; ++t)
@@ -139,24 +155,27 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
             FV_HIP(hipStreamSynchronize(st));
             for (int t = 0; t < nt; ++t) {
                 const double *chk = pin + 8 * t;
-                if (n_src > 0 && (chk[6] != 0.0 || chk[7] != 0.0))
+                const int ns = vis_src[t];
+                if (ns > 0 && (chk[6] != 0.0 || chk[7] != 0.0))
                     fail(FV_EINVAL, "invalid source vectors or fluxes (directions must be unit vectors)");
                 DevInputs in;
                 in.ant = ant_dev;
                 in.src = dir + t * dir_stride;
-                in.flux = d->flux;
-                in.beam = beam + t * beam_stride;
+                in.flux = str + t * str_stride;
+                in.beam = nullptr;
                 in.vis = vis + 2 * (size_t)(t0g + t) * n_freq * n_pairs;
                 const int dim = choose_dim(d->ant_enu, n_ant, d->eps, d->freq_hz, n_freq, d->flags);
-                if (n_src > 0)
+                if (ns > 0)
                     for (int a = 0; a < dim; ++a) {
                         in.s_c[a] = 0.5 * (chk[2 * a] + chk[2 * a + 1]);
                         in.S[a] = 0.5 * (chk[2 * a + 1] - chk[2 * a]);
                     }
                 in.cmax = validate_partials(scal + (size_t)t * nvd, n_ant, n_freq);
-                in.cmax_span = validate_span((long long)n_src * n_freq);
+                in.cmax_span = validate_span((long long)ns * n_freq);
+                fv_problem mt = meta;
+                mt.n_src = ns;
                 fv_report r;
-                run_device(ctx, slot, meta, in, in.vis, &r);
+                run_device(ctx, slot, mt, in, in.vis, &r);
                 add_report(r, total, t0g == 0 && t == 0);
             }
         }

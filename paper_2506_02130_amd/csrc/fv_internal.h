@@ -307,13 +307,21 @@ void launch_validate(const double *src, int n_src, const double *flux, const dou
                      const double *ant, int n_ant, const double *freq, double *out, hipStream_t s);
 void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
 
-// Drift-scan front end: for each of n_time rotations rot_dev [n_time][9]
-// (rows E, N, U), dir + t dir_stride [n_src][3] = R_t src_eq and
-// beam + t beam_stride [n_freq][n_src] = 2^(-kbeam[f] theta^2) (1 if unit_beam),
-// zero at and below the horizon.
-void launch_frontend(const double *src_eq, int n_src, int n_time, const double *rot_dev, int n_freq,
-                     const double *kbeam_dev, bool unit_beam, double *dir, long long dir_stride, double *beam,
-                     long long beam_stride, hipStream_t st);
+// Drift-scan front end.  rot_dev [n_time][9] holds the rotations (rows E, N,
+// U).  launch_frontend_count: bcnt [n_time][frontend_blocks(n_src)] receives
+// the exclusive offsets of the sources above the horizon per block of
+// sources, tot [n_time] the visible counts and tot[n_time] the number of
+// invalid inputs (non-finite or non-unit vectors, non-finite fluxes);
+// bbad [frontend_blocks] is scratch.  launch_frontend: the visible sources of
+// time t, packed in input order, go to dir + t dir_stride [tot[t]][3] (ENU)
+// and str + t str_stride [n_freq][tot[t]] (flux times the beam
+// 2^(-kbeam[f] theta^2), or times 1 if unit_beam).
+int frontend_blocks(int n_src);
+void launch_frontend_count(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
+                           int n_freq, int *bcnt, int *bbad, int *tot, hipStream_t st);
+void launch_frontend(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
+                     int n_freq, const double *kbeam_dev, bool unit_beam, const int *boff, const int *tot, double *dir,
+                     long long dir_stride, double *str, long long str_stride, hipStream_t st);
 
 // Direct sums.
 void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,

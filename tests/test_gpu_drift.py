@@ -127,3 +127,24 @@ def test_config4_drift_sampled(gpu_lib, ctx):
     ref = frontend.drift_vis(d.ant_enu, d.src_eq, d.freq_hz, d.flux, d.lst, d.latitude, d.beam_fwhm,
                              d.beam_nu_ref, pairs=sub)
     assert oracle.rel_l2(v[:, :, sub], ref) <= d.eps
+
+
+def test_horizon_sources_are_dropped_and_counted(gpu_lib, ctx):
+    d = synth.small_drift(9, n_ant=19, n_src=1000, n_freq=2, n_time=3)
+    v, rep = _run(gpu_lib, ctx, d)
+    alpha, delta = frontend.radec(d.src_eq)
+    visible = sum(int((frontend.enu(alpha, delta, float(t), d.latitude)[:, 2] > 0).sum()) for t in d.lst)
+    assert 0 < visible < 3 * 1000
+    assert rep["src_pairs"] == visible * d.n_pairs * len(d.freq_hz)
+    assert oracle.rel_l2(v, _ref(d)) <= d.eps
+
+
+def test_invalid_source_below_the_horizon_is_still_rejected(gpu_lib, ctx):
+    import dataclasses
+    d = synth.small_drift(10, n_ant=7, n_src=60, n_freq=1, n_time=1)
+    alpha, delta = frontend.radec(d.src_eq)
+    below = int(np.argmin(frontend.enu(alpha, delta, float(d.lst[0]), d.latitude)[:, 2]))
+    src = d.src_eq.copy()
+    src[below] *= np.nan
+    with pytest.raises(gpu_lib.FvError, match="EINVAL"):
+        _run(gpu_lib, ctx, dataclasses.replace(d, src_eq=src))
