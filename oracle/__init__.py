@@ -14,6 +14,8 @@ Contents
     (spread, oversampled FFT, deconvolve + interpolate), for per-stage checks.
   * ``type1``       -- lattice detection and the type-1 steps for gridded
     arrays (section 2.2.1).
+  * ``beams``       -- the direct sum with per-antenna beam patterns
+    (section 2.2.3), pair by pair.
   * ``frontend``    -- drift-scan front end: rotation of equatorial directions
     to ENU per sidereal time (section 2.3) and an analytic Gaussian power beam
     (section 2.4).
