@@ -186,6 +186,33 @@ typedef struct {
  * or non-finite fluxes (the output is then undefined). */
 fv_status fv_simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, void *stream, fv_report *rep);
 
+/* Per-antenna beams (paper section 2.2.3: when antennas carry different
+ * beam patterns, each unordered pair of patterns defines its own response to
+ * the sky, so one snapshot takes N_beam (N_beam + 1) / 2 transforms).  With
+ * real amplitude patterns a_p and pattern p(i) on antenna i:
+ *   V_ij(nu) = sum_s a_{p(i)}(nu, s) a_{p(j)}(nu, s) flux(nu, s)
+ *              exp(-2 pi i (nu / c) (x_i - x_j) . s_hat_s)
+ * to the eps contract of fv_simulate_dev.  One transform runs for each pattern
+ * pair that occurs among the antenna pairs (strengths a_p a_q flux, formed on
+ * the device); each visibility is taken from the transform of its pair. */
+typedef struct {
+    int n_ant;  const double *ant_enu;   /* DEVICE [n_ant][3] metres */
+    int n_src;  const double *src_lmn;   /* DEVICE [n_src][3] unit vectors (l, m, n) */
+    int n_freq; const double *freq_hz;   /* DEVICE [n_freq] */
+    const double *flux;                  /* DEVICE [n_freq][n_src] */
+    int n_beam; const double *beams;     /* DEVICE [n_beam][n_freq][n_src] amplitude patterns */
+    const int *beam_of_ant;              /* HOST [n_ant] pattern index of each antenna, in [0, n_beam) */
+    double eps;
+    unsigned flags;                      /* FV_* flags as in fv_problem; the NUFFT method only */
+} fv_beams;
+
+/* vis: DEVICE [n_freq][n_pairs] complex128.  Work is enqueued on `stream`;
+ * the call blocks once for the planning scalars.  Workspace: the product
+ * strengths and one visibility array per pattern pair.  Errors: FV_EINVAL for
+ * bad sizes, pattern indices out of range, non-unit directions or non-finite
+ * values. */
+fv_status fv_simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, void *stream, fv_report *rep);
+
 /* Serving loop: a worker thread admits submitted requests while HBM (the
  * context budget) and one of max_slots slots are free, and runs admitted
  * requests concurrently on per-slot streams.  Host buffers, which must stay

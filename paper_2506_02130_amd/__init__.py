@@ -35,7 +35,7 @@ STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "othe
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
-               "fv_simulate_drift")
+               "fv_simulate_drift", "fv_simulate_beams")
 
 
 class FvError(RuntimeError):
@@ -59,6 +59,14 @@ class Drift(ctypes.Structure):
                 ("flux", ctypes.c_void_p), ("n_time", ctypes.c_int), ("lst", ctypes.c_void_p),
                 ("latitude", ctypes.c_double), ("beam_fwhm", ctypes.c_double), ("beam_nu_ref", ctypes.c_double),
                 ("eps", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+class Beams(ctypes.Structure):
+    """fv_beams: per-antenna beam patterns."""
+    _fields_ = [("n_ant", ctypes.c_int), ("ant_enu", ctypes.c_void_p), ("n_src", ctypes.c_int),
+                ("src_lmn", ctypes.c_void_p), ("n_freq", ctypes.c_int), ("freq_hz", ctypes.c_void_p),
+                ("flux", ctypes.c_void_p), ("n_beam", ctypes.c_int), ("beams", ctypes.c_void_p),
+                ("beam_of_ant", ctypes.c_void_p), ("eps", ctypes.c_double), ("flags", ctypes.c_uint)]
 
 
 class Report(ctypes.Structure):
@@ -98,6 +106,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_debug_stages.argtypes = [vp, P(Problem), ctypes.c_int, dp, vp, ctypes.c_size_t, vp, ctypes.c_size_t]
     lib.fv_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
     lib.fv_simulate_drift.argtypes = [vp, P(Drift), vp, vp, P(Report)]
+    lib.fv_simulate_beams.argtypes = [vp, P(Beams), vp, vp, P(Report)]
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
@@ -236,6 +245,38 @@ class Context:
                   float(beam_nu_ref), float(eps), int(flags))
         rep = Report()
         _check(_lib.fv_simulate_drift(self._h, ctypes.byref(d), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
+                                      ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return self.last_report
+
+    def simulate_beams(self, ant_enu, src_lmn, freq_hz, flux, beams, beam_of_ant, vis, eps: float = 1e-6,
+                       flags: int = 0, stream=None) -> dict:
+        """Per-antenna beam patterns.  ``ant_enu``, ``src_lmn``, ``freq_hz``,
+        ``flux`` [n_freq, n_src], ``beams`` [n_beam, n_freq, n_src] and ``vis``
+        [n_freq, n_pairs, 2] are contiguous float64 torch tensors on this
+        context's device; ``beam_of_ant`` [n_ant] is a host integer array."""
+        import torch
+        for name, t in (("ant_enu", ant_enu), ("src_lmn", src_lmn), ("freq_hz", freq_hz), ("flux", flux),
+                        ("beams", beams), ("vis", vis)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
+        which = np.ascontiguousarray(beam_of_ant, dtype=np.int32).reshape(-1)
+        n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
+        n_beam = beams.shape[0] if beams.dim() == 3 else 1
+        for name, t, want in (("ant_enu", ant_enu, 3 * n_ant), ("src_lmn", src_lmn, 3 * n_src),
+                              ("freq_hz", freq_hz, n_freq), ("flux", flux, n_freq * n_src),
+                              ("beams", beams, n_beam * n_freq * n_src),
+                              ("vis", vis, 2 * n_freq * n_ant * (n_ant + 1) // 2)):
+            if t.numel() != want:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {want}")
+        if which.shape[0] != n_ant:
+            raise ValueError(f"beam_of_ant has {which.shape[0]} entries, expected {n_ant}")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        b = Beams(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
+                  freq_hz.data_ptr(), flux.data_ptr() if n_src else None, n_beam,
+                  beams.data_ptr() if n_src else None, which.ctypes.data, float(eps), int(flags))
+        rep = Report()
+        _check(_lib.fv_simulate_beams(self._h, ctypes.byref(b), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
                                       ctypes.byref(rep)))
         self.last_report = rep.as_dict()
         return self.last_report

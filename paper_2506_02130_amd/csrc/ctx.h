@@ -101,6 +101,9 @@ double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, c
 void run_direct(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int dim,
                 int prec, StageTimer *tm);
 void fill_report(StageTimer &tm, fv_report &r);
+// Adds the stage times, bytes, launches and pairs of one sub-call's report to
+// r (the first sub-call's report is copied whole).
+void accumulate_report(const fv_report &a, fv_report &r, bool first);
 // Lattice plan of an array (cached per array, tolerance and kernel width, with
 // its deconvolution tables for that width), null when the
 // East/North positions are not a lattice within tol metres.

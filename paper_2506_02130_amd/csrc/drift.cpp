@@ -49,23 +49,6 @@ void rotation(double lst, double lat, double *R) {
     std::memcpy(R, m, sizeof(m));
 }
 
-void add_report(const fv_report &a, fv_report &r, bool first) {
-    if (first) {
-        const double keep_pairs = r.src_pairs;
-        r = a;
-        r.src_pairs = keep_pairs + a.src_pairs;
-        return;
-    }
-    r.src_pairs += a.src_pairs;
-    r.model_bytes += a.model_bytes;
-    for (int i = 0; i < FV_NSTAGE; ++i) {
-        r.t_stage_ms[i] += a.t_stage_ms[i];
-        r.stage_bytes[i] += a.stage_bytes[i];
-        r.stage_launches[i] += a.stage_launches[i];
-    }
-    r.lattice = std::max(r.lattice, a.lattice);
-}
-
 }  // namespace
 
 void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st, fv_report *rep) {
@@ -176,7 +159,7 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
                 mt.n_src = ns;
                 fv_report r;
                 run_device(ctx, slot, mt, in, in.vis, &r);
-                add_report(r, total, t0g == 0 && t == 0);
+                accumulate_report(r, total, t0g == 0 && t == 0);
             }
         }
     } catch (...) {

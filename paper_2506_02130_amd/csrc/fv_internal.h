@@ -316,6 +316,13 @@ void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
 // time t, packed in input order, go to dir + t dir_stride [tot[t]][3] (ENU)
 // and str + t str_stride [n_freq][tot[t]] (flux times the beam
 // 2^(-kbeam[f] theta^2), or times 1 if unit_beam).
+// Per-antenna beams: prod [n_vec][n_fs] = beams[p_v] * beams[q_v] with
+// pq_dev [n_vec][2] pattern pairs and beams [n_beam][n_fs]; vis [n_freq][n_pairs]
+// (complex) = tmp [vec[k]][n_freq][n_pairs] at each pair k.
+void launch_beam_products(const double *beams, const int *pq_dev, int n_vec, long long n_fs, double *prod,
+                          hipStream_t st);
+void launch_beam_select(const double *tmp, const int *vec_dev, long long n_pairs, int n_freq, double *vis,
+                        hipStream_t st);
 int frontend_blocks(int n_src);
 void launch_frontend_count(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
                            int n_freq, int *bcnt, int *bbad, int *tot, hipStream_t st);

@@ -446,6 +446,23 @@ void run_direct(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &i
     }
 }
 
+void accumulate_report(const fv_report &a, fv_report &r, bool first) {
+    if (first) {
+        const double keep_pairs = r.src_pairs;
+        r = a;
+        r.src_pairs = keep_pairs + a.src_pairs;
+        return;
+    }
+    r.src_pairs += a.src_pairs;
+    r.model_bytes += a.model_bytes;
+    for (int i = 0; i < FV_NSTAGE; ++i) {
+        r.t_stage_ms[i] += a.t_stage_ms[i];
+        r.stage_bytes[i] += a.stage_bytes[i];
+        r.stage_launches[i] += a.stage_launches[i];
+    }
+    r.lattice = std::max(r.lattice, a.lattice);
+}
+
 void fill_report(StageTimer &tm, fv_report &r) {
     tm.collect();
     for (int i = 0; i < FV_NSTAGE; ++i) {
