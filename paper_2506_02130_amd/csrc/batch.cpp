@@ -27,8 +27,8 @@ std::vector<BatchInputs> upload_batch(Slot &slot, int n, const fv_problem *ps) {
         const fv_problem &p = ps[i];
         const size_t fs = sizeof(double) * (size_t)p.n_freq * p.n_src;
         const long long np = (long long)p.n_ant * (p.n_ant + 1) / 2;
-        total += al(24 * (size_t)p.n_ant) + al(24 * (size_t)p.n_src) + al(fs) * (p.beam ? 2 : 1) +
-                 al(16 * (size_t)np * p.n_freq);
+        total += al(24 * (size_t)p.n_ant) + al(8 * (size_t)p.n_freq) + al(24 * (size_t)p.n_src) +
+                 al(fs) * (p.beam ? 2 : 1) + al(16 * (size_t)np * p.n_freq);
     }
     slot.inputs.ensure(total + 256);
     slot.inputs.reset();
@@ -41,6 +41,8 @@ std::vector<BatchInputs> upload_batch(Slot &slot, int n, const fv_problem *ps) {
         const long long np = (long long)p.n_ant * (p.n_ant + 1) / 2;
         b.in.ant = (double *)slot.inputs.take(24 * (size_t)p.n_ant);
         FV_HIP(hipMemcpyAsync((void *)b.in.ant, p.ant_enu, 24 * (size_t)p.n_ant, hipMemcpyHostToDevice, st));
+        b.in.freq = (double *)slot.inputs.take(8 * (size_t)p.n_freq);
+        FV_HIP(hipMemcpyAsync((void *)b.in.freq, p.freq_hz, 8 * (size_t)p.n_freq, hipMemcpyHostToDevice, st));
         if (p.n_src) {
             b.in.src = (double *)slot.inputs.take(24 * (size_t)p.n_src);
             b.in.flux = (double *)slot.inputs.take(fs);

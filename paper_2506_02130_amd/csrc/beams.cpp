@@ -115,6 +115,7 @@ void simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, hipStream_t st,
         for (int v = 0; v < n_vec; ++v) {
             DevInputs in;
             in.ant = b->ant_enu;
+            in.freq = b->freq_hz;
             in.src = b->src_lmn;
             in.flux = b->flux;
             in.beam = prod + (size_t)v * n_fs;
@@ -133,6 +134,7 @@ void simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, hipStream_t st,
         launch_beam_select(tmp, vec_dev, n_pairs, n_freq, vis, st);
     } catch (...) {
         slot.stream = keep;
+        (void)hipEventRecord(slot.done, st);  // work already enqueued must finish before the workspace is reused
         throw;
     }
     slot.stream = keep;

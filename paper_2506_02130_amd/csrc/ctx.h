@@ -19,6 +19,7 @@ namespace fv {
 // Device pointers of one problem's inputs plus the host-side source box.
 struct DevInputs {
     const double *ant = nullptr, *src = nullptr, *flux = nullptr, *beam = nullptr;
+    const double *freq = nullptr;  // frequencies on the device
     double *vis = nullptr;
     double s_c[3] = {0, 0, 0}, S[3] = {0, 0, 0};
     // device input check's block partials (largest |flux beam| per flat range
@@ -59,6 +60,21 @@ struct fv_ctx {
     double *scalar_buf = nullptr;
     size_t scalar_cap = 0;  // doubles
     fv::PinnedBuf plan_pin;  // host staging of the planning scalars of fv_simulate_dev
+    // The device entry point's last planning scalars, for calls that repeat its
+    // arguments (same device pointers and sizes): when that call took the type-1
+    // path, the next one enqueues the type-1 kernels right behind its input check
+    // on the last call's antenna positions and frequencies, then verifies them
+    // (and the path choice) against the new check and recomputes on a mismatch.
+    struct DevSpec {
+        bool valid = false;
+        const void *ptr[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // ant, freq, src, flux, beam
+        int n_ant = 0, n_freq = 0, n_src = 0;
+        double eps = 0;
+        unsigned flags = 0;
+        std::vector<double> ant, freq;
+        double s_c[3] = {0, 0, 0}, S[3] = {0, 0, 0};
+        hipEvent_t ev = nullptr;  // the check's copy to the host
+    } spec;
     fv::TuneCache tunes;     // autotuned FFT launch shapes
     fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
     double *scalars(size_t n_doubles) {
@@ -108,6 +124,11 @@ void accumulate_report(const fv_report &a, fv_report &r, bool first);
 // its deconvolution tables for that width), null when the
 // East/North positions are not a lattice within tol metres.
 std::shared_ptr<LatticePlan> ctx_lattice(fv_ctx *ctx, const double *ant_host, int n_ant, double tol, int w);
+// The lattice plan and kernel width when the type-1 path should run for this
+// problem (lattice array, fine grid no larger than the type-3 grid at the top
+// frequency for the source box in `in`), else null.
+std::shared_ptr<LatticePlan> lattice_choice(fv_ctx *ctx, const fv_problem &p, const DevInputs &in, int prec,
+                                            int *w_out);
 // The type-1 path (paper section 2.2.1) for a coplanar problem when its
 // antennas form a lattice and its fine grid is the smaller one; false when
 // the type-3 path should run instead.

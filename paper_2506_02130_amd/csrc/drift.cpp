@@ -143,6 +143,7 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
                     fail(FV_EINVAL, "invalid source vectors or fluxes (directions must be unit vectors)");
                 DevInputs in;
                 in.ant = ant_dev;
+                in.freq = freq_dev;
                 in.src = dir + t * dir_stride;
                 in.flux = str + t * str_stride;
                 in.beam = nullptr;
@@ -164,6 +165,7 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
         }
     } catch (...) {
         slot.stream = keep;
+        (void)hipEventRecord(slot.done, st);  // work already enqueued must finish before the workspace is reused
         throw;
     }
     slot.stream = keep;

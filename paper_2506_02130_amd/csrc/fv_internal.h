@@ -23,6 +23,7 @@ constexpr int kMinW = 3;
 constexpr int kQuadHalf = 32;    // positive nodes of the 64-node Gauss-Legendre rule
 constexpr int kSubBin = 8;       // sub-bin edge (cells) of the source sort along x and y
 constexpr int kSubBinZ = 4;      // sub-bin edge along z
+constexpr double kMaxSrcPerCell = 16.0;  // FP32 grids while sources per covered cell stay below this
 constexpr int kSrcCheckBlocks = 2048;  // blocks of the input-check pass (one partial each)
 
 // ---------------------------------------------------------------------------
@@ -251,6 +252,14 @@ struct LatticePlan {
     int K[2] = {0, 0};
     int w = 0;                          // kernel width the tables below are for
     std::vector<double> dc;             // [N0 + N1] deconvolution factor per mode and axis
+    // device copy [dc][k as int pairs] on the context's device, made by
+    // lattice_tables; freed (after a device synchronisation, since kernels may
+    // still read it) when the plan goes
+    void *dev = nullptr;
+    LatticePlan() = default;
+    LatticePlan(const LatticePlan &) = delete;
+    LatticePlan &operator=(const LatticePlan &) = delete;
+    ~LatticePlan();
 };
 // True when the array's East/North positions form a lattice within `tol`
 // metres (n_ant >= 2, not collinear).
@@ -262,14 +271,15 @@ double phihat_host(double xi, const double *qtab);  // qtab from quad_table
 // holds lattice_work_bytes(); `stage` is pinned host staging.
 size_t lattice_work_bytes(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w);
 bool lattice_fits(const LatticePlan &lp, int prec_bits, int w);  // LDS limits of the kernels
-void lattice_tables(LatticePlan &lp, int w);  // fills lp.w and lp.dc (host, once per plan)
+void lattice_tables(LatticePlan &lp, int w);  // fills lp.w, lp.dc and lp.dev (once per plan)
 void lattice_grid(const LatticePlan &lp, int w, int nf[2]);       // fine periodic grid per axis
-// cmax_part / cmax_span: the device input check's block partials (each
-// holds the largest |flux beam| of a flat range of cmax_span values), or null
-// to have the spreading kernel find each chunk's largest strength itself.
-double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_host, int n_freq,
+// freq_dev: the frequencies on the device.  cmax_part / cmax_span: the device
+// input check's block partials (each holds the largest |flux beam| of a flat
+// range of cmax_span values), or null to have the spreading kernel find each
+// chunk's largest strength itself.  Enqueues kernels only (no copies).
+double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_dev, int n_freq,
                       const double *flux_dev, const double *beam_dev, const double *cmax_part, long long cmax_span,
-                      int n_ant, int prec_bits, int w, double *vis_dev, void *work, PinnedBuf &stage, hipStream_t st,
+                      int n_ant, int prec_bits, int w, double *vis_dev, void *work, hipStream_t st,
                       StageTimer *timer);
 
 // Enqueue the whole type-3 pipeline for jobs that share (dim, precision, w).

@@ -46,7 +46,7 @@ struct T1Params {
     const double *src, *flux, *beam;
     const double *cmax;   // input-check partials (largest |c| per flat range of cspan values), or null
     long long cspan;
-    const double *kturn;  // [n_freq] nu / c
+    const double *freq;   // [n_freq] Hz (device)
     const double *dc;     // [N0 + N1] deconvolution factors
     const int *kc;        // [n_ant][2] lattice coordinates
     void *part;           // [n_freq][nchunk][nf1][nf0] 64-bit fixed point
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kT1Threads) void k_t1_spread(T1Params P) {
     const int f = blockIdx.y, ch = blockIdx.x;
     const int s0 = ch * P.chunk, s1 = min(s0 + P.chunk, P.n_src);
     const double scale = ldexp(1.0, t1_chunk_scale(P, f, ch, s0, s1, G, g0 * g1, kWrap ? 50 : 62));
-    const double kt = P.kturn[f];
+    const double kt = P.freq[f] * (1.0 / kCLight);  // nu / c
     const double magic = 6755399441055744.0;  // 1.5 * 2^52
     const R beta = (R)P.beta, inv_hw = (R)(2.0 / W);
     for (int s = s0 + (int)threadIdx.x; s < s1; s += kT1Threads) {
@@ -148,7 +148,9 @@ __global__ __launch_bounds__(kT1Threads) void k_t1_spread(T1Params P) {
             const double g = (u - floor(u)) * P.nf[a];  // grid coordinate in [0, nf)
             const double lc = ceil(g - 0.5 * W);         // first cell of the kernel
             const R off = (R)(g - lc);
-            l[a] = (int)lc < 0 ? (int)lc + P.nf[a] : (int)lc;  // in [0, nf): the footprint ends below nf + W - 1
+            // in [0, nf), so the footprint ends below nf + W - 1; the clamp only acts
+            // on non-finite input (which the call rejects) and keeps every add in range
+            l[a] = min(max((int)lc < 0 ? (int)lc + P.nf[a] : (int)lc, 0), P.nf[a] - 1);
             const double sc = a == 0 ? 1.0 : c * scale;
 #pragma unroll
             for (int i = 0; i < W; ++i) wd[a][i] = sc * (double)t1_phi((R)((R)i - off) * inv_hw, beta);
@@ -267,7 +269,7 @@ struct T1Shape {
     int nf[2], N[2], gs[2];
     int nchunk, chunk;
     size_t lds;  // spreading workgroup's LDS grid bytes
-    size_t part_bytes, t_bytes, mode_bytes, tab_bytes;
+    size_t part_bytes, t_bytes, mode_bytes;
 };
 
 T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w) {
@@ -292,7 +294,6 @@ T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int pr
     s.part_bytes = (size_t)n_freq * s.nchunk * (cells * 8 + 8);
     s.t_bytes = (size_t)n_freq * s.nf[1] * s.N[0] * sizeof(double2);
     s.mode_bytes = (size_t)n_freq * s.N[0] * s.N[1] * sizeof(double2);
-    s.tab_bytes = sizeof(double) * ((size_t)n_freq + s.N[0] + s.N[1]) + sizeof(int) * 2 * (size_t)n_ant;
     return s;
 }
 
@@ -325,6 +326,25 @@ void lattice_tables(LatticePlan &lp, int w) {
         for (int k = 0; k < sh.N[a]; ++k) lp.dc[o + k] = h / (alpha * phihat_host(alpha * (k - lp.K[a]), qtab));
     }
     lp.w = w;
+    // one device copy: [dc][k], uploaded once (synchronous; the plan is cached)
+    const size_t bd = sizeof(double) * lp.dc.size(), bk = sizeof(int) * lp.k.size();
+    std::vector<char> h(bd + bk);
+    std::memcpy(h.data(), lp.dc.data(), bd);
+    std::memcpy(h.data() + bd, lp.k.data(), bk);
+    if (lp.dev) {
+        FV_HIP(hipDeviceSynchronize());
+        FV_HIP(hipFree(lp.dev));
+        lp.dev = nullptr;
+    }
+    FV_HIP(hipMalloc(&lp.dev, bd + bk));
+    FV_HIP(hipMemcpy(lp.dev, h.data(), bd + bk, hipMemcpyHostToDevice));
+}
+
+LatticePlan::~LatticePlan() {
+    if (dev) {
+        (void)hipDeviceSynchronize();  // kernels enqueued with this plan may still read the table
+        (void)hipFree(dev);
+    }
 }
 
 void lattice_grid(const LatticePlan &lp, int w, int nf[2]) {
@@ -341,13 +361,12 @@ bool lattice_fits(const LatticePlan &lp, int prec_bits, int w) {
 
 size_t lattice_work_bytes(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w) {
     const T1Shape s = t1_shape(lp, n_src, n_freq, n_ant, prec_bits, w);
-    return al256(s.part_bytes) + al256(s.t_bytes) + al256(s.mode_bytes) + al256(s.tab_bytes) + 256;
+    return al256(s.part_bytes) + al256(s.t_bytes) + al256(s.mode_bytes) + 256;
 }
 
-double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_host, int n_freq,
+double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_dev, int n_freq,
                       const double *flux_dev, const double *beam_dev, const double *cmax_part, long long cmax_span,
-                      int n_ant, int prec_bits, int w, double *vis_dev, void *work, PinnedBuf &stage, hipStream_t st,
-                      StageTimer *tm) {
+                      int n_ant, int prec_bits, int w, double *vis_dev, void *work, hipStream_t st, StageTimer *tm) {
     StageTimer dummy;
     if (!tm) tm = &dummy;
     const T1Shape sh = t1_shape(lp, n_src, n_freq, n_ant, prec_bits, w);
@@ -384,18 +403,12 @@ double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, c
     wp += al256(sh.t_bytes);
     P.modes = (double2 *)wp;
     wp += al256(sh.mode_bytes);
-    // tables: nu / c per frequency, deconvolution factors per axis, lattice coordinates
-    char *tab = wp;
-    char *host = (char *)stage.get(sh.tab_bytes);
-    double *hk = (double *)host, *hdc = hk + n_freq;
-    for (int f = 0; f < n_freq; ++f) hk[f] = freq_host[f] / kCLight;
-    if (lp.w != w || lp.dc.size() != (size_t)(sh.N[0] + sh.N[1])) fail(FV_EDEVICE, "lattice tables not prepared");
-    std::memcpy(hdc, lp.dc.data(), sizeof(double) * lp.dc.size());
-    std::memcpy(hdc + sh.N[0] + sh.N[1], lp.k.data(), sizeof(int) * 2 * (size_t)n_ant);
-    FV_HIP(hipMemcpyAsync(tab, host, sh.tab_bytes, hipMemcpyHostToDevice, st));
-    stage.record(st);
-    P.kturn = (const double *)tab;
-    P.dc = P.kturn + n_freq;
+    // device tables of the plan: deconvolution factors per axis, lattice coordinates
+    if (lp.w != w || !lp.dev || lp.dc.size() != (size_t)(sh.N[0] + sh.N[1]) || lp.k.size() != 2 * (size_t)n_ant)
+        fail(FV_EDEVICE, "lattice tables not prepared");
+    if (!freq_dev) fail(FV_EDEVICE, "lattice path needs the frequencies on the device");
+    P.freq = freq_dev;
+    P.dc = (const double *)lp.dev;
     P.kc = (const int *)(P.dc + sh.N[0] + sh.N[1]);
 
     const size_t cells = (size_t)sh.nf[0] * sh.nf[1];

@@ -120,7 +120,9 @@ void StageTimer::begin(int stage, hipStream_t s) {
     if (used + 2 > pool.size()) {
         for (int i = 0; i < 16; ++i) {
             hipEvent_t e;
-            FV_HIP(hipEventCreate(&e));
+            // timestamps only: no system-scope fence (the data the stages write
+            // is made visible by the caller's own synchronisation)
+            FV_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             pool.push_back(e);
         }
     }
@@ -330,26 +332,35 @@ std::shared_ptr<LatticePlan> ctx_lattice(fv_ctx *ctx, const double *ant_host, in
     return lp;
 }
 
-bool run_lattice(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int prec,
-                 StageTimer *tm, fv_report &r) {
+std::shared_ptr<LatticePlan> lattice_choice(fv_ctx *ctx, const fv_problem &p, const DevInputs &in, int prec, int *w_out) {
     double numax = 0.0;
     for (int f = 0; f < p.n_freq; ++f) numax = std::max(numax, p.freq_hz[f]);
     const double tol = p.eps * kCLight / (20.0 * M_PI * numax);
     const int w = kernel_width(p.eps);
     std::shared_ptr<LatticePlan> lp = ctx_lattice(ctx, p.ant_enu, p.n_ant, tol, w);
-    if (!lp) return false;
-    if (!lattice_fits(*lp, prec, w)) return false;
+    if (!lp || !lattice_fits(*lp, prec, w)) return nullptr;
     int nf[2];
     lattice_grid(*lp, w, nf);
     GeomPlan g = ctx_geometry(ctx, p.ant_enu, p.n_ant, 2, p.eps, in.s_c, in.S, !(p.flags & FV_NO_FOLD));
     const SnapPlan top = plan_snapshot(g, numax);
-    if ((double)nf[0] * nf[1] > (double)top.n1[0] * top.n1[1]) return false;
+    if ((double)nf[0] * nf[1] > (double)top.n1[0] * top.n1[1]) return nullptr;
+    *w_out = w;
+    return lp;
+}
+
+bool run_lattice(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &in, double *vis_dev, int prec,
+                 StageTimer *tm, fv_report &r) {
+    int w = 0;
+    std::shared_ptr<LatticePlan> lp = lattice_choice(ctx, p, in, prec, &w);
+    if (!lp) return false;
+    int nf[2];
+    lattice_grid(*lp, w, nf);
     const size_t need = lattice_work_bytes(*lp, p.n_src, p.n_freq, p.n_ant, prec, w);
     slot.arena.ensure(need);
     slot.arena.reset();
     void *work = slot.arena.take(need);
-    r.model_bytes += launch_lattice(*lp, in.src, p.n_src, p.freq_hz, p.n_freq, in.flux, in.beam, in.cmax,
-                                    in.cmax_span, p.n_ant, prec, w, vis_dev, work, slot.arena.host, slot.stream, tm);
+    r.model_bytes += launch_lattice(*lp, in.src, p.n_src, in.freq, p.n_freq, in.flux, in.beam, in.cmax,
+                                    in.cmax_span, p.n_ant, prec, w, vis_dev, work, slot.stream, tm);
     r.lattice = 1;
     r.w = w;
     r.n1[0] = nf[0];
@@ -390,6 +401,20 @@ NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in,
         if (p.freq_hz[f] > p.freq_hz[best_f]) best_f = f;
     }
     if (top) *top = jobs[jobs.size() - n_freq + best_f].plan;
+    // FP32 grids sum the sources of a cell in FP32; when the sources crowd into
+    // few cells (more than kMaxSrcPerCell per cell the source box covers, at
+    // the lowest frequency) that sum would no longer hold eps >= 1e-6, so the
+    // grids switch to FP64 unless the caller forced a precision
+    if (k.prec == 32 && !(p.flags & FV_PREC_MASK) && n_src > 0) {
+        int lo_f = 0;
+        for (int f = 0; f < n_freq; ++f)
+            if (p.freq_hz[f] < p.freq_hz[lo_f]) lo_f = f;
+        const SnapPlan &lo = jobs[jobs.size() - n_freq + lo_f].plan;
+        double occ = 1.0;
+        for (int a = 0; a < k.dim; ++a)
+            occ *= std::max(1.0, 2.0 * kSigma / M_PI * lo.X[a] * std::max(lo.S[a], 1.0 / lo.X[a]));
+        if ((double)n_src > kMaxSrcPerCell * occ) k.prec = 64;
+    }
     return k;
 }
 
@@ -504,6 +529,7 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
         SnapPlan top;
         NufftGroupKey k = append_jobs(ctx, *p, in, vis_dev, st, jobs, hold, &top);
         r.model_bytes = execute_jobs(ctx, slot, jobs, k, &tm);
+        r.prec_bits = k.prec;
         r.w = k.w;
         r.fold_axis = k.fold_axis;
         for (int a = 0; a < 3; ++a) {
@@ -522,16 +548,19 @@ DevInputs upload(Slot &slot, const fv_problem *p, double *s_c, double *S) {
     const size_t b_fs = sizeof(double) * (size_t)n_freq * n_src;
     const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
     const size_t b_vis = sizeof(double) * 2 * (size_t)n_pairs * n_freq;
-    slot.inputs.ensure(b_ant + b_src + 2 * b_fs + b_vis + 8 * 256);
+    const size_t b_freq = sizeof(double) * (size_t)n_freq;
+    slot.inputs.ensure(b_ant + b_freq + b_src + 2 * b_fs + b_vis + 8 * 256);
     slot.inputs.reset();
     DevInputs in;
     in.ant = (double *)slot.inputs.take(b_ant);
+    in.freq = (double *)slot.inputs.take(b_freq);
     in.src = n_src ? (double *)slot.inputs.take(b_src) : nullptr;
     in.flux = n_src ? (double *)slot.inputs.take(b_fs) : nullptr;
     in.beam = (n_src && p->beam) ? (double *)slot.inputs.take(b_fs) : nullptr;
     in.vis = (double *)slot.inputs.take(b_vis);
     hipStream_t st = slot.stream;
     FV_HIP(hipMemcpyAsync((void *)in.ant, p->ant_enu, b_ant, hipMemcpyHostToDevice, st));
+    FV_HIP(hipMemcpyAsync((void *)in.freq, p->freq_hz, b_freq, hipMemcpyHostToDevice, st));
     if (n_src) {
         FV_HIP(hipMemcpyAsync((void *)in.src, p->src_lmn, b_src, hipMemcpyHostToDevice, st));
         FV_HIP(hipMemcpyAsync((void *)in.flux, p->flux, b_fs, hipMemcpyHostToDevice, st));
@@ -623,6 +652,7 @@ void fv_destroy(fv_ctx *ctx) {
         fv_server_stop(ctx);
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
+        if (ctx->spec.ev) (void)hipEventDestroy(ctx->spec.ev);
     } catch (...) {
     }
     delete ctx;
@@ -660,44 +690,95 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     fv::launch_validate(p->src_lmn, p->n_src, p->flux, p->beam, p->n_freq, p->ant_enu, p->n_ant, p->freq_hz, dev,
                         st);
     FV_HIP(hipMemcpyAsync(pin, dev, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
-    FV_HIP(hipStreamSynchronize(st));
-    double *host_chk = pin, *pfreq = pin + 8, *pant = pfreq + p->n_freq;
-    const std::vector<double> ant(pant, pant + n_ant3), freq(pfreq, pfreq + p->n_freq);
-    fv_problem meta = *p;
-    meta.ant_enu = ant.data();
-    meta.freq_hz = freq.data();
-    for (double a : ant)
-        if (!std::isfinite(a)) fv::fail(FV_EINVAL, "non-finite antenna position");
-    for (double f : freq)
-        if (!(std::isfinite(f) && f > 0)) fv::fail(FV_EINVAL, "frequency must be finite and > 0");
-    if (p->n_src > 0 && (host_chk[6] != 0.0 || host_chk[7] != 0.0))
-        fv::fail(FV_EINVAL, "invalid source directions or strengths");
-    if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6) fv::fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
-    fv::DevInputs in;
-    in.ant = nullptr;
-    in.src = p->src_lmn;
-    in.flux = p->flux;
-    in.beam = p->beam;
-    in.vis = vis;
-    const int dim = fv::choose_dim(ant.data(), p->n_ant, p->eps, freq.data(), p->n_freq, p->flags);
-    for (int a = 0; a < 3; ++a) {
-        in.s_c[a] = 0;
-        in.S[a] = 0;
-    }
-    if (p->n_src > 0)
-        for (int a = 0; a < dim; ++a) {
-            in.s_c[a] = 0.5 * (host_chk[2 * a] + host_chk[2 * a + 1]);
-            in.S[a] = 0.5 * (host_chk[2 * a + 1] - host_chk[2 * a]);
+    auto &sp = ctx->spec;
+    const void *ptrs[5] = {p->ant_enu, p->freq_hz, p->src_lmn, p->flux, p->beam};
+    const bool speculate = sp.valid && std::memcmp(sp.ptr, ptrs, sizeof(ptrs)) == 0 && sp.n_ant == p->n_ant &&
+                           sp.n_freq == p->n_freq && sp.n_src == p->n_src && sp.eps == p->eps && sp.flags == p->flags;
+    sp.valid = false;  // set again below once this call's scalars are known
+    // the device inputs; the source box is filled from the host-side check
+    auto dev_inputs = [&](const double *box) {
+        fv::DevInputs in;
+        in.ant = p->ant_enu;
+        in.freq = p->freq_hz;
+        in.src = p->src_lmn;
+        in.flux = p->flux;
+        in.beam = p->beam;
+        in.vis = vis;
+        for (int a = 0; a < 3; ++a) {
+            in.s_c[a] = box[a];
+            in.S[a] = box[3 + a];
         }
-    in.ant = p->ant_enu;
-    in.cmax = fv::validate_partials(dev, p->n_ant, p->n_freq);
-    in.cmax_span = fv::validate_span((long long)p->n_src * p->n_freq);
+        in.cmax = fv::validate_partials(dev, p->n_ant, p->n_freq);
+        in.cmax_span = fv::validate_span((long long)p->n_src * p->n_freq);
+        return in;
+    };
     hipStream_t keep = slot.stream;
     slot.stream = st;
     try {
-        fv::run_device(ctx, slot, meta, in, vis, rep);
+        fv_report rs;
+        bool ran = false;
+        if (speculate) {
+            if (!sp.ev) FV_HIP(hipEventCreateWithFlags(&sp.ev, hipEventDisableTiming));
+            FV_HIP(hipEventRecord(sp.ev, st));
+            fv_problem meta = *p;
+            meta.ant_enu = sp.ant.data();
+            meta.freq_hz = sp.freq.data();
+            double box[6];
+            std::memcpy(box, sp.s_c, sizeof(sp.s_c));
+            std::memcpy(box + 3, sp.S, sizeof(sp.S));
+            fv::run_device(ctx, slot, meta, dev_inputs(box), vis, &rs);  // the last call's path: type 1
+            FV_HIP(hipEventSynchronize(sp.ev));
+            ran = true;
+        } else {
+            FV_HIP(hipStreamSynchronize(st));
+        }
+        double *host_chk = pin, *pfreq = pin + 8, *pant = pfreq + p->n_freq;
+        const std::vector<double> ant(pant, pant + n_ant3), freq(pfreq, pfreq + p->n_freq);
+        fv_problem meta = *p;
+        meta.ant_enu = ant.data();
+        meta.freq_hz = freq.data();
+        for (double a : ant)
+            if (!std::isfinite(a)) fv::fail(FV_EINVAL, "non-finite antenna position");
+        for (double f : freq)
+            if (!(std::isfinite(f) && f > 0)) fv::fail(FV_EINVAL, "frequency must be finite and > 0");
+        if (p->n_src > 0 && (host_chk[6] != 0.0 || host_chk[7] != 0.0))
+            fv::fail(FV_EINVAL, "invalid source directions or strengths");
+        if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6)
+            fv::fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
+        const int dim = fv::choose_dim(ant.data(), p->n_ant, p->eps, freq.data(), p->n_freq, p->flags);
+        double box[6] = {0, 0, 0, 0, 0, 0};
+        if (p->n_src > 0)
+            for (int a = 0; a < dim; ++a) {
+                box[a] = 0.5 * (host_chk[2 * a] + host_chk[2 * a + 1]);
+                box[3 + a] = 0.5 * (host_chk[2 * a + 1] - host_chk[2 * a]);
+            }
+        const fv::DevInputs in = dev_inputs(box);
+        if (ran) {
+            // the speculation holds when the geometry is the last call's and the
+            // type-1 path is still the choice for this call's source box
+            int w = 0;
+            ran = ant == sp.ant && freq == sp.freq && dim == 2 &&
+                  fv::lattice_choice(ctx, meta, in, fv::choose_prec(p->eps, p->flags), &w) != nullptr;
+            if (ran && rep) *rep = rs;
+        }
+        if (!ran) fv::run_device(ctx, slot, meta, in, vis, rep ? rep : &rs);
+        const fv_report &used = rep ? *rep : rs;
+        if (used.lattice && p->n_src > 0 && (p->flags & FV_METHOD_MASK) == FV_METHOD_NUFFT && !(p->flags & FV_GRAPH)) {
+            std::memcpy(sp.ptr, ptrs, sizeof(ptrs));
+            sp.n_ant = p->n_ant;
+            sp.n_freq = p->n_freq;
+            sp.n_src = p->n_src;
+            sp.eps = p->eps;
+            sp.flags = p->flags;
+            sp.ant = ant;
+            sp.freq = freq;
+            std::memcpy(sp.s_c, box, sizeof(sp.s_c));
+            std::memcpy(sp.S, box + 3, sizeof(sp.S));
+            sp.valid = true;
+        }
     } catch (...) {
         slot.stream = keep;
+        (void)hipEventRecord(slot.done, st);  // work already enqueued must finish before the workspace is reused
         throw;
     }
     slot.stream = keep;

@@ -92,3 +92,62 @@ def test_successive_device_calls_on_different_streams_are_ordered(gpu_lib):
             o = vis_s.cpu().numpy()
             assert oracle.rel_l2(o[..., 0] + 1j * o[..., 1], oracle.direct_problem(small)) <= small.eps
             assert oracle.rel_l2(v_o, oracle.direct_problem(other)) <= other.eps
+
+
+def test_repeated_device_calls_follow_changed_contents(gpu_lib):
+    """Calls repeating the device pointers of a type-1 call start its kernels
+    before the planning scalars are back; every change of the contents behind
+    those pointers must still give the right answer: new fluxes, moved
+    antennas, new frequencies, a source box that flips the path choice, and an
+    invalid input followed by a valid one."""
+    import torch
+    fv = gpu_lib
+    dev = torch.device("cuda:0")
+    p = synth.small_problem(160, n_ant=37, n_src=3000, n_freq=3, hex_layout=True)
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(p, k), dtype=np.float64)).to(dev)
+         for k in ("ant_enu", "src_lmn", "freq_hz", "flux", "beam")}
+    vis = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+
+    def run(c, ref_problem):
+        rep = c.simulate_dev(t["ant_enu"], t["src_lmn"], t["freq_hz"], t["flux"], t["beam"], vis, eps=1e-6)
+        torch.cuda.synchronize()
+        o = vis.cpu().numpy()
+        assert oracle.rel_l2(o[..., 0] + 1j * o[..., 1], oracle.direct_problem(ref_problem)) <= 1e-6
+        return rep
+
+    import dataclasses
+    with fv.Context(0) as c:
+        assert run(c, p)["lattice"] == 1
+        assert run(c, p)["lattice"] == 1                       # repeated as is
+        q = dataclasses.replace(p, flux=p.flux * np.linspace(0.5, 2.0, p.n_src)[None, :])
+        t["flux"].copy_(torch.from_numpy(q.flux))
+        run(c, q)                                              # new strengths
+        ant2 = synth.hex_array(37) * 1.3 + np.array([2.0, -1.0, 0.0])
+        q = dataclasses.replace(q, ant_enu=ant2)
+        t["ant_enu"].copy_(torch.from_numpy(ant2))
+        assert run(c, q)["lattice"] == 1                       # moved and rescaled array
+        rng = np.random.default_rng(3)
+        ant3 = synth.disk_array(rng, 37, 60.0, 0.0)
+        q3 = dataclasses.replace(q, ant_enu=ant3)
+        t["ant_enu"].copy_(torch.from_numpy(ant3))
+        assert run(c, q3)["lattice"] == 0                      # no longer a lattice
+        t["ant_enu"].copy_(torch.from_numpy(ant2))
+        run(c, q)
+        q = dataclasses.replace(q, freq_hz=q.freq_hz * 1.1)
+        t["freq_hz"].copy_(torch.from_numpy(q.freq_hz))
+        run(c, q)                                              # new frequencies
+        # a tiny source patch: the type-3 grid becomes the smaller one
+        src = np.tile(np.array([[0.001, 0.002, 0.0]]), (p.n_src, 1))
+        src[:, 0] += np.linspace(0, 1e-4, p.n_src)
+        src[:, 2] = np.sqrt(1 - src[:, 0] ** 2 - src[:, 1] ** 2)
+        qs = dataclasses.replace(q, src_lmn=src)
+        t["src_lmn"].copy_(torch.from_numpy(src))
+        assert run(c, qs)["lattice"] == 0
+        t["src_lmn"].copy_(torch.from_numpy(p.src_lmn))
+        run(c, q)
+        bad = t["flux"].clone()
+        t["flux"][0, 5] = float("nan")
+        with pytest.raises(fv.FvError, match="EINVAL"):
+            c.simulate_dev(t["ant_enu"], t["src_lmn"], t["freq_hz"], t["flux"], t["beam"], vis, eps=1e-6)
+        t["flux"].copy_(bad)
+        run(c, q)

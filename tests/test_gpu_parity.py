@@ -248,3 +248,19 @@ def test_fp64_multi_frequency(gpu_lib, ctx):
     v, rep = _run(gpu_lib, ctx, p, eps=1e-10, flags=gpu_lib.NO_LATTICE)
     errs = [oracle.rel_l2(v[f], oracle.direct_problem(p)[f]) for f in range(3)]
     assert max(errs) <= 1e-10, errs
+
+
+@pytest.mark.parametrize("n_src", [10, 300, 3000])
+def test_crowded_sources_keep_eps(gpu_lib, ctx, n_src):
+    # every source inside one grid cell of a random array: FP32 cell sums would
+    # lose the 1e-6 contract, so the grids switch to FP64 (unless forced)
+    import dataclasses
+    fv = gpu_lib
+    p = synth.small_problem(170, n_ant=30, n_src=n_src, n_freq=2)
+    src = np.tile(np.array([[0.001, 0.002, 0.0]]), (n_src, 1))
+    src[:, 0] += np.linspace(0, 1e-4, n_src)
+    src[:, 2] = np.sqrt(1 - src[:, 0] ** 2 - src[:, 1] ** 2)
+    q = dataclasses.replace(p, src_lmn=src, beam=None)
+    v, rep = _run(fv, ctx, q, eps=1e-6)
+    assert rep["prec_bits"] == (64 if n_src > 16 else 32) and rep["lattice"] == 0
+    assert oracle.rel_l2(v, oracle.direct_problem(q)) <= 1e-6
