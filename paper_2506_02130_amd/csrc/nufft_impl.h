@@ -319,13 +319,6 @@ struct SpreadCfg {
     static_assert(WPB * WAVE_BYTES <= 160 * 1024, "spread staging does not fit in LDS");
 };
 
-// ES kernel weights for the spread (FP32: hardware exp2 and sqrt, about 1
-// ulp; FP64: libm).
-__device__ __forceinline__ float es_phi_fast(float z, float beta) {
-    const float t = fmaxf(1.0f - z * z, 0.0f);
-    return __expf(beta * (__builtin_amdgcn_sqrtf(t) - 1.0f));
-}
-__device__ __forceinline__ double es_phi_fast(double z, double beta) { return es_phi(z, beta); }
 
 // Spreading (gather form).  Each lane owns one cell of an 8 x 8 sub-tile (and
 // TZ z slices in 3-D) and keeps its sum in registers.  The records of the
