@@ -19,7 +19,8 @@ antenna offset must be an integer combination of the basis within `tol`
 metres.
 
 Type-1 steps (the published algorithm the paper cites), per frequency, with
-sigma = 2, w and beta as for type 3:
+sigma = 2, beta = 2.3 w and the paper's width rule w = ceil(log10(1/eps)) + 1
+(one kernel application, unlike type 3):
   u_s = (nu / c) A^T s (turns), x_s = 2 pi frac(u_s) in [0, 2 pi)^2;
   N_a = 2 K_a + 1 modes per axis, fine periodic grid n_a = smallest even
   {2,3,5}-smooth size >= max(sigma N_a, 2 w), h_a = 2 pi / n_a,
@@ -38,7 +39,7 @@ from typing import Optional
 import numpy as np
 
 from .es_kernel import es_beta, es_phi, es_phihat
-from .type3 import C_LIGHT, SIGMA, kernel_width, next_smooth_even
+from .type3 import C_LIGHT, SIGMA, next_smooth_even
 
 
 @dataclass
@@ -88,6 +89,13 @@ def find_lattice(ant: np.ndarray, tol: float) -> Optional[Lattice]:
 def lattice_tolerance(eps: float, freq_hz: np.ndarray) -> float:
     """Position tolerance (metres) that keeps the phase error below eps / 10."""
     return eps * C_LIGHT / (20.0 * math.pi * float(np.max(freq_hz)))
+
+
+def kernel_width_type1(eps: float) -> int:
+    """The paper's rule w = ceil(log10(1/eps)) + 1 (section 2.2), at least 3.
+    Type 1 applies the kernel once (one spread, no interpolation), so the rule
+    holds the error below eps without the extra point type 3 needs."""
+    return max(3, int(math.ceil(-math.log10(eps) - 1e-9)) + 1)
 
 
 def grid_sizes(lat: Lattice, w: int) -> np.ndarray:
@@ -141,7 +149,7 @@ def type1_vis(ant: np.ndarray, src: np.ndarray, freq: np.ndarray, c: np.ndarray,
         lat = find_lattice(ant, lattice_tolerance(eps, freq))
         if lat is None:
             raise ValueError("antennas are not on a lattice")
-    w = kernel_width(eps)
+    w = kernel_width_type1(eps)
     nf = grid_sizes(lat, w)
     n = ant.shape[0]
     iu, ju = np.triu_indices(n)

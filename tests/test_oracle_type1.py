@@ -42,7 +42,12 @@ def test_random_collinear_and_jittered_arrays_are_not_lattices():
     assert type1.find_lattice(tiny, 1e-9) is not None
 
 
-@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-10])
+def test_type1_kernel_width_is_the_papers_rule():
+    # w = ceil(log10(1/eps)) + 1, at least 3
+    assert [type1.kernel_width_type1(e) for e in (1e-1, 1e-2, 1e-3, 1e-6, 1e-12)] == [3, 3, 4, 7, 13]
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-8, 1e-10, 1e-12])
 def test_type1_within_eps_of_direct_sum(eps):
     p = synth.small_problem(120, n_ant=37, n_src=150, n_freq=2, hex_layout=True)
     c = p.strengths()
