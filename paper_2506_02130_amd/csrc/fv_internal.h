@@ -100,6 +100,7 @@ struct GeomPlan {
 };
 
 int kernel_width(double eps);
+int kernel_width_type1(double eps);  // the lattice path's width (one kernel application)
 int next_smooth_even(long long n);
 void src_box(const double *src, int n_src, int dim, double *s_c, double *S);
 GeomPlan plan_geometry(const double *ant, int n_ant, int dim, double eps, const double *s_c, const double *S,

@@ -20,6 +20,13 @@ int kernel_width(double eps) {
     return std::max(2, std::min(kMaxW, w));
 }
 
+int kernel_width_type1(double eps) {
+    // the paper's rule ceil(log10(1/eps)) + 1: type 1 applies the kernel once
+    // (one spread, no interpolation), so the rule's error stays below eps
+    const int w = (int)std::ceil(-std::log10(eps) - 1e-9) + 1;
+    return std::max(3, std::min(kMaxW, w));
+}
+
 // Even numbers whose only prime factors are 2, 3 and 5, up to 2^31, sorted
 // (about 1.5k of them), built once.
 static const std::vector<long long> &smooth_even_table() {

@@ -336,7 +336,7 @@ std::shared_ptr<LatticePlan> lattice_choice(fv_ctx *ctx, const fv_problem &p, co
     double numax = 0.0;
     for (int f = 0; f < p.n_freq; ++f) numax = std::max(numax, p.freq_hz[f]);
     const double tol = p.eps * kCLight / (20.0 * M_PI * numax);
-    const int w = kernel_width(p.eps);
+    const int w = kernel_width_type1(p.eps);
     std::shared_ptr<LatticePlan> lp = ctx_lattice(ctx, p.ant_enu, p.n_ant, tol, w);
     if (!lp || !lattice_fits(*lp, prec, w)) return nullptr;
     int nf[2];
