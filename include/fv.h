@@ -22,7 +22,9 @@
  *   beam     [n_freq][n_src]  real beam weight applied as-is (the source
  *                        strength is beam*flux); NULL means 1.
  *   vis      [n_freq][n_ant*(n_ant+1)/2] complex128 (interleaved re, im),
- *                        pairs (i <= j) in row-major order (autos included).
+ *                        pairs (i <= j) in row-major order (autos included);
+ *                        a device output must be 16-byte aligned (FV_EINVAL
+ *                        otherwise).
  *   eps      requested relative l2 error of the whole output of the call
  *            (all frequencies, all pairs) against the exact sum;
  *            1e-14 <= eps <= 1e-1.

@@ -149,6 +149,7 @@ void simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, hipStream_t st,
 extern "C" fv_status fv_simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, void *stream, fv_report *rep) {
     try {
         if (!ctx || !b || !vis) fv::fail(FV_EINVAL, "null argument");
+        if ((uintptr_t)vis & 15) fv::fail(FV_EINVAL, "the output must be 16-byte aligned");
         fv::simulate_beams(ctx, b, vis, (hipStream_t)stream, rep);
         return FV_OK;
     } catch (const fv::Error &e) {

@@ -179,6 +179,7 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
 extern "C" fv_status fv_simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, void *stream, fv_report *rep) {
     try {
         if (!ctx || !d || !vis) fv::fail(FV_EINVAL, "null argument");
+        if ((uintptr_t)vis & 15) fv::fail(FV_EINVAL, "the output must be 16-byte aligned");
         fv::simulate_drift(ctx, d, vis, (hipStream_t)stream, rep);
         return FV_OK;
     } catch (const fv::Error &e) {

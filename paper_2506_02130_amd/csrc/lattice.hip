@@ -14,10 +14,11 @@
 //   k_t1_rows    one workgroup per (grid row, frequency): the partials of
 //                the row summed in FP64, then the DFT along axis 0 at the
 //                modes k0 (FP64).
-//   k_t1_cols    one workgroup per (mode k0, frequency): the DFT along
+//   k_t1_cols    one workgroup per (8 modes k0, frequency): the DFT along
 //                axis 1 at the modes k1 and the deconvolution
 //                h / (alpha phihat(alpha k)) per axis (FP64).
-//   k_t1_out     V(i, j) = mode (k_i - k_j), written to the caller's layout.
+//   k_t1_out     V(i, j) = mode (k_i - k_j), written to the caller's layout
+//                (one thread per pair and 8 frequencies).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -216,46 +217,55 @@ __global__ __launch_bounds__(256) void k_t1_rows(T1Params P) {
     }
 }
 
+constexpr int kT1ColTile = 8;  // columns k0 per column-DFT workgroup (8 double2 = one 128-byte line)
+constexpr int kT1OutFreq = 8;  // frequencies per output thread
+
+// Column DFTs of kT1ColTile adjacent modes k0: the workgroup stages
+// T[f][l1][k0 .. k0 + 7] (one 128-byte line per row) and forms every (k1, k0).
 __global__ __launch_bounds__(256) void k_t1_cols(T1Params P) {
     extern __shared__ __align__(16) char smem[];
-    const int k0 = blockIdx.x, f = blockIdx.y;
-    const int nf1 = P.nf[1], N0 = P.N[0];
-    double2 *col = (double2 *)smem;  // [nf1]
-    double2 *tw = col + nf1;         // [nf1]
-    for (int l1 = threadIdx.x; l1 < nf1; l1 += 256) {
-        col[l1] = P.T[((size_t)f * nf1 + l1) * N0 + k0];
-        tw[l1] = wneg(l1, nf1);
+    const int kb = blockIdx.x * kT1ColTile, f = blockIdx.y;
+    const int nf1 = P.nf[1], N0 = P.N[0], N1 = P.N[1];
+    const int nc = min(kT1ColTile, N0 - kb);
+    double2 *col = (double2 *)smem;         // [nf1][kT1ColTile]
+    double2 *tw = col + nf1 * kT1ColTile;   // [nf1]
+    for (int e = threadIdx.x; e < nf1 * kT1ColTile; e += 256) {
+        const int l1 = e / kT1ColTile, c = e - l1 * kT1ColTile;
+        col[e] = c < nc ? P.T[((size_t)f * nf1 + l1) * N0 + kb + c] : make_double2(0.0, 0.0);
     }
+    for (int l1 = threadIdx.x; l1 < nf1; l1 += 256) tw[l1] = wneg(l1, nf1);
     __syncthreads();
-    const double d0 = P.dc[k0];
-    for (int k1 = threadIdx.x; k1 < P.N[1]; k1 += 256) {
+    for (int e = threadIdx.x; e < N1 * kT1ColTile; e += 256) {
+        const int k1 = e / kT1ColTile, c = e - k1 * kT1ColTile;
+        if (c >= nc) continue;
         int kk = (k1 - P.K[1]) % nf1;
         if (kk < 0) kk += nf1;
         double re = 0.0, im = 0.0;
         int m = 0;
         for (int l1 = 0; l1 < nf1; ++l1) {
-            const double2 v = col[l1], t = tw[m];
+            const double2 v = col[l1 * kT1ColTile + c], t = tw[m];
             re += v.x * t.x - v.y * t.y;
             im += v.x * t.y + v.y * t.x;
             m += kk;
             if (m >= nf1) m -= nf1;
         }
-        const double d = d0 * P.dc[N0 + k1];
-        P.modes[((size_t)f * P.N[1] + k1) * N0 + k0] = make_double2(re * d, im * d);
+        const double d = P.dc[kb + c] * P.dc[N0 + k1];
+        P.modes[((size_t)f * N1 + k1) * N0 + kb + c] = make_double2(re * d, im * d);
     }
 }
 
+// V(i, j) at mode (k_i - k_j): one thread per pair and kT1OutFreq frequencies
+// (the pair's mode index formed once), one 16-byte store per value.
 __global__ __launch_bounds__(256) void k_t1_out(T1Params P) {
     const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-    const int f = blockIdx.y;
     if (p >= P.n_pairs) return;
     int i, j;
     pair_decode(p, P.n_ant, &i, &j);
     const int d0 = P.kc[2 * i] - P.kc[2 * j] + P.K[0], d1 = P.kc[2 * i + 1] - P.kc[2 * j + 1] + P.K[1];
-    const double2 v = P.modes[((size_t)f * P.N[1] + d1) * P.N[0] + d0];
-    double *o = P.vis + 2 * ((size_t)f * P.n_pairs + p);
-    o[0] = v.x;
-    o[1] = v.y;
+    const size_t mode = (size_t)d1 * P.N[0] + d0, per_f = (size_t)P.N[0] * P.N[1];
+    const int f0 = blockIdx.y * kT1OutFreq, f1 = min(f0 + kT1OutFreq, P.n_freq);
+    double2 *o = (double2 *)P.vis;
+    for (int f = f0; f < f1; ++f) o[(size_t)f * P.n_pairs + p] = P.modes[f * per_f + mode];
 }
 
 struct T1Shape {
@@ -423,12 +433,14 @@ double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, c
     tm->end(st);
     tm->add(FV_STAGE_FFT_X, (double)sh.part_bytes + (double)sh.t_bytes, 1);
     tm->begin(FV_STAGE_FFT_Y, st);
-    hipLaunchKernelGGL(k_t1_cols, dim3((unsigned)sh.N[0], (unsigned)n_freq), dim3(256), (size_t)sh.nf[1] * 32, st,
-                       P);
+    hipLaunchKernelGGL(k_t1_cols, dim3((unsigned)((sh.N[0] + kT1ColTile - 1) / kT1ColTile), (unsigned)n_freq),
+                       dim3(256), (size_t)sh.nf[1] * 16 * (kT1ColTile + 1), st, P);
     tm->end(st);
     tm->add(FV_STAGE_FFT_Y, (double)sh.t_bytes + (double)sh.mode_bytes, 1);
     tm->begin(FV_STAGE_INTERP, st);
-    hipLaunchKernelGGL(k_t1_out, dim3((unsigned)((P.n_pairs + 255) / 256), (unsigned)n_freq), dim3(256), 0, st, P);
+    hipLaunchKernelGGL(k_t1_out,
+                       dim3((unsigned)((P.n_pairs + 255) / 256), (unsigned)((n_freq + kT1OutFreq - 1) / kT1OutFreq)),
+                       dim3(256), 0, st, P);
     tm->end(st);
     tm->add(FV_STAGE_INTERP, (double)n_freq * (double)P.n_pairs * 16.0 + (double)sh.mode_bytes, 1);
     FV_HIP(hipGetLastError());

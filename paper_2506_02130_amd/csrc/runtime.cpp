@@ -672,6 +672,7 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     FV_GUARD_BEGIN
     auto t0 = std::chrono::steady_clock::now();
     if (!ctx || !p || !vis) fv::fail(FV_EINVAL, "null argument");
+    if ((uintptr_t)vis & 15) fv::fail(FV_EINVAL, "the output must be 16-byte aligned");
     if (p->n_ant < 1 || p->n_src < 0 || p->n_freq < 1) fv::fail(FV_EINVAL, "bad sizes");
     if (!p->ant_enu || !p->freq_hz || (p->n_src > 0 && (!p->src_lmn || !p->flux)))
         fv::fail(FV_EINVAL, "null device array");

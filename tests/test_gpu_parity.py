@@ -264,3 +264,14 @@ def test_crowded_sources_keep_eps(gpu_lib, ctx, n_src):
     v, rep = _run(fv, ctx, q, eps=1e-6)
     assert rep["prec_bits"] == (64 if n_src > 16 else 32) and rep["lattice"] == 0
     assert oracle.rel_l2(v, oracle.direct_problem(q)) <= 1e-6
+
+
+def test_device_output_must_be_16_byte_aligned(gpu_lib, ctx):
+    import torch
+    fv = gpu_lib
+    p = synth.small_problem(171, n_ant=7, n_src=20, n_freq=1)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+    flat = torch.zeros(2 * p.n_pairs + 1, dtype=torch.float64, device="cuda:0")
+    vis = flat[1:].view(1, p.n_pairs, 2)
+    with pytest.raises(fv.FvError, match="EINVAL"):
+        ctx.simulate_dev(d(p.ant_enu), d(p.src_lmn), d(p.freq_hz), d(p.flux), d(p.beam), vis, eps=1e-6)
