@@ -16,6 +16,8 @@ Contents
     arrays (section 2.2.1).
   * ``beams``       -- the direct sum with per-antenna beam patterns
     (section 2.2.3), pair by pair.
+  * ``polar``       -- polarised feed products, the Jones-form sum of
+    section 2.1 with a shared beam, source by source.
   * ``frontend``    -- drift-scan front end: rotation of equatorial directions
     to ENU per sidereal time (section 2.3) and an analytic Gaussian power beam
     (section 2.4).
