@@ -215,6 +215,32 @@ typedef struct {
  * values. */
 fv_status fv_simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, void *stream, fv_report *rep);
 
+/* Polarised feed products (paper section 2.1, the measurement equation in
+ * Jones form) with one beam shared by every antenna:
+ *   V_ij = sum_s A(s) C(s) A(s)^H exp(-2 pi i (nu / c) (x_i - x_j) . s_hat_s),
+ *   C = [[I + Q, U + i V], [U - i V, I - Q]],
+ * a 2 x 2 complex matrix per pair and frequency, to the eps contract of
+ * fv_simulate_dev for each product.  P = A C A^H is Hermitian, so four
+ * transforms with real strengths (P_xx, P_yy, Re P_xy, Im P_xy, formed on the
+ * device) give all four products. */
+typedef struct {
+    int n_ant;  const double *ant_enu;   /* DEVICE [n_ant][3] metres */
+    int n_src;  const double *src_lmn;   /* DEVICE [n_src][3] unit vectors (l, m, n) */
+    int n_freq; const double *freq_hz;   /* DEVICE [n_freq] */
+    const double *stokes;                /* DEVICE [4][n_freq][n_src]: I, Q, U, V */
+    const double *jones;                 /* DEVICE [n_freq][n_src][2][2] complex (interleaved re, im) feed
+                                            response A, or NULL for ideal feeds (A = identity) */
+    double eps;
+    unsigned flags;                      /* FV_* flags as in fv_problem; the NUFFT method only */
+} fv_polar;
+
+/* vis: DEVICE [4][n_freq][n_pairs] complex128, products in the order xx, xy,
+ * yx, yy (row-major 2 x 2), 16-byte aligned.  Work is enqueued on `stream`;
+ * the call blocks once for the planning scalars.  Workspace: four strength
+ * arrays and four visibility arrays.  Errors: FV_EINVAL for bad sizes,
+ * non-unit directions or non-finite values. */
+fv_status fv_simulate_polar(fv_ctx *ctx, const fv_polar *q, double *vis, void *stream, fv_report *rep);
+
 /* Serving loop: a worker thread admits submitted requests while HBM (the
  * context budget) and one of max_slots slots are free, and runs admitted
  * requests concurrently on per-slot streams.  Host buffers, which must stay

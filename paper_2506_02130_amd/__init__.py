@@ -35,7 +35,7 @@ STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "othe
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
-               "fv_simulate_drift", "fv_simulate_beams")
+               "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar")
 
 
 class FvError(RuntimeError):
@@ -67,6 +67,14 @@ class Beams(ctypes.Structure):
                 ("src_lmn", ctypes.c_void_p), ("n_freq", ctypes.c_int), ("freq_hz", ctypes.c_void_p),
                 ("flux", ctypes.c_void_p), ("n_beam", ctypes.c_int), ("beams", ctypes.c_void_p),
                 ("beam_of_ant", ctypes.c_void_p), ("eps", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+class Polar(ctypes.Structure):
+    """fv_polar: polarised feed products with a shared beam."""
+    _fields_ = [("n_ant", ctypes.c_int), ("ant_enu", ctypes.c_void_p), ("n_src", ctypes.c_int),
+                ("src_lmn", ctypes.c_void_p), ("n_freq", ctypes.c_int), ("freq_hz", ctypes.c_void_p),
+                ("stokes", ctypes.c_void_p), ("jones", ctypes.c_void_p), ("eps", ctypes.c_double),
+                ("flags", ctypes.c_uint)]
 
 
 class Report(ctypes.Structure):
@@ -107,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
     lib.fv_simulate_drift.argtypes = [vp, P(Drift), vp, vp, P(Report)]
     lib.fv_simulate_beams.argtypes = [vp, P(Beams), vp, vp, P(Report)]
+    lib.fv_simulate_polar.argtypes = [vp, P(Polar), vp, vp, P(Report)]
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
@@ -277,6 +286,38 @@ class Context:
                   beams.data_ptr() if n_src else None, which.ctypes.data, float(eps), int(flags))
         rep = Report()
         _check(_lib.fv_simulate_beams(self._h, ctypes.byref(b), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
+                                      ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return self.last_report
+
+    def simulate_polar(self, ant_enu, src_lmn, freq_hz, stokes, jones, vis, eps: float = 1e-6, flags: int = 0,
+                       stream=None) -> dict:
+        """Polarised feed products.  ``ant_enu``, ``src_lmn``, ``freq_hz``,
+        ``stokes`` [4, n_freq, n_src], ``jones`` ([n_freq, n_src, 2, 2, 2] real
+        view of the complex feed response, or None for ideal feeds) and ``vis``
+        [4, n_freq, n_pairs, 2] (xx, xy, yx, yy) are contiguous float64 torch
+        tensors on this context's device."""
+        import torch
+        named = [("ant_enu", ant_enu), ("src_lmn", src_lmn), ("freq_hz", freq_hz), ("stokes", stokes), ("vis", vis)]
+        if jones is not None:
+            named.append(("jones", jones))
+        for name, t in named:
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
+        n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
+        want = [("ant_enu", ant_enu, 3 * n_ant), ("src_lmn", src_lmn, 3 * n_src), ("freq_hz", freq_hz, n_freq),
+                ("stokes", stokes, 4 * n_freq * n_src), ("vis", vis, 8 * n_freq * n_ant * (n_ant + 1) // 2)]
+        if jones is not None:
+            want.append(("jones", jones, 8 * n_freq * n_src))
+        for name, t, n in want:
+            if t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        q = Polar(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
+                  freq_hz.data_ptr(), stokes.data_ptr() if n_src else None,
+                  None if jones is None or not n_src else jones.data_ptr(), float(eps), int(flags))
+        rep = Report()
+        _check(_lib.fv_simulate_polar(self._h, ctypes.byref(q), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
                                       ctypes.byref(rep)))
         self.last_report = rep.as_dict()
         return self.last_report

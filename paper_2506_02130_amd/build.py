@@ -29,7 +29,7 @@ HOST_ONLY_FLAGS = ["-ffp-contract=off"]
 
 SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp", "server.cpp", "tune.cpp", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip",
            "nufft_f64_2d.hip", "nufft_f64_3d.hip", "direct.hip", "zz.hip", "lattice.hip", "frontend.hip",
-           "drift.cpp", "beams.hip", "beams.cpp"]
+           "drift.cpp", "beams.hip", "beams.cpp", "polar.hip", "polar.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -14,6 +14,77 @@
 
 namespace fv {
 
+void run_vectors(fv_ctx *ctx, Slot &slot, hipStream_t st, const double *ant_dev, int n_ant, const double *src_dev,
+                 int n_src, const double *freq_dev, int n_freq, double eps, unsigned flags, const double *flux,
+                 const double *prod, int n_vec, double *tmp, fv_report &total) {
+    const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
+    const long long n_fs = (long long)n_freq * n_src;
+    // input check and planning scalars of every vector's strengths; the first
+    // one also gathers the frequencies and antenna positions
+    const size_t nvd = validate_doubles(n_ant, n_freq);
+    const size_t nscal = 8 + (size_t)n_freq + 3 * (size_t)n_ant;
+    auto fl = [&](int v) { return flux ? flux : prod + (size_t)v * n_fs; };
+    auto bm = [&](int v) { return flux ? prod + (size_t)v * n_fs : nullptr; };
+    double *scal = ctx->scalars(nvd * (size_t)n_vec);
+    for (int v = 0; v < n_vec; ++v)
+        launch_validate(src_dev, n_src, fl(v), bm(v), n_freq, ant_dev, n_ant, freq_dev, scal + (size_t)v * nvd, st);
+    double *pin = (double *)ctx->plan_pin.get(sizeof(double) * (nscal + 8 * (size_t)n_vec));
+    FV_HIP(hipMemcpyAsync(pin, scal, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
+    for (int v = 1; v < n_vec; ++v)
+        FV_HIP(hipMemcpyAsync(pin + nscal + 8 * v, scal + (size_t)v * nvd, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                              st));
+    FV_HIP(hipStreamSynchronize(st));
+    const double *pfreq = pin + 8, *pant = pfreq + n_freq;
+    const std::vector<double> ant(pant, pant + 3 * (size_t)n_ant), freq(pfreq, pfreq + n_freq);
+    for (double a : ant)
+        if (!std::isfinite(a)) fail(FV_EINVAL, "non-finite antenna position");
+    for (double f : freq)
+        if (!(std::isfinite(f) && f > 0)) fail(FV_EINVAL, "frequency must be finite and > 0");
+    for (int v = 0; v < n_vec; ++v) {
+        const double *chk = v == 0 ? pin : pin + nscal + 8 * v;
+        if (n_src > 0 && (chk[6] != 0.0 || chk[7] != 0.0))
+            fail(FV_EINVAL, "invalid source directions or strengths");
+    }
+    fv_problem meta;
+    std::memset(&meta, 0, sizeof(meta));
+    meta.n_ant = n_ant;
+    meta.ant_enu = ant.data();
+    meta.n_src = n_src;
+    meta.n_freq = n_freq;
+    meta.freq_hz = freq.data();
+    meta.eps = eps;
+    meta.flags = flags & ~FV_GRAPH;  // several transforms share the workspace: no replay
+    const int dim = choose_dim(ant.data(), n_ant, eps, freq.data(), n_freq, flags);
+    std::memset(&total, 0, sizeof(total));
+    hipStream_t keep = slot.stream;
+    slot.stream = st;
+    try {
+        for (int v = 0; v < n_vec; ++v) {
+            DevInputs in;
+            in.ant = ant_dev;
+            in.freq = freq_dev;
+            in.src = src_dev;
+            in.flux = fl(v);
+            in.beam = bm(v);
+            in.vis = tmp + 2 * (size_t)v * n_freq * n_pairs;
+            if (n_src > 0)
+                for (int a = 0; a < dim; ++a) {  // the same directions for every vector
+                    in.s_c[a] = 0.5 * (pin[2 * a] + pin[2 * a + 1]);
+                    in.S[a] = 0.5 * (pin[2 * a + 1] - pin[2 * a]);
+                }
+            in.cmax = validate_partials(scal + (size_t)v * nvd, n_ant, n_freq);
+            in.cmax_span = validate_span(n_fs);
+            fv_report r;
+            run_device(ctx, slot, meta, in, in.vis, &r);
+            accumulate_report(r, total, v == 0);
+        }
+    } catch (...) {
+        slot.stream = keep;
+        throw;
+    }
+    slot.stream = keep;
+}
+
 void simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, hipStream_t st, fv_report *rep) {
     auto t0 = std::chrono::steady_clock::now();
     if (!b) fail(FV_EINVAL, "null argument");
@@ -71,73 +142,15 @@ void simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, hipStream_t st,
     }
     if (n_src > 0) launch_beam_products(b->beams, pq_dev, n_vec, n_fs, prod, st);
 
-    // input check and planning scalars of every pattern pair's strengths; the
-    // first one also gathers the frequencies and antenna positions
-    const size_t nvd = validate_doubles(n_ant, n_freq);
-    const size_t nscal = 8 + (size_t)n_freq + 3 * (size_t)n_ant;
-    double *scal = ctx->scalars(nvd * (size_t)n_vec);
-    for (int v = 0; v < n_vec; ++v)
-        launch_validate(b->src_lmn, n_src, b->flux, prod + (size_t)v * n_fs, n_freq, b->ant_enu, n_ant, b->freq_hz,
-                        scal + (size_t)v * nvd, st);
-    double *pin = (double *)ctx->plan_pin.get(sizeof(double) * (nscal + 8 * (size_t)n_vec));
-    FV_HIP(hipMemcpyAsync(pin, scal, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
-    for (int v = 1; v < n_vec; ++v)
-        FV_HIP(hipMemcpyAsync(pin + nscal + 8 * v, scal + (size_t)v * nvd, 8 * sizeof(double), hipMemcpyDeviceToHost,
-                              st));
-    FV_HIP(hipStreamSynchronize(st));
-    const double *pfreq = pin + 8, *pant = pfreq + n_freq;
-    const std::vector<double> ant(pant, pant + 3 * (size_t)n_ant), freq(pfreq, pfreq + n_freq);
-    for (double a : ant)
-        if (!std::isfinite(a)) fail(FV_EINVAL, "non-finite antenna position");
-    for (double f : freq)
-        if (!(std::isfinite(f) && f > 0)) fail(FV_EINVAL, "frequency must be finite and > 0");
-    for (int v = 0; v < n_vec; ++v) {
-        const double *chk = v == 0 ? pin : pin + nscal + 8 * v;
-        if (n_src > 0 && (chk[6] != 0.0 || chk[7] != 0.0))
-            fail(FV_EINVAL, "invalid source directions, fluxes or beam values");
-    }
-    fv_problem meta;
-    std::memset(&meta, 0, sizeof(meta));
-    meta.n_ant = n_ant;
-    meta.ant_enu = ant.data();
-    meta.n_src = n_src;
-    meta.n_freq = n_freq;
-    meta.freq_hz = freq.data();
-    meta.eps = b->eps;
-    meta.flags = b->flags & ~FV_GRAPH;  // several transforms share the workspace: no replay
-    const int dim = choose_dim(ant.data(), n_ant, b->eps, freq.data(), n_freq, b->flags);
-
     fv_report total;
-    std::memset(&total, 0, sizeof(total));
-    hipStream_t keep = slot.stream;
-    slot.stream = st;
     try {
-        for (int v = 0; v < n_vec; ++v) {
-            DevInputs in;
-            in.ant = b->ant_enu;
-            in.freq = b->freq_hz;
-            in.src = b->src_lmn;
-            in.flux = b->flux;
-            in.beam = prod + (size_t)v * n_fs;
-            in.vis = tmp + 2 * (size_t)v * n_freq * n_pairs;
-            if (n_src > 0)
-                for (int a = 0; a < dim; ++a) {  // the same directions for every pair of patterns
-                    in.s_c[a] = 0.5 * (pin[2 * a] + pin[2 * a + 1]);
-                    in.S[a] = 0.5 * (pin[2 * a + 1] - pin[2 * a]);
-                }
-            in.cmax = validate_partials(scal + (size_t)v * nvd, n_ant, n_freq);
-            in.cmax_span = validate_span(n_fs);
-            fv_report r;
-            run_device(ctx, slot, meta, in, in.vis, &r);
-            accumulate_report(r, total, v == 0);
-        }
+        run_vectors(ctx, slot, st, b->ant_enu, n_ant, b->src_lmn, n_src, b->freq_hz, n_freq, b->eps, b->flags,
+                    b->flux, prod, n_vec, tmp, total);
         launch_beam_select(tmp, vec_dev, n_pairs, n_freq, vis, st);
     } catch (...) {
-        slot.stream = keep;
         (void)hipEventRecord(slot.done, st);  // work already enqueued must finish before the workspace is reused
         throw;
     }
-    slot.stream = keep;
     FV_HIP(hipEventRecord(slot.done, st));
     total.src_pairs = (double)n_src * (double)n_pairs * n_freq;  // each visibility once
     total.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

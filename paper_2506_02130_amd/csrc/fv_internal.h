@@ -334,6 +334,12 @@ void launch_beam_products(const double *beams, const int *pq_dev, int n_vec, lon
                           hipStream_t st);
 void launch_beam_select(const double *tmp, const int *vec_dev, long long n_pairs, int n_freq, double *vis,
                         hipStream_t st);
+// Polarised products: out [4][n_fs] = P_xx, P_yy, Re P_xy, Im P_xy of
+// P = A C A^H from stokes [4][n_fs] and jones [n_fs][2][2] complex (null =
+// identity); vis [4][n_fp] complex = xx, xy, yx, yy from the four transforms
+// tmp [4][n_fp] complex.
+void launch_polar_strengths(const double *stokes, const double *jones, long long n_fs, double *out, hipStream_t st);
+void launch_polar_combine(const double *tmp, long long n_fp, double *vis, hipStream_t st);
 int frontend_blocks(int n_src);
 void launch_frontend_count(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
                            int n_freq, int *bcnt, int *bbad, int *tot, hipStream_t st);
