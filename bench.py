@@ -272,6 +272,42 @@ def drift_leg(fv, synth, np, torch, stream) -> dict:
             "lattice": rep["lattice"], "gpu_stage_ms": sum(rep_t["t_stage_ms"])}
 
 
+def multivector_legs(fv, synth, np, torch, stream) -> dict:
+    """The HERA-350 workload with per-antenna beams (3 amplitude patterns,
+    6 pattern pairs, antennas assigned at random) and as polarised products
+    (Stokes I, Q, U, V with ideal feeds: 4 transforms): inputs in HBM, best of
+    two timed calls after one warm-up call."""
+    p = synth.config2()
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    rng = np.random.default_rng(350)
+    ant, src, freq = g(p.ant_enu), g(p.src_lmn), g(p.freq_hz)
+    pats = g(np.sqrt(p.beam)[None] * rng.uniform(0.8, 1.0, (3, 1, p.n_src)))
+    which = rng.integers(0, 3, p.n_ant)
+    stokes = g(np.concatenate([p.flux[None], rng.uniform(-0.1, 0.1, (3, 1, 1)) * p.flux[None]]))
+    vis_b = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+    vis_p = torch.empty((4, p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+    out = {}
+    with fv.Context(0) as c:
+        calls = {"beams_3_patterns": lambda: c.simulate_beams(ant, src, freq, g(p.flux), pats, which, vis_b,
+                                                             eps=p.eps, stream=stream),
+                 "polarised_4_products": lambda: c.simulate_polar(ant, src, freq, stokes, None, vis_p, eps=p.eps,
+                                                                  stream=stream)}
+        for name, call in calls.items():
+            call()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(2):
+                t0 = time.perf_counter()
+                rep = call()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = min(ts)
+            out[name] = {"ms": t * 1e3, "pairs_per_s": rep["src_pairs"] / t, "lattice": rep["lattice"],
+                         "transforms": 6 if name.startswith("beams") else 4}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -498,6 +534,9 @@ def main():
         extras["serving"] = serving_leg(fv, synth, np, args.serve_requests)
         extras["disk1000_3d"] = disk3d_leg(fv, synth, np, torch, stream)
         extras["drift_config4"] = drift_leg(fv, synth, np, torch, stream)
+        extras.update(multivector_legs(fv, synth, np, torch, stream))
+        print(f"bench: per-antenna beams {extras['beams_3_patterns']['ms']:.2f} ms, polarised "
+              f"{extras['polarised_4_products']['ms']:.2f} ms", file=sys.stderr, flush=True)
         print(f"bench: drift scan {extras['drift_config4']['ms']:.1f} ms "
               f"({extras['drift_config4']['pairs_per_s']:.3e} pairs/s)", file=sys.stderr, flush=True)
 
