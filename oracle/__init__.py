@@ -18,6 +18,8 @@ Contents
     (section 2.2.3), pair by pair.
   * ``polar``       -- polarised feed products, the Jones-form sum of
     section 2.1 with a shared beam, source by source.
+  * ``basis``       -- spectral-basis evaluation (appendix A): projection,
+    structure constants, one transform per basis function, expansion.
   * ``frontend``    -- drift-scan front end: rotation of equatorial directions
     to ENU per sidereal time (section 2.3) and an analytic Gaussian power beam
     (section 2.4).
