@@ -241,6 +241,22 @@ typedef struct {
  * non-unit directions or non-finite values. */
 fv_status fv_simulate_polar(fv_ctx *ctx, const fv_polar *q, double *vis, void *stream, fv_report *rep);
 
+/* Spectral basis (paper appendix A, which the paper leaves unvalidated): the
+ * flux and beam spectra of every source are projected onto n_basis
+ * orthonormal functions of frequency (discrete orthonormal polynomials in
+ * (nu - nu_mid) / half-width), their product is expanded with the basis's
+ * structure constants d_ijk = sum_q M_qi M_qj M_qk, and one type-3 transform
+ * per basis function, planned at the highest frequency, is evaluated at the
+ * baselines of every frequency; the visibilities are the expansion
+ *   V(b, nu_q) = sum_k M_qk F_k(b nu_q / c).
+ * The result approximates fv_simulate_dev's to within the basis's fit of the
+ * spectra (exact for a complete basis, n_basis = n_freq) plus eps.  Arrays as
+ * for fv_simulate_dev (device pointers); 1 <= n_basis <= min(n_freq, 16).
+ * vis: DEVICE [n_freq][n_pairs] complex128, 16-byte aligned.  Workspace: the
+ * coefficients and one [n_freq][n_pairs] array per basis function. */
+fv_status fv_simulate_basis(fv_ctx *ctx, const fv_problem *p, int n_basis, double *vis, void *stream,
+                            fv_report *rep);
+
 /* Serving loop: a worker thread admits submitted requests while HBM (the
  * context budget) and one of max_slots slots are free, and runs admitted
  * requests concurrently on per-slot streams.  Host buffers, which must stay

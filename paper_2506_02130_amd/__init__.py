@@ -35,7 +35,7 @@ STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "othe
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
-               "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar")
+               "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar", "fv_simulate_basis")
 
 
 class FvError(RuntimeError):
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_simulate_drift.argtypes = [vp, P(Drift), vp, vp, P(Report)]
     lib.fv_simulate_beams.argtypes = [vp, P(Beams), vp, vp, P(Report)]
     lib.fv_simulate_polar.argtypes = [vp, P(Polar), vp, vp, P(Report)]
+    lib.fv_simulate_basis.argtypes = [vp, P(Problem), ctypes.c_int, vp, vp, P(Report)]
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
@@ -319,6 +320,35 @@ class Context:
         rep = Report()
         _check(_lib.fv_simulate_polar(self._h, ctypes.byref(q), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
                                       ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return self.last_report
+
+    def simulate_basis(self, ant_enu, src_lmn, freq_hz, flux, beam, vis, n_basis: int, eps: float = 1e-6,
+                       flags: int = 0, stream=None) -> dict:
+        """Spectral-basis evaluation: arguments as for simulate_dev, plus the
+        number of basis functions."""
+        import torch
+        for name, t in (("ant_enu", ant_enu), ("src_lmn", src_lmn), ("freq_hz", freq_hz), ("flux", flux),
+                        ("vis", vis)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
+        if beam is not None and not (beam.is_cuda and beam.dtype == torch.float64 and beam.is_contiguous()):
+            raise ValueError("beam must be a contiguous float64 device tensor")
+        n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
+        sizes = (("ant_enu", ant_enu, 3 * n_ant), ("src_lmn", src_lmn, 3 * n_src), ("freq_hz", freq_hz, n_freq),
+                 ("flux", flux, n_freq * n_src), ("vis", vis, 2 * n_freq * n_ant * (n_ant + 1) // 2))
+        if beam is not None:
+            sizes += (("beam", beam, n_freq * n_src),)
+        for name, t, want in sizes:
+            if t.numel() != want:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {want}")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        c = Problem(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
+                    freq_hz.data_ptr(), flux.data_ptr() if n_src else None,
+                    None if beam is None else beam.data_ptr(), float(eps), int(flags))
+        rep = Report()
+        _check(_lib.fv_simulate_basis(self._h, ctypes.byref(c), int(n_basis), vis.data_ptr(),
+                                      ctypes.c_void_p(st.cuda_stream), ctypes.byref(rep)))
         self.last_report = rep.as_dict()
         return self.last_report
 

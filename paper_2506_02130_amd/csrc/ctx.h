@@ -94,8 +94,11 @@ namespace fv {
 
 GeomPlan ctx_geometry(fv_ctx *ctx, const double *ant_host, int n_ant, int dim, double eps, const double *s_c,
                       const double *S, bool fold);
+// Target table of an array (cached); with `scales`, all pairs at each of
+// those frequency ratios of one snapshot (targets q n_pairs + t).
 std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, const double *ant_dev,
-                                         const GeomPlan &g, hipStream_t st);
+                                         const GeomPlan &g, hipStream_t st,
+                                         const std::vector<double> *scales = nullptr);
 void validate_host(const fv_problem *p);
 DevInputs upload(Slot &slot, const fv_problem *p, double *s_c, double *S);
 void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevInputs &in, double *vis_dev,

@@ -294,6 +294,12 @@ size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec
 
 void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B,
                    int w, const double *qn_dev, const int *perm_dev, TargetTable &tt, hipStream_t s);
+// The same table over n_scale frequencies of one snapshot: target
+// q n_pairs + t is the folded baseline of pair perm[t] times scale_dev[q], with
+// output index q n_pairs + pair (tt holds n_pairs n_scale targets).
+void build_targets_multi(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B,
+                         int w, const double *qn_dev, const int *perm_dev, const double *scale_dev, int n_scale,
+                         TargetTable &tt, hipStream_t st);
 // Spatial order of the pairs of an array: Morton order of the folded baselines
 // normalised to the target box (x, y interleaved; z as the least significant
 // part in 3-D).
@@ -340,6 +346,15 @@ void launch_beam_select(const double *tmp, const int *vec_dev, long long n_pairs
 // tmp [4][n_fp] complex.
 void launch_polar_strengths(const double *stokes, const double *jones, long long n_fs, double *out, hipStream_t st);
 void launch_polar_combine(const double *tmp, long long n_fp, double *vis, hipStream_t st);
+// Spectral basis: v [K][n_src] = product coefficients of flux and beam (null
+// = 1) per source, from M [n_freq][K] (orthonormal columns) and d [K][K][K];
+// vis [n_freq][n_pairs] = sum_k M[q][k] F[k][q][pair] (complex).  K is at most
+// basis_max().
+int basis_max();
+void launch_basis_coeffs(const double *M_dev, const double *d_dev, int n_freq, int K, int n_src, const double *flux,
+                         const double *beam, double *v, hipStream_t st);
+void launch_basis_expand(const double *M_dev, int K, int n_freq, long long n_pairs, const double *F, double *vis,
+                         hipStream_t st);
 int frontend_blocks(int n_src);
 void launch_frontend_count(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
                            int n_freq, int *bcnt, int *bbad, int *tot, hipStream_t st);

@@ -250,6 +250,62 @@ void nufft_debug(const SnapJob &job, int dim, int prec_bits, int w, Arena &arena
 }
 
 // ---------------------------------------------------------------------------
+namespace {
+
+// Target table over several frequencies of one planned snapshot: target
+// q n_pairs + t is pair perm[t]'s folded baseline scaled by scale[q] (the
+// frequency over the planned one); the output index is q n_pairs + pair.
+__global__ __launch_bounds__(256) void k_targets_multi(const double *ant, int n_ant, long long n_pairs, int n_scale,
+                                                       const double *scale, int dim, int fold_axis, double3 b_c,
+                                                       double3 B, double xi0, const double *qn, const int *perm,
+                                                       double *tb, int *tidx, double *tphi) {
+    const long long n_tgt = n_pairs * n_scale;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tgt) return;
+    const int q = (int)(t / n_pairs);
+    const long long tp = t - (long long)q * n_pairs;
+    const long long p = perm ? (long long)perm[tp] : tp;
+    int i, j;
+    pair_decode(p, n_ant, &i, &j);
+    double b[3];
+    for (int a = 0; a < 3; ++a) b[a] = ant[3 * (size_t)i + a] - ant[3 * (size_t)j + a];
+    bool flip = false;
+    if (fold_axis >= 0) {
+        int order[3] = {fold_axis, 0, 0};
+        int k = 1;
+        for (int a = 0; a < dim; ++a)
+            if (a != fold_axis) order[k++] = a;
+        for (int r = 0; r < dim; ++r) {
+            const double v = b[order[r]];
+            if (v < 0) { flip = true; break; }
+            if (v > 0) break;
+        }
+    }
+    const double sc = scale[q];
+    const double bc[3] = {b_c.x, b_c.y, b_c.z}, Bh[3] = {B.x, B.y, B.z};
+    for (int a = 0; a < dim; ++a) {
+        const double f = (flip ? -b[a] : b[a]) * sc;
+        tb[(long long)a * n_tgt + t] = f;
+        const double xi = Bh[a] > 0 ? xi0 * (f - bc[a]) / Bh[a] : 0.0;
+        tphi[(long long)a * n_tgt + t] = phihat_quad(xi, qn);
+    }
+    tidx[t] = (int)((long long)q * n_pairs + p) | (flip ? (int)0x80000000 : 0);
+}
+
+}  // namespace
+
+void build_targets_multi(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B,
+                         int w, const double *qn_dev, const int *perm_dev, const double *scale_dev, int n_scale,
+                         TargetTable &tt, hipStream_t st) {
+    const long long n = (long long)n_ant * (n_ant + 1) / 2 * n_scale;
+    const double xi0 = w * M_PI / (2.0 * kSigma);
+    hipLaunchKernelGGL(k_targets_multi, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ant_dev, n_ant,
+                       (long long)n_ant * (n_ant + 1) / 2, n_scale, scale_dev, dim, fold_axis,
+                       make_double3(b_c[0], b_c[1], b_c[2]), make_double3(B[0], B[1], B[2]), xi0, qn_dev, perm_dev,
+                       tt.tb, tt.tidx, tt.tphi);
+    FV_HIP(hipGetLastError());
+}
+
 void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B, int w,
                    const double *qn_dev, const int *perm_dev, TargetTable &tt, hipStream_t st) {
     const long long n = (long long)n_ant * (n_ant + 1) / 2;

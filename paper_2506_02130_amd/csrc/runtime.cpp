@@ -230,9 +230,10 @@ GeomPlan ctx_geometry(fv_ctx *ctx, const double *ant_host, int n_ant, int dim, d
     return g;
 }
 
-// Target table for (array, dim, fold axis, w), built on the device and cached.
+// Target table for (array, dim, fold axis, w), built on the device and cached;
+// with `scales`, the table of all pairs at each of those frequency ratios.
 std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, const double *ant_dev,
-                                         const GeomPlan &g, hipStream_t st) {
+                                         const GeomPlan &g, hipStream_t st, const std::vector<double> *scales) {
     std::lock_guard<std::mutex> lk(ctx->geo_mu);
     uint64_t key = fnv1a(ant_host, sizeof(double) * 3 * (size_t)g.n_ant);
     key = fnv1a(&g.dim, sizeof(int), key);
@@ -240,6 +241,8 @@ std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, co
     key = fnv1a(&g.w, sizeof(int), key);
     key = fnv1a(g.b_c, sizeof(double) * 3, key);
     key = fnv1a(g.B, sizeof(double) * 3, key);
+    const int n_scale = scales ? (int)scales->size() : 1;
+    if (scales) key = fnv1a(scales->data(), sizeof(double) * scales->size(), key ^ 0x9e3779b97f4a7c15ull);
     for (auto it = ctx->targets.begin(); it != ctx->targets.end(); ++it)
         if ((*it)->key == key) {
             auto t = *it;
@@ -257,19 +260,27 @@ std::shared_ptr<TargetTable> ctx_targets(fv_ctx *ctx, const double *ant_host, co
     t->w = g.w;
     t->fold_axis = g.fold_axis;
     t->n_ant = g.n_ant;
-    t->n_tgt = g.n_pairs;
-    const size_t n = (size_t)std::max<long long>(g.n_pairs, 1);
+    t->n_tgt = g.n_pairs * n_scale;
+    const size_t n = (size_t)std::max<long long>(t->n_tgt, 1);
     FV_HIP(hipMalloc((void **)&t->tb, n * g.dim * sizeof(double)));
     FV_HIP(hipMalloc((void **)&t->tidx, n * sizeof(int)));
     FV_HIP(hipMalloc((void **)&t->tphi, n * g.dim * sizeof(double)));
     const double *qn = ctx->cache.quad(g.w, st);
     const std::vector<int> order = target_order(ant_host, g);
     int *perm_dev = nullptr;
-    FV_HIP(hipMalloc((void **)&perm_dev, n * sizeof(int)));
+    // the pair order, then the frequency ratios
+    FV_HIP(hipMalloc((void **)&perm_dev, order.size() * sizeof(int) + (size_t)n_scale * sizeof(double) + 16));
+    double *scale_dev = (double *)((char *)perm_dev + (order.size() * sizeof(int) + 15) / 16 * 16);
     hipError_t e = hipMemcpyAsync(perm_dev, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && scales)
+        e = hipMemcpyAsync(scale_dev, scales->data(), sizeof(double) * n_scale, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         try {
-            build_targets(ant_dev, g.n_ant, g.dim, g.fold_axis, g.b_c, g.B, g.w, qn, perm_dev, *t, st);
+            if (scales)
+                build_targets_multi(ant_dev, g.n_ant, g.dim, g.fold_axis, g.b_c, g.B, g.w, qn, perm_dev, scale_dev,
+                                    n_scale, *t, st);
+            else
+                build_targets(ant_dev, g.n_ant, g.dim, g.fold_axis, g.b_c, g.B, g.w, qn, perm_dev, *t, st);
         } catch (...) {
             (void)hipStreamSynchronize(st);
             (void)hipFree(perm_dev);
