@@ -308,6 +308,43 @@ def multivector_legs(fv, synth, np, torch, stream) -> dict:
     return out
 
 
+def basis_leg(fv, synth, np, torch, stream) -> dict:
+    """The spectral-basis path against the per-frequency type-3 path on two
+    workloads: the HERA-350 workload (64 frequencies over an octave, lattice
+    path off so both are type 3) and the 3-D disk workload (16 frequencies,
+    150-170 MHz).  Reports each path's time (best of two after a warm-up) and
+    the relative l2 difference of the two outputs (which holds the basis's fit
+    of the spectra)."""
+    out = {}
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    for name, p, K in (("basis_hex350_type3", synth.config2(), 12), ("basis_disk1000_3d", synth.config3(), 6)):
+        args = (g(p.ant_enu), g(p.src_lmn), g(p.freq_hz), g(p.flux), None if p.beam is None else g(p.beam))
+        v_ref = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+        v_b = torch.empty_like(v_ref)
+        with fv.Context(0) as c:
+            runs = {"per_frequency": lambda: c.simulate_dev(*args, v_ref, eps=p.eps, flags=fv.NO_LATTICE,
+                                                            stream=stream),
+                    "basis": lambda: c.simulate_basis(*args, v_b, K, eps=p.eps, stream=stream)}
+            res = {}
+            for k, call in runs.items():
+                call()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(2):
+                    t0 = time.perf_counter()
+                    call()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                res[k] = min(ts) * 1e3
+        diff = float(torch.linalg.vector_norm(v_b - v_ref) / torch.linalg.vector_norm(v_ref))
+        out[name] = {"n_freq": p.n_freq, "n_basis": K, "ms_per_frequency_path": res["per_frequency"],
+                     "ms_basis": res["basis"], "rel_l2_basis_vs_per_frequency": diff}
+        del v_ref, v_b, args
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -535,6 +572,10 @@ def main():
         extras["disk1000_3d"] = disk3d_leg(fv, synth, np, torch, stream)
         extras["drift_config4"] = drift_leg(fv, synth, np, torch, stream)
         extras.update(multivector_legs(fv, synth, np, torch, stream))
+        extras.update(basis_leg(fv, synth, np, torch, stream))
+        print("bench: spectral basis " + ", ".join(
+            f"{k}: {v['ms_basis']:.2f} ms vs {v['ms_per_frequency_path']:.2f} ms (diff {v['rel_l2_basis_vs_per_frequency']:.1e})"
+            for k, v in extras.items() if k.startswith("basis_")), file=sys.stderr, flush=True)
         print(f"bench: per-antenna beams {extras['beams_3_patterns']['ms']:.2f} ms, polarised "
               f"{extras['polarised_4_products']['ms']:.2f} ms", file=sys.stderr, flush=True)
         print(f"bench: drift scan {extras['drift_config4']['ms']:.1f} ms "
