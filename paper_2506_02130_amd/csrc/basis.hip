@@ -71,8 +71,7 @@ void launch_basis_coeffs(const double *M_dev, const double *d_dev, int n_freq, i
     if (K < 1 || K > kMaxBasis) fail(FV_EINVAL, "basis size out of range");
     const size_t lds = sizeof(double) * ((size_t)n_freq * K + (size_t)K * K * K);
     if (lds > 160 * 1024) fail(FV_EUNSUPPORTED, "basis tables exceed LDS (too many frequencies for this basis size)");
-    if (lds > 64 * 1024)
-        FV_HIP(hipFuncSetAttribute((const void *)k_basis_coeffs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ensure_lds((const void *)k_basis_coeffs, lds);
     hipLaunchKernelGGL(k_basis_coeffs, dim3((unsigned)((n_src + 255) / 256)), dim3(256), lds, st, M_dev, d_dev, n_freq,
                        K, n_src, flux, beam, v);
     FV_HIP(hipGetLastError());

@@ -99,6 +99,9 @@ struct GeomPlan {
     double b_c[3] = {0, 0, 0}, B[3] = {0, 0, 0};
 };
 
+// Kernels asking for more than 64 KB of dynamic LDS must say so first; the
+// attribute is set once per (kernel, device, size) and remembered.
+void ensure_lds(const void *fn, size_t bytes);
 int kernel_width(double eps);
 int kernel_width_type1(double eps);  // the lattice path's width (one kernel application)
 int next_smooth_even(long long n);
@@ -182,6 +185,10 @@ struct StageTimer {
     void reset(bool enable);
     void begin(int stage, hipStream_t s);
     void end(hipStream_t s);
+    // Start and stop events for one kernel launched with hipExtLaunchKernel
+    // (the dispatch itself records them: no separate marker packets), both
+    // null when timing is off.
+    void kernel_events(int stage, hipEvent_t *a, hipEvent_t *b);
     void add(int stage, double b, int n_launch) {
         bytes[stage] += b;
         launches[stage] += n_launch;

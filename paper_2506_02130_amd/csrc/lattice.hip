@@ -19,6 +19,7 @@
 //                h / (alpha phihat(alpha k)) per axis (FP64).
 //   k_t1_out     V(i, j) = mode (k_i - k_j), written to the caller's layout
 //                (one thread per pair and 8 frequencies).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -303,17 +304,16 @@ T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int pr
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 template <typename R, int W>
-void spread_w(dim3 g, size_t lds, hipStream_t st, const T1Params &P) {
-    if (lds > 65536)
-        FV_HIP(hipFuncSetAttribute((const void *)k_t1_spread<R, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-    hipLaunchKernelGGL((k_t1_spread<R, W>), g, dim3(kT1Threads), lds, st, P);
+void spread_w(dim3 g, size_t lds, hipStream_t st, hipEvent_t ea, hipEvent_t eb, const T1Params &P) {
+    ensure_lds((const void *)k_t1_spread<R, W>, lds);
+    hipExtLaunchKernelGGL((k_t1_spread<R, W>), g, dim3(kT1Threads), (uint32_t)lds, st, ea, eb, 0u, P);
 }
 
 template <typename R, int... Ws>
-void spread_pick(int w, dim3 g, size_t lds, hipStream_t st, const T1Params &P, std::integer_sequence<int, Ws...>) {
+void spread_pick(int w, dim3 g, size_t lds, hipStream_t st, hipEvent_t ea, hipEvent_t eb, const T1Params &P,
+                 std::integer_sequence<int, Ws...>) {
     bool done = false;
-    ((w == Ws ? (spread_w<R, Ws>(g, lds, st, P), done = true) : false), ...);
+    ((w == Ws ? (spread_w<R, Ws>(g, lds, st, ea, eb, P), done = true) : false), ...);
     if (!done) fail(FV_EUNSUPPORTED, "kernel width out of range");
 }
 
@@ -414,34 +414,31 @@ double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, c
     P.dc = (const double *)lp.dev;
     P.kc = (const int *)(P.dc + sh.N[0] + sh.N[1]);
 
-    const size_t cells = (size_t)sh.nf[0] * sh.nf[1];
     using WL = std::integer_sequence<int, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
-    tm->begin(FV_STAGE_SPREAD, st);
+    // each stage is one kernel, timed by the events its dispatch records
+    hipEvent_t ea, eb;
+    tm->kernel_events(FV_STAGE_SPREAD, &ea, &eb);
     const dim3 gs((unsigned)sh.nchunk, (unsigned)n_freq);
     if (prec_bits == 32)
-        spread_pick<float>(w, gs, sh.lds, st, P, WL{});
+        spread_pick<float>(w, gs, sh.lds, st, ea, eb, P, WL{});
     else
-        spread_pick<double>(w, gs, sh.lds, st, P, WL{});
-    tm->end(st);
+        spread_pick<double>(w, gs, sh.lds, st, ea, eb, P, WL{});
     // algorithmic bytes: the directions once, strengths (and beam) once per
     // frequency, the partial grids once
     tm->add(FV_STAGE_SPREAD,
             24.0 * n_src + (double)n_freq * n_src * (beam_dev ? 16.0 : 8.0) + (double)sh.part_bytes, 1);
-    tm->begin(FV_STAGE_FFT_X, st);
-    hipLaunchKernelGGL(k_t1_rows, dim3((unsigned)sh.nf[1], (unsigned)n_freq), dim3(256),
-                       (size_t)sh.nf[0] * (8 + 16), st, P);
-    tm->end(st);
+    tm->kernel_events(FV_STAGE_FFT_X, &ea, &eb);
+    hipExtLaunchKernelGGL(k_t1_rows, dim3((unsigned)sh.nf[1], (unsigned)n_freq), dim3(256),
+                          (uint32_t)((size_t)sh.nf[0] * (8 + 16)), st, ea, eb, 0u, P);
     tm->add(FV_STAGE_FFT_X, (double)sh.part_bytes + (double)sh.t_bytes, 1);
-    tm->begin(FV_STAGE_FFT_Y, st);
-    hipLaunchKernelGGL(k_t1_cols, dim3((unsigned)((sh.N[0] + kT1ColTile - 1) / kT1ColTile), (unsigned)n_freq),
-                       dim3(256), (size_t)sh.nf[1] * 16 * (kT1ColTile + 1), st, P);
-    tm->end(st);
+    tm->kernel_events(FV_STAGE_FFT_Y, &ea, &eb);
+    hipExtLaunchKernelGGL(k_t1_cols, dim3((unsigned)((sh.N[0] + kT1ColTile - 1) / kT1ColTile), (unsigned)n_freq),
+                          dim3(256), (uint32_t)((size_t)sh.nf[1] * 16 * (kT1ColTile + 1)), st, ea, eb, 0u, P);
     tm->add(FV_STAGE_FFT_Y, (double)sh.t_bytes + (double)sh.mode_bytes, 1);
-    tm->begin(FV_STAGE_INTERP, st);
-    hipLaunchKernelGGL(k_t1_out,
-                       dim3((unsigned)((P.n_pairs + 255) / 256), (unsigned)((n_freq + kT1OutFreq - 1) / kT1OutFreq)),
-                       dim3(256), 0, st, P);
-    tm->end(st);
+    tm->kernel_events(FV_STAGE_INTERP, &ea, &eb);
+    hipExtLaunchKernelGGL(k_t1_out,
+                          dim3((unsigned)((P.n_pairs + 255) / 256), (unsigned)((n_freq + kT1OutFreq - 1) / kT1OutFreq)),
+                          dim3(256), 0u, st, ea, eb, 0u, P);
     tm->add(FV_STAGE_INTERP, (double)n_freq * (double)P.n_pairs * 16.0 + (double)sh.mode_bytes, 1);
     FV_HIP(hipGetLastError());
     return (double)sh.part_bytes + 2.0 * sh.t_bytes + 2.0 * sh.mode_bytes + 16.0 * n_freq * P.n_pairs;

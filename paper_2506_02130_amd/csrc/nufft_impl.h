@@ -1205,11 +1205,6 @@ inline bool xcd_affine(int n_snap) {
     return n_snap % 8 == 0 || n_snap >= 32;
 }
 
-// Kernels asking for more than 64 KB of dynamic LDS must say so first.
-inline void ensure_lds(const void *fn, size_t bytes) {
-    if (bytes > 65536) FV_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-}
-
 // stages: bit 0 sort + spread, bit 1 FFT passes, bit 2 interpolation.
 template <typename R, int D, int W>
 void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, int stages, StageTimer *tm) {

@@ -104,6 +104,19 @@ void TargetTable::release() {
     tidx = nullptr;
 }
 
+void ensure_lds(const void *fn, size_t bytes) {
+    if (bytes <= 65536) return;
+    int dev = 0;
+    FV_HIP(hipGetDevice(&dev));
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> set;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t &have = set[{fn, dev}];
+    if (have >= bytes) return;
+    FV_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    have = bytes;
+}
+
 void StageTimer::reset(bool enable) {
     on = enable;
     for (int i = 0; i < FV_NSTAGE; ++i) {
@@ -129,6 +142,21 @@ void StageTimer::begin(int stage, hipStream_t s) {
     cur = stage;
     cur_a = pool[used++];
     FV_HIP(hipEventRecord(cur_a, s));
+}
+
+void StageTimer::kernel_events(int stage, hipEvent_t *a, hipEvent_t *b) {
+    *a = *b = nullptr;
+    if (!on) return;
+    if (used + 2 > pool.size()) {
+        for (int i = 0; i < 16; ++i) {
+            hipEvent_t e;
+            FV_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+            pool.push_back(e);
+        }
+    }
+    *a = pool[used++];
+    *b = pool[used++];
+    marks.push_back({stage, *a, *b});
 }
 
 void StageTimer::end(hipStream_t s) {
