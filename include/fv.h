@@ -84,6 +84,10 @@ typedef enum {
                                       a lattice within eps c / (20 pi nu_max) metres is simulated with a
                                       type-1 transform onto its integer baseline modes when that grid is
                                       the smaller one */
+#define FV_TIMING_ACCUM    0x2000u /* device entry point: record the stage events like FV_TIMING but do
+                                      not wait for them; fv_stage_times returns their sums over every
+                                      such call since its last use (t_stage_ms stays 0 in each call's
+                                      report, stage_bytes and stage_launches are filled) */
 
 /* stage indices of fv_report.t_stage_ms / stage_bytes / stage_launches */
 #define FV_STAGE_SORT      0      /* key, count, scan and scatter of the source records */
@@ -273,6 +277,13 @@ fv_status fv_server_stop(fv_ctx *ctx);
  * the file are loaded now; new entries found by FV_AUTOTUNE calls are written
  * back.  path NULL or "" keeps the cache in memory only.  An unreadable or
  * missing file is not an error. */
+/* Stage event times of the FV_TIMING_ACCUM calls on this context since the
+ * last fv_stage_times: waits for them, writes the summed milliseconds and the
+ * number of timed launches of each stage (arrays of FV_NSTAGE; either may be
+ * NULL) and starts a new sum.  *n_calls (may be NULL) receives the number of
+ * calls. */
+fv_status fv_stage_times(fv_ctx *ctx, double *ms, int *launches, int *n_calls);
+
 fv_status fv_set_tune_cache(fv_ctx *ctx, const char *path);
 
 /* Diagnostic entry point for stage-by-stage checks of the NUFFT path

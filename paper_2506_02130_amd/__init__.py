@@ -31,11 +31,13 @@ TIMING = 0x200
 AUTOTUNE = 0x400
 GRAPH = 0x800
 NO_LATTICE = 0x1000
+TIMING_ACCUM = 0x2000  # stage events without waiting; sums from Context.stage_times()
 STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
-               "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar", "fv_simulate_basis")
+               "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar", "fv_simulate_basis",
+               "fv_stage_times")
 
 
 class FvError(RuntimeError):
@@ -117,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_simulate_beams.argtypes = [vp, P(Beams), vp, vp, P(Report)]
     lib.fv_simulate_polar.argtypes = [vp, P(Polar), vp, vp, P(Report)]
     lib.fv_simulate_basis.argtypes = [vp, P(Problem), ctypes.c_int, vp, vp, P(Report)]
+    lib.fv_stage_times.argtypes = [vp, dp, P(ctypes.c_int), P(ctypes.c_int)]
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
@@ -351,6 +354,16 @@ class Context:
                                       ctypes.c_void_p(st.cuda_stream), ctypes.byref(rep)))
         self.last_report = rep.as_dict()
         return self.last_report
+
+    def stage_times(self) -> dict:
+        """Summed stage event times of the TIMING_ACCUM calls since the last
+        query (waits for them): {"ms": [...], "launches": [...], "calls": n}."""
+        ms = np.zeros(len(STAGES), dtype=np.float64)
+        launches = (ctypes.c_int * len(STAGES))()
+        calls = ctypes.c_int(0)
+        _check(_lib.fv_stage_times(self._h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), launches,
+                                   ctypes.byref(calls)))
+        return {"ms": ms.tolist(), "launches": list(launches), "calls": calls.value}
 
     def set_tune_cache(self, path: Optional[str]):
         """Autotuner cache file (JSON); None keeps the cache in memory only."""

@@ -182,7 +182,13 @@ struct StageTimer {
     size_t used = 0;
     int cur = -1;
     hipEvent_t cur_a = nullptr;
-    void reset(bool enable);
+    // accum: keep the events of earlier calls (FV_TIMING_ACCUM); collect()
+    // then leaves them for take()
+    bool accum = false;
+    int calls = 0;
+    void reset(bool enable, bool accum_mode = false);
+    // sums of the kept events per stage (waits for them) and starts anew
+    void take(double *ms_out, int *launches_out, int *calls_out);
     void begin(int stage, hipStream_t s);
     void end(hipStream_t s);
     // Start and stop events for one kernel launched with hipExtLaunchKernel

@@ -117,15 +117,43 @@ void ensure_lds(const void *fn, size_t bytes) {
     have = bytes;
 }
 
-void StageTimer::reset(bool enable) {
+void StageTimer::reset(bool enable, bool accum_mode) {
     on = enable;
     for (int i = 0; i < FV_NSTAGE; ++i) {
         ms[i] = bytes[i] = 0;
         launches[i] = 0;
     }
+    if (!(accum_mode && accum)) {  // a new sum starts unless one is running
+        marks.clear();
+        used = 0;
+        calls = 0;
+    }
+    accum = accum_mode;
+    if (accum) ++calls;
+    cur = -1;
+}
+
+void StageTimer::take(double *ms_out, int *launches_out, int *calls_out) {
+    double sum[FV_NSTAGE] = {0};
+    int cnt[FV_NSTAGE] = {0};
+    if (!marks.empty()) {
+        FV_HIP(hipEventSynchronize(marks.back().b));
+        for (auto &m : marks) {
+            float t = 0;
+            FV_HIP(hipEventElapsedTime(&t, m.a, m.b));
+            sum[m.stage] += t;
+            cnt[m.stage] += 1;
+        }
+    }
+    for (int i = 0; i < FV_NSTAGE; ++i) {
+        if (ms_out) ms_out[i] = sum[i];
+        if (launches_out) launches_out[i] = cnt[i];
+    }
+    if (calls_out) *calls_out = calls;
     marks.clear();
     used = 0;
-    cur = -1;
+    calls = 0;
+    accum = false;
 }
 
 void StageTimer::begin(int stage, hipStream_t s) {
@@ -168,7 +196,7 @@ void StageTimer::end(hipStream_t s) {
 }
 
 void StageTimer::collect() {
-    if (!on || marks.empty()) return;
+    if (!on || accum || marks.empty()) return;
     FV_HIP(hipEventSynchronize(marks.back().b));
     for (auto &m : marks) {
         float t = 0;
@@ -550,7 +578,7 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
     fv_report r;
     std::memset(&r, 0, sizeof(r));
     StageTimer &tm = slot.timer;
-    tm.reset((p->flags & FV_TIMING) != 0);
+    tm.reset((p->flags & (FV_TIMING | FV_TIMING_ACCUM)) != 0, (p->flags & FV_TIMING_ACCUM) != 0);
     r.dim = dim;
     r.prec_bits = prec;
     r.method = (int)method;
@@ -824,6 +852,15 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     slot.stream = keep;
     FV_HIP(hipEventRecord(slot.done, st));
     if (rep) rep->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return FV_OK;
+    FV_GUARD_END
+}
+
+fv_status fv_stage_times(fv_ctx *ctx, double *ms, int *launches, int *n_calls) {
+    FV_GUARD_BEGIN
+    if (!ctx) fv::fail(FV_EINVAL, "null context");
+    FV_HIP(hipSetDevice(ctx->device));
+    ctx->main.timer.take(ms, launches, n_calls);
     return FV_OK;
     FV_GUARD_END
 }

@@ -151,3 +151,27 @@ def test_repeated_device_calls_follow_changed_contents(gpu_lib):
             c.simulate_dev(t["ant_enu"], t["src_lmn"], t["freq_hz"], t["flux"], t["beam"], vis, eps=1e-6)
         t["flux"].copy_(bad)
         run(c, q)
+
+
+def test_accumulated_stage_times(gpu_lib):
+    """FV_TIMING_ACCUM calls record stage events without waiting; the query
+    sums them over the calls and starts anew."""
+    import torch
+    fv = gpu_lib
+    p = synth.small_problem(161, n_ant=37, n_src=2000, n_freq=4, hex_layout=True)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+    args = (d(p.ant_enu), d(p.src_lmn), d(p.freq_hz), d(p.flux), d(p.beam))
+    vis = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device="cuda:0")
+    with fv.Context(0) as c:
+        reps = [c.simulate_dev(*args, vis, eps=1e-6, flags=fv.TIMING_ACCUM) for _ in range(3)]
+        t = c.stage_times()
+        assert t["calls"] == 3
+        i = fv.STAGES.index("spread")
+        assert t["launches"][i] == 3 and t["ms"][i] > 0
+        assert all(r["t_stage_ms"][i] == 0 and r["stage_launches"][i] == 1 for r in reps)
+        assert c.stage_times()["calls"] == 0                       # a new sum started
+        r = c.simulate_dev(*args, vis, eps=1e-6, flags=fv.TIMING)    # per-call timing still works
+        assert r["t_stage_ms"][i] > 0
+        torch.cuda.synchronize()
+        o = vis.cpu().numpy()
+        assert oracle.rel_l2(o[..., 0] + 1j * o[..., 1], oracle.direct_problem(p)) <= 1e-6
