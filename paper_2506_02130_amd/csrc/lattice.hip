@@ -11,7 +11,7 @@
 //                private copy of the periodic fine grid in LDS (real: the
 //                strengths are real and no pre-phase is needed), which is
 //                then stored as the chunk's partial grid.
-//   k_t1_rows    one workgroup per (grid row, frequency): the partials of
+//   k_t1_rows    one wavefront per (grid row, frequency): the partials of
 //                the row summed in FP64, then the DFT along axis 0 at the
 //                modes k0 (FP64).
 //   k_t1_cols    one workgroup per (8 modes k0, frequency): the DFT along
@@ -113,10 +113,36 @@ __device__ int t1_chunk_scale(const T1Params &P, int f, int ch, int s0, int s1, 
     return S;
 }
 
-// One source per lane: the lane computes its source's first cells and the
-// 2 W kernel weights in registers (c and the scale folded into the axis-1
-// weights) and adds its W x W footprint with W^2 atomic adds.  The LDS grid
-// carries a halo of W - 1 cells per axis, so no add wraps (the footprint's
+constexpr int kT1Batch = 4;     // sources per lane in one bank-balancing batch (256 per wavefront)
+constexpr int kT1Classes = 16;  // 8-byte LDS bank classes (32 banks of 4 bytes)
+constexpr size_t kT1IdBytes = (size_t)(kT1Threads / 64) * 64 * kT1Batch;  // LDS for the batch orders
+
+// First cell along axis a of the kernel of a source at (sx, sy), and the
+// offset of the grid coordinate from it.  The coordinate lies in [0, nf), so
+// the footprint ends below nf + W - 1; the clamp only acts on non-finite
+// input (which the call rejects) and keeps every add in range.
+template <int W>
+__device__ __forceinline__ int t1_first_cell(const T1Params &P, int a, double kt, double sx, double sy, double *off) {
+    const double u = kt * (P.A[0][a] * sx + P.A[1][a] * sy);
+    const double g = (u - floor(u)) * P.nf[a];  // grid coordinate in [0, nf)
+    const double lc = ceil(g - 0.5 * W);         // first cell of the kernel
+    *off = g - lc;
+    return min(max((int)lc < 0 ? (int)lc + P.nf[a] : (int)lc, 0), P.nf[a] - 1);
+}
+
+// Sources are taken in batches of 64 kT1Batch per wavefront.  The 64-bit adds
+// of a wavefront run fastest when its lanes' addresses fall evenly into the
+// kT1Classes bank classes (address mod kT1Classes); with random positions a
+// wavefront instead waits on its most crowded class.  So the lanes first find
+// the class of their sources' first cells (every add of a footprint shifts all
+// lanes' classes alike), rank the batch by class with ballots (no workgroup
+// barrier) and write the order to the wavefront's LDS slots.  The LDS serves
+// 64-bit operands 16 lanes at a time, so the order is dealt out such that the
+// 16 lanes of each group take sources about one class apart: each group's adds
+// then meet few bank conflicts.  The lane computes its source's first cells
+// and the 2 W kernel weights in registers (c and the scale folded into the
+// axis-1 weights) and adds its W x W footprint with W^2 atomic adds.  The LDS
+// grid carries a halo of W - 1 cells per axis, so no add wraps (the footprint's
 // columns are immediate offsets of one address); the halo is folded back when
 // the partial is stored.  Sixteen wavefronts share one LDS grid.
 template <typename R, int W>
@@ -125,41 +151,82 @@ __global__ __launch_bounds__(kT1Threads) void k_t1_spread(T1Params P) {
     constexpr bool kWrap = sizeof(R) == 4;
     const int nf0 = P.nf[0], nf1 = P.nf[1], g0 = P.gs[0], g1 = P.gs[1];
     unsigned long long *G = (unsigned long long *)smem;  // [g1][g0] fixed point
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned char *ids = (unsigned char *)(G + (size_t)g0 * g1) + wave * 64 * kT1Batch;  // this wavefront's order
     const int f = blockIdx.y, ch = blockIdx.x;
     const int s0 = ch * P.chunk, s1 = min(s0 + P.chunk, P.n_src);
     const double scale = ldexp(1.0, t1_chunk_scale(P, f, ch, s0, s1, G, g0 * g1, kWrap ? 50 : 62));
     const double kt = P.freq[f] * (1.0 / kCLight);  // nu / c
     const double magic = 6755399441055744.0;  // 1.5 * 2^52
     const R beta = (R)P.beta, inv_hw = (R)(2.0 / W);
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += kT1Threads) {
-        const double sx = P.src[3 * (size_t)s], sy = P.src[3 * (size_t)s + 1];
-        double c = P.flux[(size_t)f * P.n_src + s];
-        if (P.beam) c *= P.beam[(size_t)f * P.n_src + s];
-        int l[2];
-        double wd[2][W];
+    for (int b0 = s0 + wave * 64 * kT1Batch; b0 < s1; b0 += kT1Threads * kT1Batch) {
+        int cls[kT1Batch], pos[kT1Batch] = {};
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const double u = kt * (P.A[0][a] * sx + P.A[1][a] * sy);
-            const double g = (u - floor(u)) * P.nf[a];  // grid coordinate in [0, nf)
-            const double lc = ceil(g - 0.5 * W);         // first cell of the kernel
-            const R off = (R)(g - lc);
-            // in [0, nf), so the footprint ends below nf + W - 1; the clamp only acts
-            // on non-finite input (which the call rejects) and keeps every add in range
-            l[a] = min(max((int)lc < 0 ? (int)lc + P.nf[a] : (int)lc, 0), P.nf[a] - 1);
-            const double sc = a == 0 ? 1.0 : c * scale;
-#pragma unroll
-            for (int i = 0; i < W; ++i) wd[a][i] = sc * (double)es_phi_fast((R)((R)i - off) * inv_hw, beta);
-        }
-        unsigned long long *base = G + (size_t)l[1] * g0 + l[0];
-#pragma unroll
-        for (int iy = 0; iy < W; ++iy) {
-#pragma unroll
-            for (int ix = 0; ix < W; ++ix) {
-                const long long b = __double_as_longlong(fma(wd[1][iy], wd[0][ix], magic));
-                atomicAdd(&base[ix], (unsigned long long)(kWrap ? b : b - __double_as_longlong(magic)));
+        for (int r = 0; r < kT1Batch; ++r) {
+            const int s = b0 + r * 64 + lane;
+            cls[r] = kT1Classes;  // past the chunk: no class, not ranked
+            if (s < s1) {
+                const double sx = P.src[3 * (size_t)s], sy = P.src[3 * (size_t)s + 1];
+                double o;
+                const int l0 = t1_first_cell<W>(P, 0, kt, sx, sy, &o), l1 = t1_first_cell<W>(P, 1, kt, sx, sy, &o);
+                cls[r] = (l1 * g0 + l0) & (kT1Classes - 1);
             }
-            base += g0;
         }
+        // rank by class, then by round and lane
+        int nv = 0;
+        for (int k = 0; k < kT1Classes; ++k) {
+#pragma unroll
+            for (int r = 0; r < kT1Batch; ++r) {
+                const unsigned long long m = __ballot(cls[r] == k);
+                const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                if (cls[r] == k) pos[r] = nv + below;
+                nv += __popcll(m);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kT1Batch; ++r)
+            if (cls[r] < kT1Classes) ids[pos[r]] = (unsigned char)(r * 64 + lane);
+        // the order is read back by other lanes of this wavefront only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int r = 0; r < kT1Batch; ++r) {
+            // lane 16 g + j takes position 4 kT1Batch j + kT1Batch g + r: the 16 lanes
+            // of a group (served together by the LDS for 64-bit operands) sit
+            // 4 kT1Batch positions apart in the order, about one class apart
+            const int p = (lane & 15) * (4 * kT1Batch) + (lane >> 4) * kT1Batch + r;
+            if (p >= nv) continue;
+            const int s = b0 + ids[p];
+            const double sx = P.src[3 * (size_t)s], sy = P.src[3 * (size_t)s + 1];
+            double c = P.flux[(size_t)f * P.n_src + s];
+            if (P.beam) c *= P.beam[(size_t)f * P.n_src + s];
+            int l[2];
+            double wd[2][W];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                double o;
+                l[a] = t1_first_cell<W>(P, a, kt, sx, sy, &o);
+                const R off = (R)o;
+                const double sc = a == 0 ? 1.0 : c * scale;
+#pragma unroll
+                for (int i = 0; i < W; ++i) wd[a][i] = sc * (double)es_phi_fast((R)((R)i - off) * inv_hw, beta);
+            }
+            unsigned long long *base = G + (size_t)l[1] * g0 + l[0];
+#pragma unroll
+            for (int iy = 0; iy < W; ++iy) {
+#pragma unroll
+                for (int ix = 0; ix < W; ++ix) {
+                    const long long b = __double_as_longlong(fma(wd[1][iy], wd[0][ix], magic));
+                    atomicAdd(&base[ix], (unsigned long long)(kWrap ? b : b - __double_as_longlong(magic)));
+                }
+                base += g0;
+            }
+        }
+        // the next batch rewrites the order only after every lane has read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
     // fold the halo: cell (y, x) of the periodic grid gathers (y + a nf1, x + b nf0)
@@ -182,27 +249,35 @@ __device__ __forceinline__ double2 wneg(int m, int n) {
     return make_double2(c, -s);
 }
 
-__global__ __launch_bounds__(256) void k_t1_rows(T1Params P) {
+constexpr int kT1RowWaves = 4;  // rows per row-DFT workgroup (one wavefront each)
+
+// Row DFTs: one wavefront per grid row (kT1RowWaves rows per workgroup, one
+// twiddle table for all of them): the lanes sum the row's chunk partials in
+// FP64, then form the modes k0 of the row.
+__global__ __launch_bounds__(64 * kT1RowWaves) void k_t1_rows(T1Params P) {
     extern __shared__ __align__(16) char smem[];
-    const int l1 = blockIdx.x, f = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int l1 = blockIdx.x * kT1RowWaves + wave, f = blockIdx.y;
     const int nf0 = P.nf[0], nf1 = P.nf[1], ncell = nf0 * nf1;
-    double *row = (double *)smem;          // [nf0]
-    double2 *tw = (double2 *)(row + nf0);  // [nf0]
-    for (int l0 = threadIdx.x; l0 < nf0; l0 += 256) {
-        double acc = 0.0;
-        const size_t base = (size_t)f * P.nchunk * ncell + (size_t)l1 * nf0 + l0;
-        const long long *p = (const long long *)P.part + base;
+    double2 *tw = (double2 *)smem;                       // [nf0]
+    double *row = (double *)(tw + nf0) + wave * nf0;     // [kT1RowWaves][nf0]
+    for (int m = threadIdx.x; m < nf0; m += 64 * kT1RowWaves) tw[m] = wneg(m, nf0);
+    if (l1 < nf1) {
         const double *sc = P.part_scale + (size_t)f * P.nchunk;
-        for (int ch = 0; ch < P.nchunk; ++ch) {
-            long long v = p[(size_t)ch * ncell];
-            if (P.wrap51) v = (long long)((unsigned long long)v << 13) >> 13;  // sign-extend bit 50
-            acc += (double)v * sc[ch];
+        const long long *p = (const long long *)P.part + (size_t)f * P.nchunk * ncell + (size_t)l1 * nf0;
+        for (int l0 = lane; l0 < nf0; l0 += 64) {
+            double acc = 0.0;
+            for (int ch = 0; ch < P.nchunk; ++ch) {
+                long long v = p[(size_t)ch * ncell + l0];
+                if (P.wrap51) v = (long long)((unsigned long long)v << 13) >> 13;  // sign-extend bit 50
+                acc += (double)v * sc[ch];
+            }
+            row[l0] = acc;
         }
-        row[l0] = acc;
-        tw[l0] = wneg(l0, nf0);
     }
     __syncthreads();
-    for (int k0 = threadIdx.x; k0 < P.N[0]; k0 += 256) {
+    if (l1 >= nf1) return;
+    for (int k0 = lane; k0 < P.N[0]; k0 += 64) {
         int kk = (k0 - P.K[0]) % nf0;
         if (kk < 0) kk += nf0;
         double re = 0.0, im = 0.0;
@@ -288,7 +363,7 @@ T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int pr
     // chunks per frequency: about one round of workgroups over the device
     // (as many per compute unit as their LDS grids allow), at least
     // kT1MinChunk sources each
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, 160 * 1024 / (s.lds + 1024)));
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, 160 * 1024 / (s.lds + kT1IdBytes + 1024)));
     const int slots = kT1Cus * per_cu;
     s.nchunk = std::max(1, (slots + n_freq / 2) / std::max(n_freq, 1));
     s.nchunk = std::max(1, std::min(s.nchunk, n_src / kT1MinChunk));
@@ -420,16 +495,17 @@ double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, c
     tm->kernel_events(FV_STAGE_SPREAD, &ea, &eb);
     const dim3 gs((unsigned)sh.nchunk, (unsigned)n_freq);
     if (prec_bits == 32)
-        spread_pick<float>(w, gs, sh.lds, st, ea, eb, P, WL{});
+        spread_pick<float>(w, gs, sh.lds + kT1IdBytes, st, ea, eb, P, WL{});
     else
-        spread_pick<double>(w, gs, sh.lds, st, ea, eb, P, WL{});
+        spread_pick<double>(w, gs, sh.lds + kT1IdBytes, st, ea, eb, P, WL{});
     // algorithmic bytes: the directions once, strengths (and beam) once per
     // frequency, the partial grids once
     tm->add(FV_STAGE_SPREAD,
             24.0 * n_src + (double)n_freq * n_src * (beam_dev ? 16.0 : 8.0) + (double)sh.part_bytes, 1);
     tm->kernel_events(FV_STAGE_FFT_X, &ea, &eb);
-    hipExtLaunchKernelGGL(k_t1_rows, dim3((unsigned)sh.nf[1], (unsigned)n_freq), dim3(256),
-                          (uint32_t)((size_t)sh.nf[0] * (8 + 16)), st, ea, eb, 0u, P);
+    hipExtLaunchKernelGGL(k_t1_rows, dim3((unsigned)((sh.nf[1] + kT1RowWaves - 1) / kT1RowWaves), (unsigned)n_freq),
+                          dim3(64 * kT1RowWaves), (uint32_t)((size_t)sh.nf[0] * (16 + 8 * kT1RowWaves)), st, ea, eb,
+                          0u, P);
     tm->add(FV_STAGE_FFT_X, (double)sh.part_bytes + (double)sh.t_bytes, 1);
     tm->kernel_events(FV_STAGE_FFT_Y, &ea, &eb);
     hipExtLaunchKernelGGL(k_t1_cols, dim3((unsigned)((sh.N[0] + kT1ColTile - 1) / kT1ColTile), (unsigned)n_freq),
