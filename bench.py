@@ -348,8 +348,8 @@ def basis_leg(fv, synth, np, torch, stream) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-src", type=int, default=100_000)
     ap.add_argument("--n-freq", type=int, default=64)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-sum comparison")
@@ -406,35 +406,49 @@ def main():
     pairs_per_step = float(p.n_src) * p.n_pairs * p.n_freq
     # with --autotune the FFT launch shape is tuned on the first warm-up call (cached after)
     tune = fv.AUTOTUNE if args.autotune else 0
-    # stage events are recorded in every timed call and summed after the timed
-    # region (TIMING_ACCUM: the calls do not wait for their own work)
-    flags = fv.TIMING_ACCUM | tune | (fv.NO_LATTICE if args.path == "type3" else 0)
+    # stage events without waiting (TIMING_ACCUM), summed with ctx.stage_times()
+    base = fv.TIMING_ACCUM | tune | (fv.NO_LATTICE if args.path == "type3" else 0)
 
-    def step(fl=flags):
+    def step(fl=base):
         return ctx.simulate_dev(ant, src, freq, flux, beam, vis, eps=p.eps, flags=fl, stream=stream)
 
-    print(f"bench: workload {p.name}, pairs/step {pairs_per_step:.3e}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    def stage_table(t, rep):
+        names = fv.STAGES
+        ms = {n: t["ms"][i] / max(t["calls"], 1) for i, n in enumerate(names)}
+        launches = {n: rep["stage_launches"][i] for i, n in enumerate(names)}
+        nbytes = {n: rep["stage_bytes"][i] for i, n in enumerate(names)}
+        return ms, launches, nbytes
 
-    ctx.stage_times()  # drop the warm-up's events
+    print(f"bench: workload {p.name}, pairs/step {pairs_per_step:.3e}", file=sys.stderr, flush=True)
+    warm = [step() for _ in range(max(args.warmup, 1))]
+    torch.cuda.synchronize()
+    # the dominant stage, from the warm-up's stage events
+    w_ms, w_launch, _ = stage_table(ctx.stage_times(), warm[-1])
+    dom = max((n for n in fv.STAGES if w_launch[n] > 0), key=lambda n: w_ms[n])
+    # in the timed steps only the dominant kernel records events when it is the
+    # spreading kernel (two events per call, the least the live measurement costs)
+    flags = base | (fv.TIMING_SPREAD_ONLY if dom == "spread" else 0)
 
     # ---------------------------------------------------------------- timed region
     reps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        reps.append(step())
+        reps.append(step(flags))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    timed = ctx.stage_times()  # the timed steps' stage events
+    timed = ctx.stage_times()  # the timed steps' events (the dominant kernel's)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = pairs_per_step / ((t1 - t0) / args.steps)
     print(f"bench: {ms_per_step:.3f} ms/step, {value:.3e} pairs/s", file=sys.stderr, flush=True)
+    # every stage's event times, over as many steps again after the timed region
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    stage_ms, stage_launch, stage_bytes = stage_table(ctx.stage_times(), reps[0])
     # per-call latency (submit to completion), after the timed region
     lat = []
-    for _ in range(max(20, args.steps)):
+    for _ in range(max(20, min(args.steps, 50))):
         tl = time.perf_counter()
         step(fl=0)
         stream.synchronize()
@@ -449,13 +463,10 @@ def main():
         torch.cuda.synchronize()
         del xa, xb
 
-    # per-stage HIP-event times of the timed steps
+    # the dominant kernel's HIP-event time per launch, measured in the timed steps
     names = fv.STAGES
-    stage_ms = {n: timed["ms"][i] / max(timed["calls"], 1) for i, n in enumerate(names)}
-    stage_launch = {n: reps[0]["stage_launches"][i] for i, n in enumerate(names)}
-    stage_bytes = {n: reps[0]["stage_bytes"][i] for i, n in enumerate(names)}
-    dom = max((n for n in names if stage_launch[n] > 0), key=lambda n: stage_ms[n])
-    per_launch_ms = stage_ms[dom] / max(stage_launch[dom], 1)
+    live_ms, _, _ = stage_table(timed, reps[0])
+    per_launch_ms = live_ms[dom] / max(stage_launch[dom], 1)
     per_launch_bytes = stage_bytes[dom] / max(stage_launch[dom], 1)
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     lattice = bool(reps[-1].get("lattice"))
@@ -488,8 +499,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        sub = synth.subset_pairs(p.n_ant, 2048, 7)
-        fsel = np.linspace(0, p.n_freq - 1, min(8, p.n_freq)).round().astype(int)
+        sub = synth.subset_pairs(p.n_ant, 4096, 7)
+        fsel = np.linspace(0, p.n_freq - 1, min(16, p.n_freq)).round().astype(int)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
         tc0 = time.perf_counter()
         ref = oracle.direct_vis(p.ant_enu, p.src_lmn, p.freq_hz[fsel], p.flux[fsel], p.beam[fsel], pairs=sub,
@@ -536,6 +547,7 @@ def main():
 
     # ---------------------------------------------------------------- graph replay and batched snapshots
     extras = {}
+    n_extra = max(1, min(args.steps, 20))  # steps per leg outside the timed region
     if not args.no_extras:
         # the same workload on the general type-3 path (the hex array is a lattice,
         # so the default call takes the type-1 path)
@@ -544,11 +556,11 @@ def main():
             step(t3)
         torch.cuda.synchronize()
         t30 = time.perf_counter()
-        r3 = [step(t3) for _ in range(args.steps)]
+        r3 = [step(t3) for _ in range(n_extra)]
         torch.cuda.synchronize()
-        t3_ms = (time.perf_counter() - t30) * 1e3 / args.steps
+        t3_ms = (time.perf_counter() - t30) * 1e3 / n_extra
         extras["type3"] = {"ms_per_step": t3_ms, "pairs_per_s": pairs_per_step / (t3_ms * 1e-3),
-                           "stages_ms": {n: round(sum(r["t_stage_ms"][i] for r in r3) / args.steps, 4)
+                           "stages_ms": {n: round(sum(r["t_stage_ms"][i] for r in r3) / n_extra, 4)
                                          for i, n in enumerate(names) if r3[0]["stage_launches"][i] > 0},
                            "n1": r3[-1]["n1"][:2]}
         print(f"bench: type-3 path {t3_ms:.3f} ms/step", file=sys.stderr, flush=True)
@@ -557,10 +569,10 @@ def main():
             step(gfl)
         torch.cuda.synchronize()
         tg0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(n_extra):
             step(gfl)
         torch.cuda.synchronize()
-        g_ms = (time.perf_counter() - tg0) * 1e3 / args.steps
+        g_ms = (time.perf_counter() - tg0) * 1e3 / n_extra
         extras["graph_replay"] = {"ms_per_step": g_ms, "pairs_per_s": pairs_per_step / (g_ms * 1e-3),
                                   "note": "type-3 path of the same workload, launch sequence replayed as a HIP "
                                           "graph, no stage events"}
@@ -615,6 +627,8 @@ def main():
         "rel_l2_vs_oracle": rel_err,
         "latency_ms": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99), "kind": "per call, submit to completion, host clock (after the timed region)"},
         "stages": stages,
+        "stages_kind": (f"HIP-event ms per step of each stage over {args.steps} steps after the timed region; "
+                        f"roofline.avg_launch_ms is the {dom} kernel's own events in the timed steps"),
         "direct": direct or None,
         "extras": extras or None,
         "report": {k: reps[-1][k] for k in ("dim", "prec_bits", "w", "fold_axis", "n1", "n2", "model_bytes",

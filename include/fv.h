@@ -88,6 +88,9 @@ typedef enum {
                                       not wait for them; fv_stage_times returns their sums over every
                                       such call since its last use (t_stage_ms stays 0 in each call's
                                       report, stage_bytes and stage_launches are filled) */
+#define FV_TIMING_SPREAD_ONLY 0x4000u /* with FV_TIMING or FV_TIMING_ACCUM: only the spreading stage
+                                      records events (the other stages' times stay 0); two events per
+                                      call instead of two per kernel */
 
 /* stage indices of fv_report.t_stage_ms / stage_bytes / stage_launches */
 #define FV_STAGE_SORT      0      /* key, count, scan and scatter of the source records */

@@ -32,6 +32,7 @@ AUTOTUNE = 0x400
 GRAPH = 0x800
 NO_LATTICE = 0x1000
 TIMING_ACCUM = 0x2000  # stage events without waiting; sums from Context.stage_times()
+TIMING_SPREAD_ONLY = 0x4000  # with TIMING or TIMING_ACCUM: only the spreading stage records events
 STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",

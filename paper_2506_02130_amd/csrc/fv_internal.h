@@ -186,7 +186,8 @@ struct StageTimer {
     // then leaves them for take()
     bool accum = false;
     int calls = 0;
-    void reset(bool enable, bool accum_mode = false);
+    int only = -1;  // >= 0: the one stage that records events
+    void reset(bool enable, bool accum_mode = false, int only_stage = -1);
     // sums of the kept events per stage (waits for them) and starts anew
     void take(double *ms_out, int *launches_out, int *calls_out);
     void begin(int stage, hipStream_t s);
@@ -266,6 +267,7 @@ struct LatticePlan {
     int K[2] = {0, 0};
     int w = 0;                          // kernel width the tables below are for
     std::vector<double> dc;             // [N0 + N1] deconvolution factor per mode and axis
+    std::vector<float> poly;            // [w][w + 3] kernel pieces as polynomials (w <= 7), lattice_tables
     // device copy [dc][k as int pairs] on the context's device, made by
     // lattice_tables; freed (after a device synchronisation, since kernels may
     // still read it) when the plan goes

@@ -117,8 +117,9 @@ void ensure_lds(const void *fn, size_t bytes) {
     have = bytes;
 }
 
-void StageTimer::reset(bool enable, bool accum_mode) {
+void StageTimer::reset(bool enable, bool accum_mode, int only_stage) {
     on = enable;
+    only = only_stage;
     for (int i = 0; i < FV_NSTAGE; ++i) {
         ms[i] = bytes[i] = 0;
         launches[i] = 0;
@@ -157,7 +158,7 @@ void StageTimer::take(double *ms_out, int *launches_out, int *calls_out) {
 }
 
 void StageTimer::begin(int stage, hipStream_t s) {
-    if (!on) return;
+    if (!on || (only >= 0 && stage != only)) return;
     if (used + 2 > pool.size()) {
         for (int i = 0; i < 16; ++i) {
             hipEvent_t e;
@@ -174,7 +175,7 @@ void StageTimer::begin(int stage, hipStream_t s) {
 
 void StageTimer::kernel_events(int stage, hipEvent_t *a, hipEvent_t *b) {
     *a = *b = nullptr;
-    if (!on) return;
+    if (!on || (only >= 0 && stage != only)) return;
     if (used + 2 > pool.size()) {
         for (int i = 0; i < 16; ++i) {
             hipEvent_t e;
@@ -578,7 +579,8 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
     fv_report r;
     std::memset(&r, 0, sizeof(r));
     StageTimer &tm = slot.timer;
-    tm.reset((p->flags & (FV_TIMING | FV_TIMING_ACCUM)) != 0, (p->flags & FV_TIMING_ACCUM) != 0);
+    tm.reset((p->flags & (FV_TIMING | FV_TIMING_ACCUM)) != 0, (p->flags & FV_TIMING_ACCUM) != 0,
+             (p->flags & FV_TIMING_SPREAD_ONLY) ? FV_STAGE_SPREAD : -1);
     r.dim = dim;
     r.prec_bits = prec;
     r.method = (int)method;
