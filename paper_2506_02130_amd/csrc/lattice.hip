@@ -275,6 +275,7 @@ __device__ __forceinline__ double2 wneg(int m, int n) {
 }
 
 constexpr int kT1RowWaves = 4;  // rows per row-DFT workgroup (one wavefront each)
+constexpr int kT1RowLoads = 8;  // chunk partials loaded together per lane
 
 // Row DFTs: one wavefront per grid row (kT1RowWaves rows per workgroup, one
 // twiddle table for all of them): the lanes sum the row's chunk partials in
@@ -290,13 +291,22 @@ __global__ __launch_bounds__(64 * kT1RowWaves) void k_t1_rows(T1Params P) {
     if (l1 < nf1) {
         const double *sc = P.part_scale + (size_t)f * P.nchunk;
         const long long *p = (const long long *)P.part + (size_t)f * P.nchunk * ncell + (size_t)l1 * nf0;
+        // the chunks' partials are loaded kT1RowLoads at a time before they are
+        // summed, so that many loads are in flight per lane
+        const int sh = P.wrap51 ? 13 : 0;  // FP32 path: sign-extend bit 50
         for (int l0 = lane; l0 < nf0; l0 += 64) {
             double acc = 0.0;
-            for (int ch = 0; ch < P.nchunk; ++ch) {
-                long long v = p[(size_t)ch * ncell + l0];
-                if (P.wrap51) v = (long long)((unsigned long long)v << 13) >> 13;  // sign-extend bit 50
-                acc += (double)v * sc[ch];
+            int ch = 0;
+            for (; ch + kT1RowLoads <= P.nchunk; ch += kT1RowLoads) {
+                long long v[kT1RowLoads];
+#pragma unroll
+                for (int q = 0; q < kT1RowLoads; ++q) v[q] = p[(size_t)(ch + q) * ncell + l0];
+#pragma unroll
+                for (int q = 0; q < kT1RowLoads; ++q)
+                    acc += (double)((long long)((unsigned long long)v[q] << sh) >> sh) * sc[ch + q];
             }
+            for (; ch < P.nchunk; ++ch)
+                acc += (double)((long long)((unsigned long long)p[(size_t)ch * ncell + l0] << sh) >> sh) * sc[ch];
             row[l0] = acc;
         }
     }

@@ -21,11 +21,12 @@ def _run(fv, ctx, p, eps=None, flags=0):
     return v, ctx.last_report
 
 
-@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-8, 1e-10, 1e-12])
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-8, 1e-10, 1e-12])
 def test_hex_array_takes_the_lattice_path_within_eps(gpu_lib, ctx, eps):
     p = synth.small_problem(130, n_ant=61, n_src=3000, n_freq=3, hex_layout=True)
     v, rep = _run(gpu_lib, ctx, p, eps=eps)
     assert rep["lattice"] == 1 and rep["prec_bits"] == (32 if eps >= 1e-6 else 64)
+    assert rep["w"] == type1.kernel_width_type1(eps)   # every FP32 width 3..7 is met
     assert oracle.rel_l2(v, oracle.direct_problem(p)) <= eps
 
 
