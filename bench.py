@@ -448,9 +448,9 @@ def main():
     stage_ms, stage_launch, stage_bytes = stage_table(ctx.stage_times(), reps[0])
     # per-call latency (submit to completion), after the timed region
     lat = []
-    for _ in range(max(20, min(args.steps, 50))):
+    for _ in range(2 if args.profile else max(20, min(args.steps, 50))):
         tl = time.perf_counter()
-        step(fl=0)
+        step(fl=base & ~fv.TIMING_ACCUM)  # the same path, no timing
         stream.synchronize()
         lat.append((time.perf_counter() - tl) * 1e3)
 
