@@ -345,6 +345,28 @@ def basis_leg(fv, synth, np, torch, stream) -> dict:
     return out
 
 
+def make_roofline(p, dom, per_launch_ms, per_launch_bytes, lattice, w):
+    """Roofline entry of the dominant stage from its event time per launch."""
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    kernels = KERNEL_OF_STAGE_T1 if lattice else KERNEL_OF_STAGE
+    traffic = _traffic_from_profiles(dom, "type1" if lattice else "type3")
+    if lattice and dom == "spread":
+        # The type-1 spread is bound by LDS atomic adds, not HBM: its
+        # algorithmic LDS bytes are one 8-byte read-modify-write per source,
+        # frequency and footprint cell (n_freq n_src w^2), against the LDS
+        # bandwidth of the chip; its HBM bytes per launch are kept beside.
+        lds_bytes = float(p.n_freq) * p.n_src * w * w * 8.0
+        lds_achieved = lds_bytes / (per_launch_ms * 1e-3) / 1e9
+        return {"bound": "alu", "resource": "LDS (64-bit integer atomic adds)", "kernel": kernels[dom],
+                "stage": dom, "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                "frac": lds_achieved / LDS_PEAK_GBS, "traffic": traffic, "avg_launch_ms": per_launch_ms,
+                "lds_bytes_per_launch": lds_bytes, "hbm_bytes_per_launch": per_launch_bytes,
+                "hbm_achieved": achieved}
+    return {"bound": "hbm", "kernel": kernels.get(dom, dom), "stage": dom, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "avg_launch_ms": per_launch_ms, "bytes_per_launch": per_launch_bytes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,8 +382,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving mix leg")
-    ap.add_argument("--path", choices=("auto", "type3"), default="auto",
-                    help="auto: the library's choice (type 1 for lattice arrays); type3: force the type-3 path")
+    ap.add_argument("--path", choices=("type3", "auto"), default="type3",
+                    help="type3: the type-3 NUFFT (every step of the hot path; the default); auto: the "
+                         "library's choice, which is the type-1 path for this lattice array")
     ap.add_argument("--stats-md", metavar="KERNEL_STATS_CSV",
                     help="no run: print a markdown table of a rocprofv3 --stats kernel summary")
     ap.add_argument("--reduce-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -373,7 +396,7 @@ def main():
     if args.reduce_traffic:
         cmd = ("rocprofv3 --pmc COUNTER --output-format csv -d <out> -o run -- python3 bench.py --profile "
                f"--steps 2 --warmup 1 --calib-copy-mib {args.calib_copy_mib or 256}"
-               + (" --path type3" if args.path == "type3" else ""))
+               + (" --path auto" if args.path == "auto" else ""))
         reduce_traffic(args.reduce_traffic[0], args.reduce_traffic[1], args.calib_copy_mib or 256, cmd,
                        "hex350 14.6 m, 1e5 sources, 64 frequencies, eps 1e-6")
         return
@@ -466,29 +489,9 @@ def main():
     # the dominant kernel's HIP-event time per launch, measured in the timed steps
     names = fv.STAGES
     live_ms, _, _ = stage_table(timed, reps[0])
-    per_launch_ms = live_ms[dom] / max(stage_launch[dom], 1)
-    per_launch_bytes = stage_bytes[dom] / max(stage_launch[dom], 1)
-    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     lattice = bool(reps[-1].get("lattice"))
-    kernels = KERNEL_OF_STAGE_T1 if lattice else KERNEL_OF_STAGE
-    traffic = _traffic_from_profiles(dom, "type1" if lattice else "type3")
-    if lattice and dom == "spread":
-        # The type-1 spread is bound by LDS atomic adds, not HBM: its
-        # algorithmic LDS bytes are one 8-byte read-modify-write per source,
-        # frequency and footprint cell (n_freq n_src w^2), against the LDS
-        # bandwidth of the chip; its HBM bytes per launch are kept beside.
-        w = reps[-1]["w"]
-        lds_bytes = float(p.n_freq) * p.n_src * w * w * 8.0
-        lds_achieved = lds_bytes / (per_launch_ms * 1e-3) / 1e9
-        roofline = {"bound": "alu", "resource": "LDS (64-bit integer atomic adds)", "kernel": kernels[dom],
-                    "stage": dom, "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                    "frac": lds_achieved / LDS_PEAK_GBS, "traffic": traffic, "avg_launch_ms": per_launch_ms,
-                    "lds_bytes_per_launch": lds_bytes, "hbm_bytes_per_launch": per_launch_bytes,
-                    "hbm_achieved": achieved}
-    else:
-        roofline = {"bound": "hbm", "kernel": kernels.get(dom, dom), "stage": dom, "achieved": achieved,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "avg_launch_ms": per_launch_ms, "bytes_per_launch": per_launch_bytes}
+    roofline = make_roofline(p, dom, live_ms[dom] / max(stage_launch[dom], 1),
+                             stage_bytes[dom] / max(stage_launch[dom], 1), lattice, reps[-1]["w"])
     stages = {n: {"ms": round(stage_ms[n], 4), "launches": stage_launch[n],
                   "GBps": (stage_bytes[n] / max(stage_launch[n], 1)) / (stage_ms[n] / max(stage_launch[n], 1) * 1e-3)
                   / 1e9 if stage_ms[n] > 0 else None}
@@ -549,21 +552,31 @@ def main():
     extras = {}
     n_extra = max(1, min(args.steps, 20))  # steps per leg outside the timed region
     if not args.no_extras:
-        # the same workload on the general type-3 path (the hex array is a lattice,
-        # so the default call takes the type-1 path)
-        t3 = fv.TIMING | fv.NO_LATTICE | tune
-        for _ in range(2):
-            step(t3)
+        # the same workload on the other path: the library's choice (the type-1
+        # path, as the hex array is a lattice) when the timed steps ran type 3,
+        # else type 3; timed like the main steps (stage events summed after)
+        other = "auto" if args.path == "type3" else "type3"
+        ofl = fv.TIMING_ACCUM | tune | (fv.NO_LATTICE if other == "type3" else 0)
+        n_other = args.steps
+        for _ in range(3):
+            step(ofl)
         torch.cuda.synchronize()
+        ctx.stage_times()
         t30 = time.perf_counter()
-        r3 = [step(t3) for _ in range(n_extra)]
+        r3 = [step(ofl) for _ in range(n_other)]
         torch.cuda.synchronize()
-        t3_ms = (time.perf_counter() - t30) * 1e3 / n_extra
-        extras["type3"] = {"ms_per_step": t3_ms, "pairs_per_s": pairs_per_step / (t3_ms * 1e-3),
-                           "stages_ms": {n: round(sum(r["t_stage_ms"][i] for r in r3) / n_extra, 4)
-                                         for i, n in enumerate(names) if r3[0]["stage_launches"][i] > 0},
-                           "n1": r3[-1]["n1"][:2]}
-        print(f"bench: type-3 path {t3_ms:.3f} ms/step", file=sys.stderr, flush=True)
+        t3_ms = (time.perf_counter() - t30) * 1e3 / n_other
+        o_ms, o_launch, o_bytes = stage_table(ctx.stage_times(), r3[0])
+        o_lat = bool(r3[-1].get("lattice"))
+        o_dom = max((n for n in names if o_launch[n] > 0), key=lambda n: o_ms[n])
+        key = "lattice_type1" if o_lat else "type3"
+        extras[key] = {"path": "type-1 (lattice array; the library's default for this array)" if o_lat else "type-3",
+                       "ms_per_step": t3_ms, "pairs_per_s": pairs_per_step / (t3_ms * 1e-3), "steps": n_other,
+                       "stages_ms": {n: round(o_ms[n], 4) for n in names if o_launch[n] > 0},
+                       "roofline": make_roofline(p, o_dom, o_ms[o_dom] / max(o_launch[o_dom], 1),
+                                                 o_bytes[o_dom] / max(o_launch[o_dom], 1), o_lat, r3[-1]["w"]),
+                       "n1": r3[-1]["n1"][:2], "w": r3[-1]["w"]}
+        print(f"bench: {extras[key]['path']} {t3_ms:.3f} ms/step", file=sys.stderr, flush=True)
         gfl = fv.GRAPH | fv.NO_LATTICE | tune
         for _ in range(2):
             step(gfl)
@@ -619,7 +632,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"hex{p.n_ant} 14.6 m, {p.n_src} power-law sources, Gaussian beam, {p.n_freq} freqs "
                                f"100-200 MHz, eps 1e-6, 2-D, FP32 grids, inputs in HBM",
-                   "path": "type-1 (lattice array)" if reps[-1].get("lattice") else "type-3",
+                   "path": "type-1 (lattice array)" if reps[-1].get("lattice") else "type-3 NUFFT (every hot-path step)",
                    "n_ant": p.n_ant, "n_pairs": p.n_pairs, "n_src": p.n_src, "n_freq": p.n_freq, "eps": p.eps,
                    "parallelism": "1 GPU"},
         "roofline": roofline,

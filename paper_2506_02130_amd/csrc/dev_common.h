@@ -56,6 +56,26 @@ __device__ __forceinline__ float es_phi_fast(float z, float beta) {
 }
 __device__ __forceinline__ double es_phi_fast(double z, double beta) { return es_phi(z, beta); }
 
+// The W weights of the kernel from its piecewise polynomials (W <= kPolyMaxW),
+// u = 2 offset - W + 1: piece i is E(u^2) + u O(u^2) with its even and odd
+// parts, and its mirror W - 1 - i is E - u O.  No transcendental functions.
+template <int W>
+__device__ __forceinline__ void es_weights_poly(const EsPoly &P, float u, float *wt) {
+    static_assert(W <= kPolyMaxW, "no polynomial table for this width");
+    constexpr int D = W + 2, De = D - (D & 1), Do = D - 1 + (D & 1);
+    const float v = u * u;
+#pragma unroll
+    for (int i = 0; i < (W + 1) / 2; ++i) {
+        float e = P.c[i][De], od = P.c[i][Do];
+#pragma unroll
+        for (int k = De - 2; k >= 0; k -= 2) e = fmaf(e, v, P.c[i][k]);
+#pragma unroll
+        for (int k = Do - 2; k >= 1; k -= 2) od = fmaf(od, v, P.c[i][k]);
+        wt[i] = fmaf(u, od, e);
+        if (W - 1 - i != i) wt[W - 1 - i] = fmaf(-u, od, e);
+    }
+}
+
 // sin and cos of 2 pi t, with t in turns reduced exactly in FP64 first.
 __device__ __forceinline__ void sincos_turns(double t, double *s, double *c) {
     double r = t - rint(t);

@@ -267,7 +267,6 @@ struct LatticePlan {
     int K[2] = {0, 0};
     int w = 0;                          // kernel width the tables below are for
     std::vector<double> dc;             // [N0 + N1] deconvolution factor per mode and axis
-    std::vector<float> poly;            // [w][w + 3] kernel pieces as polynomials (w <= 7), lattice_tables
     // device copy [dc][k as int pairs] on the context's device, made by
     // lattice_tables; freed (after a device synchronisation, since kernels may
     // still read it) when the plan goes
@@ -282,6 +281,21 @@ struct LatticePlan {
 bool find_lattice(const double *ant, int n_ant, double tol, LatticePlan *lp);
 // phihat(xi) of the ES kernel of width w (FP64 quadrature, host).
 double phihat_host(double xi, const double *qtab);  // qtab from quad_table
+
+// FP32 kernel weights as polynomials (widths w <= kPolyMaxW, every width of an
+// FP32 grid).  The weight of the kernel's i-th cell, as a function of the
+// source's offset from its first cell (in (w/2 - 1, w/2]), is piece i; in
+// u = 2 offset - w + 1 in (-1, 1] it is interpolated at the w + 3 Chebyshev
+// nodes (degree w + 2, monomial coefficients, lowest first).  The kernel is
+// even, so piece w - 1 - i is piece i at -u and only the first (w + 1) / 2
+// pieces are kept.  Passed to kernels by value (kernel arguments sit in
+// scalar registers).
+constexpr int kPolyMaxW = 8;
+struct EsPoly {
+    float c[(kPolyMaxW + 1) / 2][kPolyMaxW + 3];
+};
+// The table of width w (computed once per width; zeros for w > kPolyMaxW).
+const EsPoly &es_poly(int w);
 
 // Type-1 path for a lattice array: every frequency of one problem.  `work`
 // holds lattice_work_bytes(); `stage` is pinned host staging.

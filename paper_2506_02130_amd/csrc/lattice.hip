@@ -56,13 +56,8 @@ struct T1Params {
     double2 *T;           // [n_freq][nf1][N0]
     double2 *modes;       // [n_freq][N1][N0]
     double *vis;
-    // FP32 spreading: the first (W + 1) / 2 of the kernel's W pieces as
-    // polynomials of degree W + 2 in the offset mapped to [-1, 1] (monomial
-    // coefficients, lowest first); piece W - 1 - i is piece i at -u
-    float poly[4][10];
+    EsPoly poly;  // FP32 spreading: the kernel's pieces as polynomials of the offset
 };
-
-constexpr int kT1PolyMaxW = 7;  // widths whose FP32 weights use the polynomials (eps >= 1e-6)
 
 
 // Nearest integer of d as a 64-bit integer for |d| < 2^51: adding 1.5 * 2^52
@@ -216,21 +211,12 @@ void k_t1_spread(T1Params P) {
                 double o;
                 l[a] = t1_first_cell<W>(P, a, kt, sx, sy, &o);
                 const double sc = a == 0 ? 1.0 : c * scale;
-                if constexpr (kWrap && W <= kT1PolyMaxW) {
-                    // o lies in (W/2 - 1, W/2]; u = 2 o - W + 1 in (-1, 1].  Piece i
-                    // is E(u^2) + u O(u^2) and its mirror W - 1 - i is E - u O.
-                    constexpr int D = W + 2, De = D - (D & 1), Do = D - 1 + (D & 1);
-                    const float u = (float)(2.0 * o - (W - 1)), v = u * u;
+                if constexpr (kWrap && W <= kPolyMaxW) {
+                    // o lies in (W/2 - 1, W/2]
+                    float wt[W];
+                    es_weights_poly<W>(P.poly, (float)(2.0 * o - (W - 1)), wt);
 #pragma unroll
-                    for (int i = 0; i < (W + 1) / 2; ++i) {
-                        float e = P.poly[i][De], od = P.poly[i][Do];
-#pragma unroll
-                        for (int k = De - 2; k >= 0; k -= 2) e = fmaf(e, v, P.poly[i][k]);
-#pragma unroll
-                        for (int k = Do - 2; k >= 1; k -= 2) od = fmaf(od, v, P.poly[i][k]);
-                        wd[a][i] = sc * (double)fmaf(u, od, e);
-                        if (W - 1 - i != i) wd[a][W - 1 - i] = sc * (double)fmaf(-u, od, e);
-                    }
+                    for (int i = 0; i < W; ++i) wd[a][i] = sc * (double)wt[i];
                 } else {
                     const R off = (R)o;
 #pragma unroll
@@ -427,41 +413,6 @@ void spread_pick(int w, dim3 g, size_t lds, hipStream_t st, hipEvent_t ea, hipEv
     if (!done) fail(FV_EUNSUPPORTED, "kernel width out of range");
 }
 
-// The FP32 spreading weights as polynomials: piece i of the ES kernel (the
-// weight of the kernel's i-th cell as a function of the source's offset) is
-// interpolated at the d + 1 Chebyshev nodes of u in [-1, 1] and the Chebyshev
-// series is turned into monomial coefficients.  With d = w + 2 the pieces
-// agree with the kernel to about exp(-beta) (the kernel's square-root edge at
-// |z| = 1 bounds a polynomial fit there), well below the accuracy the width
-// is chosen for.
-void es_poly_fit(int w, float *out /* [w][w + 3] */) {
-    const int d = w + 2, n = d + 1;
-    const double beta = 2.3 * w;
-    for (int i = 0; i < w; ++i) {
-        std::vector<double> y(n), mono(n, 0.0), tprev(n, 0.0), tcur(n, 0.0);
-        for (int j = 0; j < n; ++j) {
-            const double u = std::cos(M_PI * (j + 0.5) / n), t = 0.5 * (u + 1.0);
-            const double z = (i + 1 - 0.5 * w - t) * 2.0 / w, z2 = z * z;
-            y[j] = z2 <= 1.0 ? std::exp(-beta * z2 / (1.0 + std::sqrt(1.0 - z2))) : 0.0;
-        }
-        // T_0 = 1, T_1 = u, T_{k+1} = 2 u T_k - T_{k-1}, as monomial coefficients
-        tcur[0] = 1.0;
-        for (int k = 0; k < n; ++k) {
-            double ak = 0.0;  // Chebyshev coefficient k of the interpolant
-            for (int j = 0; j < n; ++j) ak += y[j] * std::cos(M_PI * k * (j + 0.5) / n);
-            ak *= (k == 0 ? 1.0 : 2.0) / n;
-            for (int m = 0; m < n; ++m) mono[m] += ak * tcur[m];
-            std::vector<double> next(n, 0.0);
-            for (int m = 0; m + 1 < n; ++m) next[m + 1] = (k == 0 ? 1.0 : 2.0) * tcur[m];
-            if (k > 0)
-                for (int m = 0; m < n; ++m) next[m] -= tprev[m];
-            tprev = tcur;
-            tcur = next;
-        }
-        for (int m = 0; m < n; ++m) out[i * n + m] = (float)mono[m];
-    }
-}
-
 }  // namespace
 
 void lattice_tables(LatticePlan &lp, int w) {
@@ -473,8 +424,6 @@ void lattice_tables(LatticePlan &lp, int w) {
         const double h = 2.0 * M_PI / sh.nf[a], alpha = w * h / 2.0;
         for (int k = 0; k < sh.N[a]; ++k) lp.dc[o + k] = h / (alpha * phihat_host(alpha * (k - lp.K[a]), qtab));
     }
-    lp.poly.assign((size_t)w * (w + 3), 0.0f);
-    if (w <= kT1PolyMaxW) es_poly_fit(w, lp.poly.data());
     lp.w = w;
     // one device copy: [dc][k], uploaded once (synchronous; the plan is cached)
     const size_t bd = sizeof(double) * lp.dc.size(), bk = sizeof(int) * lp.k.size();
@@ -560,11 +509,7 @@ double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, c
     P.freq = freq_dev;
     P.dc = (const double *)lp.dev;
     P.kc = (const int *)(P.dc + sh.N[0] + sh.N[1]);
-    if (w <= kT1PolyMaxW) {
-        if (lp.poly.size() != (size_t)w * (w + 3)) fail(FV_EDEVICE, "lattice tables not prepared");
-        for (int i = 0; i < (w + 1) / 2; ++i)
-            for (int m = 0; m < w + 3; ++m) P.poly[i][m] = lp.poly[(size_t)i * (w + 3) + m];
-    }
+    P.poly = es_poly(w);
 
     using WL = std::integer_sequence<int, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
     // each stage is one kernel, timed by the events its dispatch records

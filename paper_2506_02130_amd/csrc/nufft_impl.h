@@ -330,7 +330,7 @@ struct SpreadCfg {
 // multiplication by 1/psi2hat (the first deconvolution).
 template <typename R, int D, int W>
 __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, int n_snap, const int *bins,
-                                                const Rec<R, D> *recs, const R *ipsi, cplx<R> *grid) {
+                                                const Rec<R, D> *recs, const R *ipsi, cplx<R> *grid, EsPoly ep) {
     using Cfg = SpreadCfg<R, D, W>;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -408,10 +408,23 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
                 mcr = r.cr;
                 mci = r.ci;
 #pragma unroll
-                for (int a = 0; a < D; ++a)
+                for (int a = 0; a < D; ++a) {
+                    R wt[W];
+                    bool exact = true;
+                    if constexpr (std::is_same<R, float>::value && W <= kPolyMaxW) {
+                        // the offset lies in (W/2 - 1, W/2] up to rounding at the grid's edge
+                        const float u = 2.0f * r.off[a] - (float)(W - 1);
+                        if (fabsf(u) <= 1.001f) {
+                            es_weights_poly<W>(ep, u, wt);
+                            exact = false;
+                        }
+                    }
+                    if (exact)
 #pragma unroll
-                    for (int i = 0; i < W; ++i)
-                        kw[(lane * D + a) * W + i] = es_phi_fast((R)((R)i - r.off[a]) * inv_hw, beta);
+                        for (int i = 0; i < W; ++i) wt[i] = es_phi_fast((R)((R)i - r.off[a]) * inv_hw, beta);
+#pragma unroll
+                    for (int i = 0; i < W; ++i) kw[(lane * D + a) * W + i] = wt[i];
+                }
             }
             wave_sync();
             unsigned long long hm = __ballot(hit);
@@ -462,22 +475,25 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
 //     b[y][x] = sum_r ky_r(y) * (c'_r kx_r(x)),
 // i.e. the 16 x 16 x R product KY^T (C KX), accumulated 4 records at a time
 // by v_mfma_{f32,f64}_16x16x4 (A = y weights of 4 records, B = strength-scaled
-// x weights, real and imaginary parts in two accumulators).  Each lane builds
-// one A and one B element per step from the records staged in LDS.
+// x weights, real and imaginary parts in two accumulators).  Each lane stages
+// one record at a time in LDS with its 2 W kernel weights (evaluated once per
+// record and tile), then builds one A and one B element per step by lookup.
 template <typename R, int W>
 struct SpreadMfmaCfg {
     static constexpr int T = 16;            // tile edge
     static constexpr int WPB = 4;           // wavefronts (tiles) per block, along x
     static constexpr int BX = T * WPB, BY = T;
     static constexpr int MAXROWS = 8;       // sub-bin rows per tile
-    // staged records: l0x, l0y (int), offx, offy, cr, ci (R)
-    static constexpr int WAVE_BYTES = 64 * (2 * (int)sizeof(int) + 4 * (int)sizeof(R)) + 2 * MAXROWS * (int)sizeof(int);
+    // staged records: l0x, l0y (int), cr, ci (R), W x weights, W y weights (R)
+    static constexpr int WAVE_BYTES =
+        64 * (2 * (int)sizeof(int) + (2 + 2 * W) * (int)sizeof(R)) + 2 * MAXROWS * (int)sizeof(int);
     static_assert((T + W - 1 + kSubBin - 1) / kSubBin + 1 <= MAXROWS, "too many sub-bin rows per tile");
 };
 
 template <typename R, int W>
 __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int gx, int n_snap, const int *bins,
-                                                     const Rec<R, 2> *recs, const R *ipsi, cplx<R> *grid) {
+                                                     const Rec<R, 2> *recs, const R *ipsi, cplx<R> *grid,
+                                                     EsPoly ep) {
     using Cfg = SpreadMfmaCfg<R, W>;
     using MA = MfmaAcc<R>;
     extern __shared__ __align__(16) char smem[];
@@ -492,8 +508,9 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
     const int y0 = (blk / nbx) * Cfg::BY;
     char *wbase = smem + wave * Cfg::WAVE_BYTES;
     int *sl0x = (int *)wbase, *sl0y = sl0x + 64;
-    R *soffx = (R *)(sl0y + 64), *soffy = soffx + 64, *scr = soffy + 64, *sci = scr + 64;
-    int *rstart = (int *)(sci + 64), *rpre = rstart + Cfg::MAXROWS;
+    R *scr = (R *)(sl0y + 64), *sci = scr + 64;
+    R *skx = sci + 64, *sky = skx + 64 * W;  // [64][W] kernel weights per staged record
+    int *rstart = (int *)(sky + 64 * W), *rpre = rstart + Cfg::MAXROWS;
     const R beta = (R)S.beta;
     const R inv_hw = (R)(2.0 / W);
     const Rec<R, 2> *rs = recs + S.src_base;
@@ -530,10 +547,32 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
             const Rec<R, 2> r = rs[rstart[row] + (e - rpre[row])];
             sl0x[lane] = r.l0[0] - x0;
             sl0y[lane] = r.l0[1] - y0;
-            soffx[lane] = r.off[0];
-            soffy[lane] = r.off[1];
             scr[lane] = r.cr;
             sci[lane] = r.ci;
+            R wx[W], wy[W];
+            bool exact = true;
+            if constexpr (std::is_same<R, float>::value && W <= kPolyMaxW) {
+                // the offsets lie in (W/2 - 1, W/2] (up to rounding where the first
+                // cell is clamped at the grid's edge; the exact kernel takes any other)
+                const float ux = 2.0f * r.off[0] - (float)(W - 1), uy = 2.0f * r.off[1] - (float)(W - 1);
+                if (fabsf(ux) <= 1.001f && fabsf(uy) <= 1.001f) {
+                    es_weights_poly<W>(ep, ux, wx);
+                    es_weights_poly<W>(ep, uy, wy);
+                    exact = false;
+                }
+            }
+            if (exact) {
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    wx[i] = es_phi_fast((R)((R)i - r.off[0]) * inv_hw, beta);
+                    wy[i] = es_phi_fast((R)((R)i - r.off[1]) * inv_hw, beta);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                skx[lane * W + i] = wx[i];
+                sky[lane * W + i] = wy[i];
+            }
         }
         wave_sync();
         const int nb = min(64, total - b0);
@@ -543,9 +582,9 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
             R a = 0, bre = 0, bim = 0;
             if (rr < nb) {
                 const int dy = li - sl0y[rr], dx = li - sl0x[rr];
-                if ((unsigned)dy < (unsigned)W) a = es_phi_fast((R)((R)dy - soffy[rr]) * inv_hw, beta);
+                if ((unsigned)dy < (unsigned)W) a = sky[rr * W + dy];
                 if ((unsigned)dx < (unsigned)W) {
-                    const R kx = es_phi_fast((R)((R)dx - soffx[rr]) * inv_hw, beta);
+                    const R kx = skx[rr * W + dx];
                     bre = scr[rr] * kx;
                     bim = sci[rr] * kx;
                 }
@@ -855,7 +894,8 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
 // Interpolation at the targets, deconvolution by psi1hat, centring phase,
 // reflection undone, written to the caller's pair layout.
 template <typename R, int D, int W>
-__global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, int n_snap, const cplx<R> *grid) {
+__global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, int n_snap, const cplx<R> *grid,
+                                                EsPoly ep) {
     int bx, sy;
     if (!snap_block(gx, n_snap, bx, sy)) return;
     const SnapDev &S = snaps[sy];
@@ -875,8 +915,18 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, in
         int p = (int)ceil(q - 0.5 * W);
         p = min(max(p, -S.P[a]), S.P[a] - W + 1);
         const R off = (R)(q - p);
+        bool exact = true;
+        if constexpr (std::is_same<R, float>::value && W <= kPolyMaxW) {
+            // off lies in (W/2 - 1, W/2] unless the window clamp moved p
+            const float u = 2.0f * off - (float)(W - 1);
+            if (fabsf(u) <= 1.001f) {
+                es_weights_poly<W>(ep, u, kw[a]);
+                exact = false;
+            }
+        }
+        if (exact)
 #pragma unroll
-        for (int i = 0; i < W; ++i) kw[a][i] = es_phi((R)((R)i - off) * inv_hw, beta);
+            for (int i = 0; i < W; ++i) kw[a][i] = es_phi((R)((R)i - off) * inv_hw, beta);
         p0[a] = p + S.P[a];
     }
     R ar = 0, ai = 0;
@@ -1269,14 +1319,14 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
             ensure_lds((const void *)k_spread_mfma<R, W>, lds);
             hipLaunchKernelGGL((k_spread_mfma<R, W>), sgrid(L.max_tiles), dim3(64 * MC::WPB), lds, st, snaps_dev,
                                sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, 2> *)recs, (const R *)ipsi,
-                               grid);
+                               grid, es_poly(W));
         } else {
             using Cfg = SpreadCfg<R, D, W>;
             const size_t lds = spread_lds<R, D, W>();
             ensure_lds((const void *)k_spread<R, D, W>, lds);
             hipLaunchKernelGGL((k_spread<R, D, W>), sgrid(L.max_tiles), dim3(64 * Cfg::WPB), lds, st, snaps_dev,
                                sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, D> *)recs,
-                               (const R *)ipsi, grid);
+                               (const R *)ipsi, grid, es_poly(W));
         }
         tm->end(st);
         tm->add(FV_STAGE_SPREAD, L.sbytes[FV_STAGE_SPREAD], 1);
@@ -1312,7 +1362,7 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
         tm->begin(FV_STAGE_INTERP, st);
         const long long gx = blocks(L.max_tgt, 256);
         hipLaunchKernelGGL((k_interp<R, D, W>), sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap,
-                           (const cplx<R> *)grid);
+                           (const cplx<R> *)grid, es_poly(W));
         tm->end(st);
         tm->add(FV_STAGE_INTERP, L.sbytes[FV_STAGE_INTERP], 1);
     }

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <vector>
 
 #include "fv_internal.h"
 
@@ -337,6 +338,54 @@ bool find_lattice(const double *ant, int n_ant, double tol, LatticePlan *lp) {
     lp->K[0] = hi[0] - lo[0];
     lp->K[1] = hi[1] - lo[1];
     return true;
+}
+
+// Piece i of the kernel of width w interpolated at the n = w + 3 Chebyshev
+// nodes of u, then turned from a Chebyshev series into monomial coefficients.
+// The fit's largest error is about exp(-beta): the kernel's square-root edge
+// at |z| = 1 bounds any polynomial there.
+static void es_poly_piece(int w, int i, float *out /* [w + 3] */) {
+    const int n = w + 3;
+    const double beta = 2.3 * w;
+    std::vector<double> y(n), mono(n, 0.0), tprev(n, 0.0), tcur(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        const double u = std::cos(M_PI * (j + 0.5) / n), t = 0.5 * (u + 1.0);
+        const double z = (i + 1 - 0.5 * w - t) * 2.0 / w, z2 = z * z;
+        y[j] = z2 <= 1.0 ? std::exp(-beta * z2 / (1.0 + std::sqrt(1.0 - z2))) : 0.0;
+    }
+    // T_0 = 1, T_1 = u, T_{k+1} = 2 u T_k - T_{k-1}, as monomial coefficients
+    tcur[0] = 1.0;
+    for (int k = 0; k < n; ++k) {
+        double ak = 0.0;  // Chebyshev coefficient k of the interpolant
+        for (int j = 0; j < n; ++j) ak += y[j] * std::cos(M_PI * k * (j + 0.5) / n);
+        ak *= (k == 0 ? 1.0 : 2.0) / n;
+        for (int m = 0; m < n; ++m) mono[m] += ak * tcur[m];
+        std::vector<double> next(n, 0.0);
+        for (int m = 0; m + 1 < n; ++m) next[m + 1] = (k == 0 ? 1.0 : 2.0) * tcur[m];
+        if (k > 0)
+            for (int m = 0; m < n; ++m) next[m] -= tprev[m];
+        tprev = tcur;
+        tcur = next;
+    }
+    for (int m = 0; m < n; ++m) out[m] = (float)mono[m];
+}
+
+const EsPoly &es_poly(int w) {
+    static const std::vector<EsPoly> tab = [] {
+        std::vector<EsPoly> t(kPolyMaxW + 1);
+        for (int w = 0; w <= kPolyMaxW; ++w) {
+            std::memset(&t[w], 0, sizeof(EsPoly));
+            if (w >= 2)
+                for (int i = 0; i < (w + 1) / 2; ++i) es_poly_piece(w, i, t[w].c[i]);
+        }
+        return t;
+    }();
+    static const EsPoly zero = [] {
+        EsPoly z;
+        std::memset(&z, 0, sizeof(z));
+        return z;
+    }();
+    return w >= 0 && w <= kPolyMaxW ? tab[w] : zero;
 }
 
 double phihat_host(double xi, const double *q) {
