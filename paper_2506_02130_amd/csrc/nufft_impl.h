@@ -766,6 +766,10 @@ __global__ void k_digrev(int L, int *drev) {
 
 // Entries of the two twiddle tables of an N-point line.
 __host__ __device__ inline int fft_tw_entries(int N) { return (N >> 6) + 1 + 64; }
+// grid loads per thread in flight in a pass's input phase (fewer FP64 values
+// keep the FP64 passes' register count, and so their occupancy)
+template <typename R>
+constexpr int kFftLoads = sizeof(R) == 4 ? 8 : 4;
 
 // Physical workgroup b runs on XCD b mod 8 (round-robin dispatch); logical
 // workgroups are handed out so that each XCD gets one contiguous range, and
@@ -840,28 +844,45 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
         twc[t] = tw[g < N ? g : 0];
     }
     __syncthreads();
+    // kFftLoads<R> grid loads per thread are issued before any is used (one load
+    // at a time leaves the pass waiting on memory latency)
     const float invL = 1.0f / (float)L, invcx = 1.0f / (float)cx;
-    for (int e = threadIdx.x; e < cx * L; e += TPB) {
-        int l, c;
-        long long src;
-        if (rows) {
-            c = fdiv(e, L, invL);
-            l = e - c * L;
-            src = c * in_ls + l;
-        } else {
-            l = fdiv(e, cx, invcx);
-            c = e - l * cx;
-            src = (long long)l * F + c;
+    for (int e0 = threadIdx.x; e0 < cx * L; e0 += kFftLoads<R> * TPB) {
+        int lj[kFftLoads<R>], cj[kFftLoads<R>];
+        cplx<R> v[kFftLoads<R>];
+#pragma unroll
+        for (int u = 0; u < kFftLoads<R>; ++u) {
+            const int e = e0 + u * TPB;
+            lj[u] = 0;
+            cj[u] = 0;
+            if (e < cx * L) {
+                long long src;
+                if (rows) {
+                    cj[u] = fdiv(e, L, invL);
+                    lj[u] = e - cj[u] * L;
+                    src = cj[u] * in_ls + lj[u];
+                } else {
+                    lj[u] = fdiv(e, cx, invcx);
+                    cj[u] = e - lj[u] * cx;
+                    src = (long long)lj[u] * F + cj[u];
+                }
+                v[u] = in[src];
+            }
         }
-        int j = l + half;
-        if (j >= L) j -= L;
-        const cplx<R> v = in[src];
-        if (!split || only) {
-            cplx<R> vo = cmul<R>(v, twiddle<R>(twc, twf, j));
-            if (j >= half) vo = cmake<R>(-vo.x, -vo.y);
-            buf[(tps * c + tps - 1) * Lp + cpad(j)] = vo;
+#pragma unroll
+        for (int u = 0; u < kFftLoads<R>; ++u) {
+            if (e0 + u * TPB < cx * L) {
+                const int c = cj[u];
+                int j = lj[u] + half;
+                if (j >= L) j -= L;
+                if (!split || only) {
+                    cplx<R> vo = cmul<R>(v[u], twiddle<R>(twc, twf, j));
+                    if (j >= half) vo = cmake<R>(-vo.x, -vo.y);
+                    buf[(tps * c + tps - 1) * Lp + cpad(j)] = vo;
+                }
+                if (!split || !only) buf[(tps * c) * Lp + cpad(j)] = v[u];
+            }
         }
-        if (!split || !only) buf[(tps * c) * Lp + cpad(j)] = v;
     }
     __syncthreads();
     dif_fft<R, TPB>(buf, L, Lp, tps * cx, twc, twf);
