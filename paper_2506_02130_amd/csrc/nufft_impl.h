@@ -539,12 +539,19 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
     wave_sync();
     typename MA::T accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
     const int li = lane & 15, lk = lane >> 4;  // A row / B column index, record slot of the 4
+    // record e of the tile's neighbourhood (a position in its sub-bin rows)
+    auto fetch = [&](int e) {
+        int row = 0;
+        while (row + 1 < nrows && rpre[row + 1] <= e) ++row;
+        return rs[rstart[row] + (e - rpre[row])];
+    };
+    // each batch's records are loaded while the previous batch is on the matrix cores
+    Rec<R, 2> nxt;
+    if (lane < total) nxt = fetch(lane);
     for (int b0 = 0; b0 < total; b0 += 64) {
         const int e = b0 + lane;
         if (e < total) {
-            int row = 0;
-            while (row + 1 < nrows && rpre[row + 1] <= e) ++row;
-            const Rec<R, 2> r = rs[rstart[row] + (e - rpre[row])];
+            const Rec<R, 2> r = nxt;
             sl0x[lane] = r.l0[0] - x0;
             sl0y[lane] = r.l0[1] - y0;
             scr[lane] = r.cr;
@@ -575,6 +582,7 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
             }
         }
         wave_sync();
+        if (e + 64 < total) nxt = fetch(e + 64);
         const int nb = min(64, total - b0);
 #pragma unroll 2
         for (int g = 0; g < nb; g += 4) {
