@@ -118,22 +118,28 @@ __global__ void k_fill_int(int *p, long long n, int v) {
 // Rank of this lane's key among the lanes of its wavefront that share the key,
 // plus the count already in counts[key]: one returning atomic per distinct key
 // in the wavefront (lanes of a spatially ordered source list mostly share a
-// few sub-bins).  Every active lane of the wavefront must call it.
+// few sub-bins).  The groups of equal keys are found with ballots first; then
+// the first lane of every group adds its group's size in one atomic
+// instruction for all groups, and each lane reads its group's old count from
+// its leader.  Every active lane of the wavefront must call it.
 __device__ __forceinline__ int wave_rank(int *counts, int key) {
     const int lane = threadIdx.x & 63;
     unsigned long long todo = __ballot(1);
-    int rank = 0;
+    int leader = lane, below = 0, size = 0;
     while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int lk = __shfl(key, leader, 64);
+        const int l = __ffsll((long long)todo) - 1;
+        const int lk = __shfl(key, l, 64);
         const unsigned long long m = __ballot(key == lk) & todo;
-        int old = 0;
-        if (lane == leader) old = atomicAdd(&counts[lk], __popcll(m));
-        old = __shfl(old, leader, 64);
-        if ((m >> lane) & 1ull) rank = old + __popcll(m & ((1ull << lane) - 1ull));
+        if ((m >> lane) & 1ull) {
+            leader = l;
+            below = __popcll(m & ((1ull << lane) - 1ull));
+        }
+        if (lane == l) size = __popcll(m);
         todo &= ~m;
     }
-    return rank;
+    int old = 0;
+    if (lane == leader) old = atomicAdd(&counts[key], size);
+    return __shfl(old, leader, 64) + below;
 }
 
 // Per-snapshot counting sort of the sources by sub-bin.  Sources are visited
