@@ -448,9 +448,9 @@ def main():
     # the dominant stage, from the warm-up's stage events
     w_ms, w_launch, _ = stage_table(ctx.stage_times(), warm[-1])
     dom = max((n for n in fv.STAGES if w_launch[n] > 0), key=lambda n: w_ms[n])
-    # in the timed steps only the dominant kernel records events when it is the
-    # spreading kernel (two events per call, the least the live measurement costs)
-    flags = base | (fv.TIMING_SPREAD_ONLY if dom == "spread" else 0)
+    # in the timed steps only the dominant stage records events (two per launch
+    # of it: the least the live measurement costs)
+    flags = base | fv.timing_stage(dom)
 
     # ---------------------------------------------------------------- timed region
     reps = []

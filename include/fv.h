@@ -88,9 +88,11 @@ typedef enum {
                                       not wait for them; fv_stage_times returns their sums over every
                                       such call since its last use (t_stage_ms stays 0 in each call's
                                       report, stage_bytes and stage_launches are filled) */
-#define FV_TIMING_SPREAD_ONLY 0x4000u /* with FV_TIMING or FV_TIMING_ACCUM: only the spreading stage
-                                      records events (the other stages' times stay 0); two events per
-                                      call instead of two per kernel */
+#define FV_TIMING_ONE_STAGE 0x4000u /* with FV_TIMING or FV_TIMING_ACCUM: only the stage in flag bits
+                                      16-19 (FV_TIMING_STAGE) records events, two per launch of it; the
+                                      other stages' times stay 0 */
+#define FV_TIMING_STAGE(s) (FV_TIMING_ONE_STAGE | ((unsigned)(s) << 16))  /* s: an FV_STAGE_* index */
+#define FV_TIMING_STAGE_OF(flags) ((int)(((flags) >> 16) & 0xFu))
 
 /* stage indices of fv_report.t_stage_ms / stage_bytes / stage_launches */
 #define FV_STAGE_SORT      0      /* key, count, scan and scatter of the source records */

@@ -32,8 +32,17 @@ AUTOTUNE = 0x400
 GRAPH = 0x800
 NO_LATTICE = 0x1000
 TIMING_ACCUM = 0x2000  # stage events without waiting; sums from Context.stage_times()
-TIMING_SPREAD_ONLY = 0x4000  # with TIMING or TIMING_ACCUM: only the spreading stage records events
+TIMING_ONE_STAGE = 0x4000  # with TIMING or TIMING_ACCUM: only one stage (flag bits 16-19) records events
 STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
+
+
+def timing_stage(stage) -> int:
+    """Flags that restrict event recording to one stage (a name of STAGES or
+    its index), as FV_TIMING_STAGE(s); combine with TIMING or TIMING_ACCUM."""
+    s = STAGES.index(stage) if isinstance(stage, str) else int(stage)
+    if not 0 <= s < len(STAGES):
+        raise ValueError(f"no stage {stage!r}")
+    return TIMING_ONE_STAGE | (s << 16)
 
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",

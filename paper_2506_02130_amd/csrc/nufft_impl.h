@@ -23,6 +23,7 @@
 // Grid arithmetic is R (float or double); every coordinate, phase and
 // deconvolution factor is computed in FP64.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <utility>
 
@@ -1290,6 +1291,20 @@ inline bool xcd_affine(int n_snap) {
     return n_snap % 8 == 0 || n_snap >= 32;
 }
 
+// One stage that is one kernel: with timing on, the dispatch itself records
+// the stage's start and stop events (no separate marker packets); otherwise a
+// plain launch (as under graph capture).
+template <typename... KA, typename... A>
+void launch_stage(StageTimer *tm, int stage, void (*kernel)(KA...), dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                  A... args) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    tm->kernel_events(stage, &ea, &eb);
+    if (ea)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, ea, eb, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
+
 // stages: bit 0 sort + spread, bit 1 FFT passes, bit 2 interpolation.
 template <typename R, int D, int W>
 void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, int stages, StageTimer *tm) {
@@ -1312,10 +1327,9 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     if (stages & 1) {
     if (L.total_bins)
         hipLaunchKernelGGL(k_fill_int, dim3(blocks(L.total_bins, 256)), dim3(256), 0, st, bins, L.total_bins, 0);
-    tm->begin(FV_STAGE_OTHER, st);
     if (L.max_ipsi)
-        hipLaunchKernelGGL(k_ipsi<R>, dim3(blocks(L.max_ipsi, 256), n_snap), dim3(256), 0, st, snaps_dev, ipsi);
-    tm->end(st);
+        launch_stage(tm, FV_STAGE_OTHER, k_ipsi<R>, dim3(blocks(L.max_ipsi, 256), n_snap), dim3(256), 0, st,
+                     snaps_dev, ipsi);
     tm->add(FV_STAGE_OTHER, L.sbytes[FV_STAGE_OTHER], 1);
     tm->begin(FV_STAGE_SORT, st);
     int sort_launches = 3;
@@ -1347,23 +1361,21 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     tm->end(st);
     tm->add(FV_STAGE_SORT, L.sbytes[FV_STAGE_SORT], sort_launches);
     {
-        tm->begin(FV_STAGE_SPREAD, st);
         if constexpr (D == 2) {
             using MC = SpreadMfmaCfg<R, W>;
             const size_t lds = (size_t)MC::WPB * MC::WAVE_BYTES;
             ensure_lds((const void *)k_spread_mfma<R, W>, lds);
-            hipLaunchKernelGGL((k_spread_mfma<R, W>), sgrid(L.max_tiles), dim3(64 * MC::WPB), lds, st, snaps_dev,
-                               sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, 2> *)recs, (const R *)ipsi,
-                               grid, es_poly(W));
+            launch_stage(tm, FV_STAGE_SPREAD, k_spread_mfma<R, W>, sgrid(L.max_tiles), dim3(64 * MC::WPB), lds, st,
+                         snaps_dev, sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, 2> *)recs,
+                         (const R *)ipsi, grid, es_poly(W));
         } else {
             using Cfg = SpreadCfg<R, D, W>;
             const size_t lds = spread_lds<R, D, W>();
             ensure_lds((const void *)k_spread<R, D, W>, lds);
-            hipLaunchKernelGGL((k_spread<R, D, W>), sgrid(L.max_tiles), dim3(64 * Cfg::WPB), lds, st, snaps_dev,
-                               sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, D> *)recs,
-                               (const R *)ipsi, grid, es_poly(W));
+            launch_stage(tm, FV_STAGE_SPREAD, k_spread<R, D, W>, sgrid(L.max_tiles), dim3(64 * Cfg::WPB), lds, st,
+                         snaps_dev, sgx(L.max_tiles), n_snap, (const int *)bins, (const Rec<R, D> *)recs,
+                         (const R *)ipsi, grid, es_poly(W));
         }
-        tm->end(st);
         tm->add(FV_STAGE_SPREAD, L.sbytes[FV_STAGE_SPREAD], 1);
     }
     }
@@ -1371,34 +1383,31 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     for (int a = 0; a < D; ++a) {
         // a multiple of 8 workgroups along x, so that the XCD of (x, y) is x mod 8
         const dim3 nb((unsigned)((L.max_wg[a] + 7) / 8 * 8), (unsigned)n_snap);
-        tm->begin(FV_STAGE_FFT_X + a, st);
+        const int fs = FV_STAGE_FFT_X + a;
         switch (L.tpb[a]) {
             case 128:
                 ensure_lds((const void *)k_fft<R, 128>, L.fft_lds[a]);
-                hipLaunchKernelGGL((k_fft<R, 128>), nb, dim3(128), L.fft_lds[a], st, snaps_dev, a, grid);
+                launch_stage(tm, fs, k_fft<R, 128>, nb, dim3(128), L.fft_lds[a], st, snaps_dev, a, grid);
                 break;
             case 256:
                 ensure_lds((const void *)k_fft<R, 256>, L.fft_lds[a]);
-                hipLaunchKernelGGL((k_fft<R, 256>), nb, dim3(256), L.fft_lds[a], st, snaps_dev, a, grid);
+                launch_stage(tm, fs, k_fft<R, 256>, nb, dim3(256), L.fft_lds[a], st, snaps_dev, a, grid);
                 break;
             case 512:
                 ensure_lds((const void *)k_fft<R, 512>, L.fft_lds[a]);
-                hipLaunchKernelGGL((k_fft<R, 512>), nb, dim3(512), L.fft_lds[a], st, snaps_dev, a, grid);
+                launch_stage(tm, fs, k_fft<R, 512>, nb, dim3(512), L.fft_lds[a], st, snaps_dev, a, grid);
                 break;
             default:
                 ensure_lds((const void *)k_fft<R, 1024>, L.fft_lds[a]);
-                hipLaunchKernelGGL((k_fft<R, 1024>), nb, dim3(1024), L.fft_lds[a], st, snaps_dev, a, grid);
+                launch_stage(tm, fs, k_fft<R, 1024>, nb, dim3(1024), L.fft_lds[a], st, snaps_dev, a, grid);
                 break;
         }
-        tm->end(st);
         tm->add(FV_STAGE_FFT_X + a, L.sbytes[FV_STAGE_FFT_X + a], 1);
     }
     if ((stages & 4) && L.max_tgt) {
-        tm->begin(FV_STAGE_INTERP, st);
         const long long gx = blocks(L.max_tgt, 256);
-        hipLaunchKernelGGL((k_interp<R, D, W>), sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap,
-                           (const cplx<R> *)grid, es_poly(W));
-        tm->end(st);
+        launch_stage(tm, FV_STAGE_INTERP, k_interp<R, D, W>, sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap,
+                     (const cplx<R> *)grid, es_poly(W));
         tm->add(FV_STAGE_INTERP, L.sbytes[FV_STAGE_INTERP], 1);
     }
     FV_HIP(hipGetLastError());

@@ -580,7 +580,7 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
     std::memset(&r, 0, sizeof(r));
     StageTimer &tm = slot.timer;
     tm.reset((p->flags & (FV_TIMING | FV_TIMING_ACCUM)) != 0, (p->flags & FV_TIMING_ACCUM) != 0,
-             (p->flags & FV_TIMING_SPREAD_ONLY) ? FV_STAGE_SPREAD : -1);
+             (p->flags & FV_TIMING_ONE_STAGE) ? FV_TIMING_STAGE_OF(p->flags) : -1);
     r.dim = dim;
     r.prec_bits = prec;
     r.method = (int)method;

@@ -172,12 +172,18 @@ def test_accumulated_stage_times(gpu_lib):
         assert c.stage_times()["calls"] == 0                       # a new sum started
         r = c.simulate_dev(*args, vis, eps=1e-6, flags=fv.TIMING)    # per-call timing still works
         assert r["t_stage_ms"][i] > 0
-        # only the spreading stage records events with TIMING_SPREAD_ONLY
+        # only the chosen stage records events with timing_stage(...)
         for _ in range(2):
-            c.simulate_dev(*args, vis, eps=1e-6, flags=fv.TIMING_ACCUM | fv.TIMING_SPREAD_ONLY)
+            c.simulate_dev(*args, vis, eps=1e-6, flags=fv.TIMING_ACCUM | fv.timing_stage("spread"))
         t = c.stage_times()
         assert t["calls"] == 2 and t["launches"][i] == 2 and t["ms"][i] > 0
         assert sum(t["launches"]) == 2 and sum(t["ms"]) == t["ms"][i]
+        k = fv.STAGES.index("fft_y")                                 # a type-3 stage
+        for _ in range(2):
+            c.simulate_dev(*args, vis, eps=1e-6, flags=fv.TIMING_ACCUM | fv.NO_LATTICE | fv.timing_stage(k))
+        t = c.stage_times()
+        assert t["calls"] == 2 and t["launches"][k] == 2 and t["ms"][k] > 0
+        assert sum(t["launches"]) == 2 and sum(t["ms"]) == t["ms"][k]
         torch.cuda.synchronize()
         o = vis.cpu().numpy()
         assert oracle.rel_l2(o[..., 0] + 1j * o[..., 1], oracle.direct_problem(p)) <= 1e-6
