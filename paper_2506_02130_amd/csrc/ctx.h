@@ -61,9 +61,10 @@ struct fv_ctx {
     size_t scalar_cap = 0;  // doubles
     fv::PinnedBuf plan_pin;  // host staging of the planning scalars of fv_simulate_dev
     // The device entry point's last planning scalars, for calls that repeat its
-    // arguments (same device pointers and sizes): when that call took the type-1
-    // path, the next one enqueues the type-1 kernels right behind its input check
-    // on the last call's antenna positions and frequencies, then verifies them
+    // arguments (same device pointers, sizes, eps and flags): the next such call
+    // enqueues the last call's path (type 1 or type 3) right behind its input
+    // check, planned on the last call's antenna positions, frequencies and
+    // source box, while the host waits for the check; it then verifies those
     // (and the path choice) against the new check and recomputes on a mismatch.
     struct DevSpec {
         bool valid = false;
@@ -73,6 +74,8 @@ struct fv_ctx {
         unsigned flags = 0;
         std::vector<double> ant, freq;
         double s_c[3] = {0, 0, 0}, S[3] = {0, 0, 0};
+        bool lattice = false;  // the last call's path: type 1, else type 3 (whose plan follows the source box)
+        int dim = 0;
         hipEvent_t ev = nullptr;  // the check's copy to the host
     } spec;
     fv::TuneCache tunes;     // autotuned FFT launch shapes

@@ -796,7 +796,7 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
             double box[6];
             std::memcpy(box, sp.s_c, sizeof(sp.s_c));
             std::memcpy(box + 3, sp.S, sizeof(sp.S));
-            fv::run_device(ctx, slot, meta, dev_inputs(box), vis, &rs);  // the last call's path: type 1
+            fv::run_device(ctx, slot, meta, dev_inputs(box), vis, &rs);  // the last call's path and plan
             FV_HIP(hipEventSynchronize(sp.ev));
             ran = true;
         } else {
@@ -824,16 +824,20 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
             }
         const fv::DevInputs in = dev_inputs(box);
         if (ran) {
-            // the speculation holds when the geometry is the last call's and the
-            // type-1 path is still the choice for this call's source box
+            // the speculation holds when the geometry is the last call's and its
+            // path is still the choice for this call's source box; a type-3 plan
+            // also follows the source box itself
             int w = 0;
-            ran = ant == sp.ant && freq == sp.freq && dim == 2 &&
-                  fv::lattice_choice(ctx, meta, in, fv::choose_prec(p->eps, p->flags), &w) != nullptr;
+            const bool lat = dim == 2 && !(p->flags & FV_NO_LATTICE) &&
+                             fv::lattice_choice(ctx, meta, in, fv::choose_prec(p->eps, p->flags), &w) != nullptr;
+            ran = ant == sp.ant && freq == sp.freq && dim == sp.dim && lat == sp.lattice &&
+                  (sp.lattice || (std::memcmp(box, sp.s_c, sizeof(sp.s_c)) == 0 &&
+                                  std::memcmp(box + 3, sp.S, sizeof(sp.S)) == 0));
             if (ran && rep) *rep = rs;
         }
         if (!ran) fv::run_device(ctx, slot, meta, in, vis, rep ? rep : &rs);
         const fv_report &used = rep ? *rep : rs;
-        if (used.lattice && p->n_src > 0 && (p->flags & FV_METHOD_MASK) == FV_METHOD_NUFFT && !(p->flags & FV_GRAPH)) {
+        if (p->n_src > 0 && (p->flags & FV_METHOD_MASK) == FV_METHOD_NUFFT && !(p->flags & FV_GRAPH)) {
             std::memcpy(sp.ptr, ptrs, sizeof(ptrs));
             sp.n_ant = p->n_ant;
             sp.n_freq = p->n_freq;
@@ -844,6 +848,8 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
             sp.freq = freq;
             std::memcpy(sp.s_c, box, sizeof(sp.s_c));
             std::memcpy(sp.S, box + 3, sizeof(sp.S));
+            sp.lattice = used.lattice != 0;
+            sp.dim = used.dim;
             sp.valid = true;
         }
     } catch (...) {

@@ -153,6 +153,69 @@ def test_repeated_device_calls_follow_changed_contents(gpu_lib):
         run(c, q)
 
 
+def test_repeated_type3_calls_follow_changed_contents(gpu_lib):
+    """Calls repeating the device pointers of a type-3 call enqueue its plan
+    (made from the last call's antennas, frequencies and source box) before the
+    planning scalars are back; every change behind those pointers must still
+    give the right answer: new fluxes, sources reordered inside the same box
+    (the plan holds), a source box that grows or shrinks, moved antennas, new
+    frequencies, and an invalid input followed by a valid one."""
+    import dataclasses
+    import torch
+    fv = gpu_lib
+    dev = torch.device("cuda:0")
+    p = synth.small_problem(162, n_ant=30, n_src=2500, n_freq=3, hex_layout=False)
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(p, k), dtype=np.float64)).to(dev)
+         for k in ("ant_enu", "src_lmn", "freq_hz", "flux", "beam")}
+    vis = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+
+    def run(c, ref_problem, flags=0):
+        rep = c.simulate_dev(t["ant_enu"], t["src_lmn"], t["freq_hz"], t["flux"], t["beam"], vis, eps=1e-6,
+                             flags=flags)
+        torch.cuda.synchronize()
+        o = vis.cpu().numpy()
+        assert oracle.rel_l2(o[..., 0] + 1j * o[..., 1], oracle.direct_problem(ref_problem)) <= 1e-6
+        assert rep["lattice"] == 0
+        return rep
+
+    def put(q):
+        for k in ("ant_enu", "src_lmn", "freq_hz", "flux", "beam"):
+            t[k].copy_(torch.from_numpy(np.ascontiguousarray(getattr(q, k), dtype=np.float64)))
+
+    with fv.Context(0) as c:
+        for flags in (0, fv.NO_LATTICE):
+            put(p)
+            run(c, p, flags)
+            run(c, p, flags)                                       # repeated as is
+            q = dataclasses.replace(p, flux=p.flux * np.linspace(0.5, 2.0, p.n_src)[None, :])
+            put(q)
+            run(c, q, flags)                                       # new strengths
+            perm = np.random.default_rng(4).permutation(p.n_src)
+            q = dataclasses.replace(q, src_lmn=q.src_lmn[perm], flux=q.flux[:, perm], beam=q.beam[:, perm])
+            put(q)
+            run(c, q, flags)                                       # reordered, same box
+            keep = np.abs(q.src_lmn[:, 0]) < 0.3                   # a smaller box
+            inside = q.src_lmn[np.flatnonzero(keep)[0]]
+            qb = dataclasses.replace(q, src_lmn=np.where(keep[:, None], q.src_lmn, inside),
+                                     flux=np.where(keep[None, :], q.flux, 0.0))
+            put(qb)
+            run(c, qb, flags)
+            put(q)
+            run(c, q, flags)                                       # and back
+            q = dataclasses.replace(q, ant_enu=q.ant_enu * 1.2 + np.array([1.0, -2.0, 0.0]))
+            put(q)
+            run(c, q, flags)                                       # moved antennas
+            q = dataclasses.replace(q, freq_hz=q.freq_hz * 0.9)
+            put(q)
+            run(c, q, flags)                                       # new frequencies
+            t["flux"][1, 7] = float("nan")
+            with pytest.raises(fv.FvError, match="EINVAL"):
+                c.simulate_dev(t["ant_enu"], t["src_lmn"], t["freq_hz"], t["flux"], t["beam"], vis, eps=1e-6,
+                               flags=flags)
+            put(q)
+            run(c, q, flags)
+
+
 def test_accumulated_stage_times(gpu_lib):
     """FV_TIMING_ACCUM calls record stage events without waiting; the query
     sums them over the calls and starts anew."""
