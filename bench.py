@@ -371,7 +371,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed steps first (about a second on the type-3 path: a fresh GPU is still ramping up)")
     ap.add_argument("--n-src", type=int, default=100_000)
     ap.add_argument("--n-freq", type=int, default=64)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-sum comparison")
