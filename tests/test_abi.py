@@ -48,3 +48,21 @@ def test_product_does_not_import_oracle():
             if fn.endswith((".py", ".cpp", ".hip", ".h")):
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "oracle/" not in src, fn
+
+
+def test_binding_flags_and_stage_indices_match_the_header():
+    """The binding's flag constants and stage names follow include/fv.h."""
+    import paper_2506_02130_amd as fv
+    src = open(os.path.join(ROOT, "include", "fv.h")).read()
+    defs = dict(re.findall(r"#define\s+(FV_[A-Z0-9_]+)\s+(0x[0-9A-Fa-f]+|\d+)u?\b", src))
+    for name in ("TIMING", "AUTOTUNE", "GRAPH", "NO_LATTICE", "TIMING_ACCUM", "TIMING_ONE_STAGE"):
+        assert getattr(fv, name) == int(defs["FV_" + name], 0), name
+    for i, st in enumerate(fv.STAGES):
+        assert int(defs["FV_STAGE_" + st.upper()], 0) == i, st
+    assert "(FV_TIMING_ONE_STAGE | ((unsigned)(s) << 16))" in src
+    assert fv.timing_stage("fft_x") == fv.TIMING_ONE_STAGE | (2 << 16)
+    assert fv.timing_stage(1) == fv.timing_stage("spread")
+    with pytest.raises(ValueError):
+        fv.timing_stage("nope")
+    with pytest.raises(ValueError):
+        fv.timing_stage(len(fv.STAGES))
