@@ -929,7 +929,10 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
 
 // Interpolation at the targets, deconvolution by psi1hat, centring phase,
 // reflection undone, written to the caller's pair layout.
-template <typename R, int D, int W>
+// DEG: some snapshot of the launch has a clamped axis, whose psi1hat is
+// evaluated here by quadrature (a variant of its own: the quadrature's
+// registers would halve the occupancy of the common case).
+template <typename R, int D, int W, bool DEG>
 __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, int n_snap, const cplx<R> *grid,
                                                 EsPoly ep) {
     int bx, sy;
@@ -996,8 +999,12 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, in
     double dot = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double ph = (S.degenerate >> a) & 1 ? phihat_quad(S.xi_deg[a] * (bb[a] - S.b_c[a]), S.qn)
-                                                   : S.tphi[(long long)a * S.n_tgt + t];
+        double ph;
+        if constexpr (DEG)
+            ph = (S.degenerate >> a) & 1 ? phihat_quad(S.xi_deg[a] * (bb[a] - S.b_c[a]), S.qn)
+                                         : S.tphi[(long long)a * S.n_tgt + t];
+        else
+            ph = S.tphi[(long long)a * S.n_tgt + t];
         fac /= ph;
         dot += bb[a] * S.s_c[a];
     }
@@ -1072,6 +1079,7 @@ struct Layout {
     std::vector<SnapDev> snaps;
     long long total_tiles = 0, total_src = 0, total_bins = 0, total_ipsi = 0, total_grid = 0;
     long long max_src = 0, max_tgt = 0, max_ipsi = 0, max_tiles = 0;
+    bool any_degenerate = false;  // some snapshot has a clamped axis (interpolation's quadrature variant)
     long long wg_total[3] = {0, 0, 0};
     long long max_wg[3] = {0, 0, 0};
     int tpb[3] = {256, 256, 256};
@@ -1216,6 +1224,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         d.post_norm = post_norm;
         L.max_src = std::max<long long>(L.max_src, j.n_src);
         L.max_tgt = std::max<long long>(L.max_tgt, j.tt->n_tgt);
+        L.any_degenerate = L.any_degenerate || p.degenerate != 0;
         L.max_ipsi = std::max(L.max_ipsi, nipsi);
         // algorithmic bytes of the grid stages: spread write, each pass
         // read + write of the live array, interp read of the final array
@@ -1406,8 +1415,12 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     }
     if ((stages & 4) && L.max_tgt) {
         const long long gx = blocks(L.max_tgt, 256);
-        launch_stage(tm, FV_STAGE_INTERP, k_interp<R, D, W>, sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap,
-                     (const cplx<R> *)grid, es_poly(W));
+        if (L.any_degenerate)
+            launch_stage(tm, FV_STAGE_INTERP, k_interp<R, D, W, true>, sgrid(gx), dim3(256), 0, st, snaps_dev,
+                         sgx(gx), n_snap, (const cplx<R> *)grid, es_poly(W));
+        else
+            launch_stage(tm, FV_STAGE_INTERP, k_interp<R, D, W, false>, sgrid(gx), dim3(256), 0, st, snaps_dev,
+                         sgx(gx), n_snap, (const cplx<R> *)grid, es_poly(W));
         tm->add(FV_STAGE_INTERP, L.sbytes[FV_STAGE_INTERP], 1);
     }
     FV_HIP(hipGetLastError());
