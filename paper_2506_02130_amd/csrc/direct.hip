@@ -74,17 +74,26 @@ __device__ __forceinline__ void check_strengths(const double *x, const double *b
     long long done = 0;
     if (((uintptr_t)x & 15) == 0 && ((uintptr_t)b & 15) == 0) {
         const long long n2 = n / 2;
-        for (long long i = t; i < n2; i += nth) {
-            const double2 v = ((const double2 *)x)[i];
-            double2 g = make_double2(1.0, 1.0);
-            if (b) {
-                g = ((const double2 *)b)[i];
-                bad += !isfinite(g.x);
-                bad += !isfinite(g.y);
+        // kChk pairs of 16-byte loads per thread in flight before any is used
+        constexpr int kChk = 4;
+        for (long long i0 = t; i0 < n2; i0 += kChk * (long long)nth) {
+            double2 v[kChk], g[kChk];
+#pragma unroll
+            for (int u = 0; u < kChk; ++u) {
+                const long long i = i0 + u * (long long)nth;
+                v[u] = make_double2(0.0, 0.0);
+                g[u] = make_double2(1.0, 1.0);
+                if (i < n2) {
+                    v[u] = ((const double2 *)x)[i];
+                    if (b) g[u] = ((const double2 *)b)[i];
+                }
             }
-            bad += !isfinite(v.x);
-            bad += !isfinite(v.y);
-            cm = fmax(cm, fmax(fabs(v.x * g.x), fabs(v.y * g.y)));
+#pragma unroll
+            for (int u = 0; u < kChk; ++u) {
+                bad += !isfinite(v[u].x) + !isfinite(v[u].y);
+                if (b) bad += !isfinite(g[u].x) + !isfinite(g[u].y);
+                cm = fmax(cm, fmax(fabs(v[u].x * g[u].x), fabs(v[u].y * g[u].y)));
+            }
         }
         done = 2 * n2;
     }
