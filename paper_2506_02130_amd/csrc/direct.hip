@@ -158,17 +158,20 @@ __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, 
     }
 }
 
-// The 256 threads fold the per-block partials (thread t takes blocks t,
-// t + 256, ...), then a butterfly across each wavefront's lanes and a pass
-// over the four wavefronts; every thread also helps gather the frequencies
-// and antenna positions.
-__global__ __launch_bounds__(256) void k_validate_reduce(const double *part, int nblk, const double *freq,
-                                                         int n_freq, const double *ant, int n_ant, double *out) {
-    __shared__ double wred[4][8];
+// The kValReduceThreads threads fold the per-block partials (thread t takes
+// blocks t, t + kValReduceThreads, ...), then a butterfly across each
+// wavefront's lanes and a pass over the wavefronts; every thread also helps
+// gather the frequencies and antenna positions.
+constexpr int kValReduceThreads = 1024;
+__global__ __launch_bounds__(kValReduceThreads) void k_validate_reduce(const double *part, int nblk,
+                                                                       const double *freq, int n_freq,
+                                                                       const double *ant, int n_ant, double *out) {
+    constexpr int NW = kValReduceThreads / 64;
+    __shared__ double wred[NW][8];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double v[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0, 0.0};
-#pragma unroll 4
-    for (int b = t; b < nblk; b += 256) {
+#pragma unroll 2
+    for (int b = t; b < nblk; b += kValReduceThreads) {
         const double *q = part + (size_t)kValStride * b;
         for (int k = 0; k < 6; k += 2) {
             v[k] = fmin(v[k], q[k]);
@@ -190,14 +193,14 @@ __global__ __launch_bounds__(256) void k_validate_reduce(const double *part, int
     __syncthreads();
     if (t < 8) {
         double r = wred[0][t];
-        for (int w = 1; w < 4; ++w) {
+        for (int w = 1; w < NW; ++w) {
             const double x = wred[w][t];
             r = t < 6 ? ((t & 1) ? fmax(r, x) : fmin(r, x)) : r + x;
         }
         out[t] = r;
     }
-    for (int i = t; i < n_freq; i += 256) out[8 + i] = freq[i];
-    for (int i = t; i < 3 * n_ant; i += 256) out[8 + n_freq + i] = ant[i];
+    for (int i = t; i < n_freq; i += kValReduceThreads) out[8 + i] = freq[i];
+    for (int i = t; i < 3 * n_ant; i += kValReduceThreads) out[8 + n_freq + i] = ant[i];
 }
 
 __global__ void k_zero_f64(double *p, long long n) {
@@ -253,7 +256,7 @@ void launch_validate(const double *src, int n_src, const double *flux, const dou
     const long long n_fs = n_src > 0 ? (long long)n_src * n_freq : 0;
     hipLaunchKernelGGL(k_validate, dim3(kSrcCheckBlocks), dim3(256), 0, st, n_src > 0 ? src : nullptr, n_src,
                        n_src > 0 ? flux : nullptr, n_src > 0 ? beam : nullptr, n_fs, validate_span(n_fs), part);
-    hipLaunchKernelGGL(k_validate_reduce, dim3(1), dim3(256), 0, st, (const double *)part, kSrcCheckBlocks, freq,
+    hipLaunchKernelGGL(k_validate_reduce, dim3(1), dim3(kValReduceThreads), 0, st, (const double *)part, kSrcCheckBlocks, freq,
                        n_freq, ant, n_ant, out);
     FV_HIP(hipGetLastError());
 }
