@@ -485,6 +485,9 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
 // x weights, real and imaginary parts in two accumulators).  Each lane stages
 // one record at a time in LDS with its 2 W kernel weights (evaluated once per
 // record and tile), then builds one A and one B element per step by lookup.
+// first-cell offset of the staged slots past a batch's last record
+constexpr int kFarCell = 1 << 20;
+
 template <typename R, int W>
 struct SpreadMfmaCfg {
     static constexpr int T = 16;            // tile edge
@@ -492,8 +495,7 @@ struct SpreadMfmaCfg {
     static constexpr int BX = T * WPB, BY = T;
     static constexpr int MAXROWS = 8;       // sub-bin rows per tile
     // staged records: l0x, l0y (int), cr, ci (R), W x weights, W y weights (R)
-    static constexpr int WAVE_BYTES =
-        64 * (2 * (int)sizeof(int) + (2 + 2 * W) * (int)sizeof(R)) + 2 * MAXROWS * (int)sizeof(int);
+    static constexpr int WAVE_BYTES = 64 * (2 * (int)sizeof(int) + (2 + 2 * W) * (int)sizeof(R));
     static_assert((T + W - 1 + kSubBin - 1) / kSubBin + 1 <= MAXROWS, "too many sub-bin rows per tile");
 };
 
@@ -517,7 +519,6 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
     int *sl0x = (int *)wbase, *sl0y = sl0x + 64;
     R *scr = (R *)(sl0y + 64), *sci = scr + 64;
     R *skx = sci + 64, *sky = skx + 64 * W;  // [64][W] kernel weights per staged record
-    int *rstart = (int *)(sky + 64 * W), *rpre = rstart + Cfg::MAXROWS;
     const R beta = (R)S.beta;
     const R inv_hw = (R)(2.0 / W);
     const Rec<R, 2> *rs = recs + S.src_base;
@@ -539,18 +540,30 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
         if (lane >= off) inc += y;
     }
     const int total = __shfl(inc, 63, 64);
-    if (lane < nrows) {
-        rstart[lane] = st;
-        rpre[lane] = inc - cnt;
+    // per sub-bin row (wave-uniform, in scalar registers): the window position
+    // of its first record, and the change from the previous row of the offset
+    // from window position to record index; rows past nrows start at total,
+    // beyond every position
+    int rpre[Cfg::MAXROWS], rdd[Cfg::MAXROWS];
+    int prev = 0;
+#pragma unroll
+    for (int r = 0; r < Cfg::MAXROWS; ++r) {
+        rpre[r] = readlane_i(inc - cnt, r);
+        const int del = readlane_i(st - (inc - cnt), r);
+        rdd[r] = del - prev;
+        prev = del;
     }
-    wave_sync();
     typename MA::T accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
     const int li = lane & 15, lk = lane >> 4;  // A row / B column index, record slot of the 4
-    // record e of the tile's neighbourhood (a position in its sub-bin rows)
+    // record e of the tile's neighbourhood (a position in its sub-bin rows):
+    // its row is the last one starting at or before e, and the row starts are
+    // nondecreasing, so the changes of the rows starting at or before e add up
+    // to that row's offset
     auto fetch = [&](int e) {
-        int row = 0;
-        while (row + 1 < nrows && rpre[row + 1] <= e) ++row;
-        return rs[rstart[row] + (e - rpre[row])];
+        int d = rdd[0];
+#pragma unroll
+        for (int r = 1; r < Cfg::MAXROWS; ++r) d += rpre[r] <= e ? rdd[r] : 0;
+        return rs[e + d];
     };
     // each batch's records are loaded while the previous batch is on the matrix cores
     Rec<R, 2> nxt;
@@ -587,25 +600,36 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
                 skx[lane * W + i] = wx[i];
                 sky[lane * W + i] = wy[i];
             }
+        } else {
+            // past the last record: a corner no tile cell reaches, so the
+            // steps below read in-bounds weights and contribute zero
+            sl0x[lane] = sl0y[lane] = kFarCell;
+            scr[lane] = sci[lane] = 0;
         }
         wave_sync();
         if (e + 64 < total) nxt = fetch(e + 64);
         const int nb = min(64, total - b0);
-#pragma unroll 2
-        for (int g = 0; g < nb; g += 4) {
-            const int rr = g + lk;
-            R a = 0, bre = 0, bim = 0;
-            if (rr < nb) {
+        // 16 records (4 matrix-core steps) at a time, with no branches, so that
+        // the steps' LDS reads are in flight together; slots past nb hold the
+        // corner above
+        for (int g0 = 0; g0 < nb; g0 += 16) {
+            R a[4], bre[4], bim[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int rr = g0 + 4 * u + lk;
                 const int dy = li - sl0y[rr], dx = li - sl0x[rr];
-                if ((unsigned)dy < (unsigned)W) a = sky[rr * W + dy];
-                if ((unsigned)dx < (unsigned)W) {
-                    const R kx = skx[rr * W + dx];
-                    bre = scr[rr] * kx;
-                    bim = sci[rr] * kx;
-                }
+                const bool iny = (unsigned)dy < (unsigned)W, inx = (unsigned)dx < (unsigned)W;
+                const R ky = sky[rr * W + (iny ? dy : 0)], kx = skx[rr * W + (inx ? dx : 0)];
+                a[u] = iny ? ky : (R)0;
+                const R k = inx ? kx : (R)0;
+                bre[u] = scr[rr] * k;
+                bim[u] = sci[rr] * k;
             }
-            accr = MA::step(a, bre, accr);
-            acci = MA::step(a, bim, acci);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                accr = MA::step(a[u], bre[u], accr);
+                acci = MA::step(a[u], bim[u], acci);
+            }
         }
         wave_sync();
     }
