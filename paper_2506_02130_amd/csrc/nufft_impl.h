@@ -555,6 +555,7 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
     }
     typename MA::T accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
     const int li = lane & 15, lk = lane >> 4;  // A row / B column index, record slot of the 4
+    const int lib = li * (int)sizeof(R);
     // record e of the tile's neighbourhood (a position in its sub-bin rows):
     // its row is the last one starting at or before e, and the row starts are
     // nondecreasing, so the changes of the rows starting at or before e add up
@@ -572,8 +573,9 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
         const int e = b0 + lane;
         if (e < total) {
             const Rec<R, 2> r = nxt;
-            sl0x[lane] = r.l0[0] - x0;
-            sl0y[lane] = r.l0[1] - y0;
+            // first-cell offsets from the tile corner, in bytes of R
+            sl0x[lane] = (r.l0[0] - x0) * (int)sizeof(R);
+            sl0y[lane] = (r.l0[1] - y0) * (int)sizeof(R);
             scr[lane] = r.cr;
             sci[lane] = r.ci;
             R wx[W], wy[W];
@@ -603,7 +605,7 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
         } else {
             // past the last record: a corner no tile cell reaches, so the
             // steps below read in-bounds weights and contribute zero
-            sl0x[lane] = sl0y[lane] = kFarCell;
+            sl0x[lane] = sl0y[lane] = kFarCell * (int)sizeof(R);
             scr[lane] = sci[lane] = 0;
         }
         wave_sync();
@@ -617,9 +619,11 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int g
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int rr = g0 + 4 * u + lk;
-                const int dy = li - sl0y[rr], dx = li - sl0x[rr];
-                const bool iny = (unsigned)dy < (unsigned)W, inx = (unsigned)dx < (unsigned)W;
-                const R ky = sky[rr * W + (iny ? dy : 0)], kx = skx[rr * W + (inx ? dx : 0)];
+                constexpr unsigned kSpan = W * sizeof(R);
+                const int dy = lib - sl0y[rr], dx = lib - sl0x[rr];  // bytes
+                const bool iny = (unsigned)dy < kSpan, inx = (unsigned)dx < kSpan;
+                const R ky = *(const R *)((const char *)(sky + rr * W) + (iny ? dy : 0));
+                const R kx = *(const R *)((const char *)(skx + rr * W) + (inx ? dx : 0));
                 a[u] = iny ? ky : (R)0;
                 const R k = inx ? kx : (R)0;
                 bre[u] = scr[rr] * k;
