@@ -485,9 +485,6 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
 // x weights, real and imaginary parts in two accumulators).  Each lane stages
 // one record at a time in LDS with its 2 W kernel weights (evaluated once per
 // record and tile), then builds one A and one B element per step by lookup.
-// first-cell offset of the staged slots past a batch's last record
-constexpr int kFarCell = 1 << 20;
-
 template <typename R, int W>
 struct SpreadMfmaCfg {
     static constexpr int T = 16;            // tile edge
@@ -498,6 +495,8 @@ struct SpreadMfmaCfg {
     static constexpr int WAVE_BYTES = 64 * (2 * (int)sizeof(int) + (2 + 2 * W) * (int)sizeof(R));
     static_assert((T + W - 1 + kSubBin - 1) / kSubBin + 1 <= MAXROWS, "too many sub-bin rows per tile");
 };
+// first-cell offset of the staged slots past a batch's last record
+constexpr int kFarCell = 1 << 20;
 
 template <typename R, int W>
 __global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int gx, int n_snap, const int *bins,
