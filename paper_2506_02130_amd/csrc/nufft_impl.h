@@ -50,12 +50,13 @@ struct Rec {
 
 template <int D>
 struct TileShape;
-// Spread tiles: a block of 4 wavefronts covers X x Y x Z cells; each
-// wavefront owns an 8-column slice and walks it in 8 x 8 (x TZ) sub-tiles, one
-// cell (x TZ slices) per lane.
+// Spread tiles: a workgroup covers X x Y x Z cells.  In 3-D each of its 4
+// wavefronts owns an 8-column slice and walks it in 8 x 8 (x TZ) sub-tiles, one
+// cell (x TZ slices) per lane; in 2-D its one wavefront owns one matrix-core
+// tile.
 template <>
 struct TileShape<2> {
-    static constexpr int X = 64, Y = 16, Z = 1;  // 4 matrix-core tiles of 16 x 16
+    static constexpr int X = 16, Y = 16, Z = 1;  // 1 matrix-core tile of 16 x 16
 };
 template <>
 struct TileShape<3> {
@@ -488,7 +489,9 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
 template <typename R, int W>
 struct SpreadMfmaCfg {
     static constexpr int T = 16;            // tile edge
-    static constexpr int WPB = 4;           // wavefronts (tiles) per block, along x
+    // one wavefront per workgroup: tiles differ widely in record count, and a
+    // workgroup's LDS stays held until its slowest wavefront ends
+    static constexpr int WPB = 1;           // wavefronts (tiles) per block, along x
     static constexpr int BX = T * WPB, BY = T;
     static constexpr int MAXROWS = 8;       // sub-bin rows per tile
     // staged records: l0x, l0y (int), cr, ci (R), W x weights, W y weights (R)
@@ -499,9 +502,11 @@ struct SpreadMfmaCfg {
 constexpr int kFarCell = 1 << 20;
 
 template <typename R, int W>
-__global__ __launch_bounds__(256) void k_spread_mfma(const SnapDev *snaps, int gx, int n_snap, const int *bins,
-                                                     const Rec<R, 2> *recs, const R *ipsi, cplx<R> *grid,
-                                                     EsPoly ep) {
+__global__ __launch_bounds__(64 * SpreadMfmaCfg<R, W>::WPB) void k_spread_mfma(const SnapDev *snaps, int gx,
+                                                                             int n_snap, const int *bins,
+                                                                             const Rec<R, 2> *recs,
+                                                                             const R *ipsi, cplx<R> *grid,
+                                                                             EsPoly ep) {
     using Cfg = SpreadMfmaCfg<R, W>;
     using MA = MfmaAcc<R>;
     extern __shared__ __align__(16) char smem[];
