@@ -502,7 +502,7 @@ struct SpreadMfmaCfg {
 constexpr int kFarCell = 1 << 20;
 
 template <typename R, int W>
-__global__ __launch_bounds__(64 * SpreadMfmaCfg<R, W>::WPB) void k_spread_mfma(const SnapDev *snaps, int gx,
+__global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma(const SnapDev *snaps, int gx,
                                                                              int n_snap, const int *bins,
                                                                              const Rec<R, 2> *recs,
                                                                              const R *ipsi, cplx<R> *grid,
