@@ -91,6 +91,13 @@ typedef enum {
 #define FV_TIMING_ONE_STAGE 0x4000u /* with FV_TIMING or FV_TIMING_ACCUM: only the stage in flag bits
                                       16-19 (FV_TIMING_STAGE) records events, two per launch of it; the
                                       other stages' times stay 0 */
+#define FV_DETERMINISTIC   0x8000u /* NUFFT: bitwise reproducible output.  The type-3 spread adds each
+                                      tile's records in an order fixed by the sources' indices (a stable
+                                      rank inside every sort bin, one extra pass over the records)
+                                      instead of the order in which atomic counters returned; the same
+                                      problem then gives the same bits on every call, alone or among
+                                      other requests of the serving loop.  The type-1 path and the direct
+                                      sums are reproducible without it. */
 #define FV_TIMING_STAGE(s) (FV_TIMING_ONE_STAGE | ((unsigned)(s) << 16))  /* s: an FV_STAGE_* index */
 #define FV_TIMING_STAGE_OF(flags) ((int)(((flags) >> 16) & 0xFu))
 

@@ -32,6 +32,7 @@ AUTOTUNE = 0x400
 GRAPH = 0x800
 NO_LATTICE = 0x1000
 TIMING_ACCUM = 0x2000  # stage events without waiting; sums from Context.stage_times()
+DETERMINISTIC = 0x8000  # bitwise reproducible type-3 spread order
 TIMING_ONE_STAGE = 0x4000  # with TIMING or TIMING_ACCUM: only one stage (flag bits 16-19) records events
 STAGES = ("sort", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "other")
 

@@ -110,7 +110,7 @@ void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevI
 // Kernel family of a group of NUFFT jobs.
 struct NufftGroupKey {
     int dim = 2, prec = 32, w = 8, fold_axis = -1;
-    unsigned flags = 0;  // FV_AUTOTUNE | FV_GRAPH of the problem
+    unsigned flags = 0;  // FV_AUTOTUNE | FV_GRAPH | FV_DETERMINISTIC of the problem
     bool operator<(const NufftGroupKey &o) const {
         return std::tie(dim, prec, w, flags) < std::tie(o.dim, o.prec, o.w, o.flags);
     }

@@ -255,6 +255,7 @@ struct ExecOpts {
     TuneCache *tunes = nullptr;
     GraphCache *graphs = nullptr;
     size_t cap = 0;          // > 0: refuse (set *too_big) when the workspace exceeds cap bytes
+    bool det = false;        // deterministic record order in the spread (FV_DETERMINISTIC)
 };
 
 // Lattice of a coplanar array (paper section 2.2.1): every antenna offset
@@ -319,7 +320,7 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
                      DevCache &cache, hipStream_t s, StageTimer *timer = nullptr, const ExecOpts *opts = nullptr,
                      bool *too_big = nullptr);
 // Workspace bytes nufft_execute would take for these jobs.
-size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w);
+size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, bool det = false);
 
 void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B,
                    int w, const double *qn_dev, const int *perm_dev, TargetTable &tt, hipStream_t s);

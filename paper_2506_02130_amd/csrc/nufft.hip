@@ -13,8 +13,8 @@ PipeFn pick(int dim, int prec_bits, int w) {
 
 }  // namespace
 
-size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w) {
-    Layout L = make_layout(jobs, dim, prec_bits, w, Tuning::defaults());
+size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, bool det) {
+    Layout L = make_layout(jobs, dim, prec_bits, w, Tuning::defaults(), det);
     return layout_bytes(L, dim, prec_bits, (int)jobs.size());
 }
 
@@ -61,6 +61,10 @@ Prepared prepare_layout(Layout &&layout, const std::vector<SnapJob> &jobs, int d
         P.B.src_ord = (double *)arena.take(L.order_src * 24);
         P.B.orders = (OrderGroup *)arena.take(ng * sizeof(OrderGroup));
     }
+    if (L.det) {
+        P.B.recs_tmp = arena.take(std::max<long long>(L.total_src, 1) * rec_bytes(dim, prec_bits));
+        P.B.srcid = (int *)arena.take(std::max<long long>(L.total_src, 1) * 4);
+    }
     // the tables go up from pinned staging; the staging is reused only after
     // this copy has completed (PinnedBuf::get waits for it)
     const size_t tb = n * sizeof(SnapDev), ob = ng * sizeof(OrderGroup);
@@ -74,8 +78,9 @@ Prepared prepare_layout(Layout &&layout, const std::vector<SnapJob> &jobs, int d
 }
 
 Prepared prepare(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, Arena &arena, DevCache &cache,
-                 hipStream_t st, const Tuning &tune) {
-    return prepare_layout(make_layout(jobs, dim, prec_bits, w, tune), jobs, dim, prec_bits, w, arena, cache, st);
+                 hipStream_t st, const Tuning &tune, bool det = false) {
+    return prepare_layout(make_layout(jobs, dim, prec_bits, w, tune, det), jobs, dim, prec_bits, w, arena, cache,
+                          st);
 }
 
 void fetch_c128(const void *dev, long long n, int prec_bits, double *host, hipStream_t st) {
@@ -172,12 +177,12 @@ uint64_t graph_key(const Prepared &P, int n, int dim, int prec_bits, int w) {
                         L.max_wg[2], L.max_tiles, L.max_src, L.max_tgt, L.max_ipsi, L.total_bins,
                         (long long)L.orders.size(), L.max_order_src, L.order_counts, (long long)L.tpb[0],
                         (long long)L.tpb[1], (long long)L.tpb[2], (long long)L.fft_lds[0], (long long)L.fft_lds[1],
-                        (long long)L.fft_lds[2]})
+                        (long long)L.fft_lds[2], (long long)L.det})
         h = mix(h, (uint64_t)v);
     for (const void *p : {(const void *)P.B.snaps, (const void *)P.B.bins, (const void *)P.B.rank,
                           (const void *)P.B.recs, (const void *)P.B.ipsi, (const void *)P.B.grid,
                           (const void *)P.B.perm, (const void *)P.B.order_counts, (const void *)P.B.src_ord,
-                          (const void *)P.B.orders})
+                          (const void *)P.B.orders, (const void *)P.B.recs_tmp, (const void *)P.B.srcid})
         h = mix(h, (uint64_t)(uintptr_t)p);
     return h;
 }
@@ -189,7 +194,8 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
     if (jobs.empty()) return 0.0;
     // the workspace size does not depend on the launch shape
     Tuning tune = Tuning::defaults();
-    Layout layout = make_layout(jobs, dim, prec_bits, w, tune);
+    const bool det = opts && opts->det;
+    Layout layout = make_layout(jobs, dim, prec_bits, w, tune, det);
     if (opts && opts->cap && too_big && layout_bytes(layout, dim, prec_bits, (int)jobs.size()) > opts->cap) {
         *too_big = true;
         return 0.0;
@@ -202,7 +208,7 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
             opts->tunes->put(key, tune);
             have = true;
         }
-        if (have) layout = make_layout(jobs, dim, prec_bits, w, tune);
+        if (have) layout = make_layout(jobs, dim, prec_bits, w, tune, det);
     }
     Prepared P = prepare_layout(std::move(layout), jobs, dim, prec_bits, w, arena, cache, st);
     const int n = (int)jobs.size();

@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_order_place(const SnapDev *snaps, const
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_scatter(const SnapDev *snaps, int gx, int n_snap, const int *perm,
                                                  const double *src_ord, const int *bins, const int *rank,
-                                                 Rec<R, D> *recs) {
+                                                 Rec<R, D> *recs, int *srcid) {
     int bx, sy;
     if (!snap_block(gx, n_snap, bx, sy)) return;
     const SnapDev &S = snaps[sy];
@@ -294,6 +294,40 @@ __global__ __launch_bounds__(256) void k_scatter(const SnapDev *snaps, int gx, i
     r.cr = (R)(c * cs);
     r.ci = (R)(c * sn);
     recs[S.src_base + pos] = r;
+    if (srcid) srcid[S.src_base + pos] = j;
+}
+
+// Deterministic mode: the scatter's ranks follow the order of returning
+// atomics, so the records of one sub-bin land in an order that changes from
+// run to run.  Here every record moves to its stable place in its sub-bin:
+// the number of records of the same sub-bin with a smaller source index.
+// One thread per record position; the sub-bin is found by binary search in
+// the scanned counts, and the rank by a pass over the sub-bin's source
+// indices (sub-bins hold few records).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_stable(const SnapDev *snaps, int gx, int n_snap, const int *bins,
+                                                const int *srcid, const Rec<R, D> *in, Rec<R, D> *out) {
+    int bx, sy;
+    if (!snap_block(gx, n_snap, bx, sy)) return;
+    const SnapDev &S = snaps[sy];
+    const int pos = bx * 256 + threadIdx.x;
+    if (pos >= S.n_src) return;
+    long long nb = 1;
+    for (int a = 0; a < D; ++a) nb *= S.nsb[a];
+    const int *b = bins + S.bin_base;
+    // last sub-bin whose start is at or before pos
+    long long lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const long long mid = (lo + hi + 1) >> 1;
+        if (b[mid] <= pos) lo = mid;
+        else hi = mid - 1;
+    }
+    const int st = b[lo], en = b[lo + 1];
+    const int *ids = srcid + S.src_base;
+    const int me = ids[pos];
+    int r = 0;
+    for (int q = st; q < en; ++q) r += ids[q] < me;
+    out[S.src_base + st + r] = in[S.src_base + pos];
 }
 
 // 1/psi2hat(m) for m = l - n1/2, psi2hat(m) = alpha2 phihat(alpha2 m), alpha2 = w pi / n2.
@@ -1121,6 +1155,7 @@ struct Layout {
     // shared spatial orders, one per source list read by several snapshots
     std::vector<OrderGroup> orders;
     long long order_src = 0, order_counts = 0, max_order_src = 0;
+    bool det = false;  // deterministic record order (stable ranks inside each sub-bin)
 };
 
 // Device buffers of one pipeline run.
@@ -1131,6 +1166,8 @@ struct Bufs {
     int *perm = nullptr, *order_counts = nullptr;  // null unless Layout::orders is non-empty
     double *src_ord = nullptr;                     // source directions in the order perm
     OrderGroup *orders = nullptr;                  // device copy of Layout::orders
+    void *recs_tmp = nullptr;                      // deterministic mode: records in scatter order
+    int *srcid = nullptr;                          // deterministic mode: source index per scatter position
 };
 
 inline int env_int(const char *name, int dflt) {
@@ -1143,8 +1180,10 @@ inline size_t rec_bytes(int dim, int prec_bits) {
     return dim == 2 ? sizeof(Rec<double, 2>) : sizeof(Rec<double, 3>);
 }
 
-inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, const Tuning &tune) {
+inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, const Tuning &tune,
+                          bool det = false) {
     Layout L;
+    L.det = det;
     const size_t csz = prec_bits == 32 ? 8 : 16;
     const int T[3] = {dim == 2 ? TileShape<2>::X : TileShape<3>::X, dim == 2 ? TileShape<2>::Y : TileShape<3>::Y,
                       dim == 2 ? 1 : TileShape<3>::Z};
@@ -1321,7 +1360,8 @@ inline size_t layout_bytes(const Layout &L, int dim, int prec_bits, int n_snap) 
     return al(n_snap * sizeof(SnapDev)) + al(L.total_bins * 4) + al(L.total_src * 4) +
            al(L.total_src * rec_bytes(dim, prec_bits)) + al(L.total_ipsi * rsz) + al(L.total_grid * csz) +
            al(L.order_src * 4) + al(L.order_counts * 4) + al(L.order_src * 24) +
-           al(L.orders.size() * sizeof(OrderGroup)) + 4096;
+           al(L.orders.size() * sizeof(OrderGroup)) +
+           (L.det ? al(L.total_src * rec_bytes(dim, prec_bits)) + al(L.total_src * 4) : 0) + 4096;
 }
 
 // Snapshot-per-XCD launches when the snapshots fill the 8 XCDs evenly enough
@@ -1397,7 +1437,13 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     if (L.max_src) {
         const long long gx = blocks(L.max_src, 256);
         hipLaunchKernelGGL((k_scatter<R, D>), sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap, perm,
-                           (const double *)B.src_ord, (const int *)bins, (const int *)rank, recs);
+                           (const double *)B.src_ord, (const int *)bins, (const int *)rank,
+                           L.det ? (Rec<R, D> *)B.recs_tmp : recs, L.det ? B.srcid : nullptr);
+        if (L.det) {
+            hipLaunchKernelGGL((k_stable<R, D>), sgrid(gx), dim3(256), 0, st, snaps_dev, sgx(gx), n_snap,
+                               (const int *)bins, (const int *)B.srcid, (const Rec<R, D> *)B.recs_tmp, recs);
+            ++sort_launches;
+        }
     }
     tm->end(st);
     tm->add(FV_STAGE_SORT, L.sbytes[FV_STAGE_SORT], sort_launches);

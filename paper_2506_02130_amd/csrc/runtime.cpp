@@ -447,7 +447,7 @@ NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in,
     const long long n_pairs = (long long)p.n_ant * (p.n_ant + 1) / 2;
     NufftGroupKey k;
     k.dim = choose_dim(p.ant_enu, p.n_ant, p.eps, p.freq_hz, n_freq, p.flags);
-    k.flags = p.flags & (FV_AUTOTUNE | FV_GRAPH);
+    k.flags = p.flags & (FV_AUTOTUNE | FV_GRAPH | FV_DETERMINISTIC);
     k.prec = choose_prec(p.eps, p.flags);
     const bool fold = !(p.flags & FV_NO_FOLD);
     GeomPlan g = ctx_geometry(ctx, p.ant_enu, p.n_ant, k.dim, p.eps, in.s_c, in.S, fold);
@@ -494,6 +494,7 @@ double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, c
     ExecOpts opts;
     opts.autotune = (k.flags & FV_AUTOTUNE) != 0;
     opts.graph = (k.flags & FV_GRAPH) != 0;
+    opts.det = (k.flags & FV_DETERMINISTIC) != 0;
     opts.tunes = &ctx->tunes;
     opts.graphs = &slot.graphs;
     const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
@@ -506,7 +507,7 @@ double execute_jobs(fv_ctx *ctx, Slot &slot, const std::vector<SnapJob> &jobs, c
     opts.cap = 0;
     std::vector<size_t> each(jobs.size());
     for (size_t i = 0; i < jobs.size(); ++i)
-        each[i] = nufft_workspace_bytes(std::vector<SnapJob>{jobs[i]}, k.dim, k.prec, k.w);
+        each[i] = nufft_workspace_bytes(std::vector<SnapJob>{jobs[i]}, k.dim, k.prec, k.w, opts.det);
     double bytes = 0.0;
     size_t i0 = 0;
     while (i0 < jobs.size()) {

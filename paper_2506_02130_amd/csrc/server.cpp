@@ -69,7 +69,8 @@ size_t request_footprint(fv_ctx *ctx, const fv_problem &p) {
         j.src = p.src_lmn;
         j.n_src = p.n_src;
         j.tt = &tt;
-        const size_t b = nufft_workspace_bytes(std::vector<SnapJob>{j}, dim, prec, g.w);
+        const size_t b = nufft_workspace_bytes(std::vector<SnapJob>{j}, dim, prec, g.w,
+                                               (p.flags & FV_DETERMINISTIC) != 0);
         ws += b;
         ws_max = std::max(ws_max, b);
     }

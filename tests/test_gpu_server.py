@@ -51,6 +51,27 @@ def test_mixed_requests_match_solo_runs_and_oracle(gpu_lib):
         c.server_stop()
 
 
+def test_deterministic_mix_is_bitwise_equal_to_solo(gpu_lib):
+    """With FV_DETERMINISTIC every request of the mix (type-3 forced where the
+    array is a lattice) gives the same bits in the serving mix as alone."""
+    fv = gpu_lib
+    probs = [(p, e, f | fv.DETERMINISTIC | (fv.NO_LATTICE if i % 2 == 0 else 0))
+             for i, (p, e, f) in enumerate(_mix())]
+    with fv.Context(0) as c:
+        hps = [fv.HostProblem.of(p, eps=e, flags=f) for p, e, f in probs]
+        solo = [c.simulate_problem(h) for h in hps]
+        c.server_start(3)
+        outs = [_out(p) for p, _, _ in probs]
+        tickets = [c.submit(h, o) for h, o in zip(hps, outs)]
+        for (p, e, f), t, o, s in zip(probs, tickets, outs, solo):
+            st, _ = c.wait(t)
+            assert st == 0, (p.name, st)
+            assert np.array_equal(_c(o), s), p.name
+            if p.n_src:
+                assert oracle.rel_l2(s, oracle.direct_problem(p)) <= e, p.name
+        c.server_stop()
+
+
 def test_budget_admission_and_oversize_rejection(gpu_lib):
     fv = gpu_lib
     small = [synth.small_problem(90 + k, n_ant=20, n_src=800, n_freq=2, hex_layout=True) for k in range(5)]
