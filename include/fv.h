@@ -273,6 +273,25 @@ fv_status fv_simulate_polar(fv_ctx *ctx, const fv_polar *q, double *vis, void *s
 fv_status fv_simulate_basis(fv_ctx *ctx, const fv_problem *p, int n_basis, double *vis, void *stream,
                             fv_report *rep);
 
+/* Allocation-free variant of fv_simulate_dev for the matrix-core direct form
+ * (flags must select FV_METHOD_MFMA), for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Arrays as for fv_simulate_dev (device pointers; vis
+ * [n_freq][n_pairs] complex128, 16-byte aligned); it runs on the calling
+ * thread's current HIP device and enqueues on `stream` (a hipStream_t of that
+ * device; NULL = the null stream), blocking once for the planning scalars.
+ * It needs no context and makes no device or pinned allocation: every buffer
+ * beyond the inputs and the output (the input check's partials and scalars,
+ * the Z chunk, the strengths, the partial tiles) lives in one 64 MiB array in
+ * the library's device memory, one copy per device, held until the process
+ * ends.  Limits: n_ant <= 1024 and n_freq <= 1024, and the partial tiles of
+ * the pair triangle must fit the array (sources are processed in chunks that
+ * fit); beyond them FV_EINVAL.  Every call on a device shares that device's
+ * array, which keeps the last call's contents: calls that overlap on one
+ * device (other streams or threads) race.  Errors as for fv_simulate_dev;
+ * FV_EINVAL also for any other method. */
+fv_status fv_simulate_mfma_noalloc(const fv_problem *p, double *vis, void *stream);
+
 /* Serving loop: a worker thread admits submitted requests while HBM (the
  * context budget) and one of max_slots slots are free, and runs admitted
  * requests concurrently on per-slot streams.  Host buffers, which must stay

@@ -48,7 +48,7 @@ def timing_stage(stage) -> int:
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
                "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar", "fv_simulate_basis",
-               "fv_stage_times")
+               "fv_stage_times", "fv_simulate_mfma_noalloc")
 
 
 class FvError(RuntimeError):
@@ -131,6 +131,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_simulate_polar.argtypes = [vp, P(Polar), vp, vp, P(Report)]
     lib.fv_simulate_basis.argtypes = [vp, P(Problem), ctypes.c_int, vp, vp, P(Report)]
     lib.fv_stage_times.argtypes = [vp, dp, P(ctypes.c_int), P(ctypes.c_int)]
+    lib.fv_simulate_mfma_noalloc.argtypes = [P(Problem), vp, vp]
+    lib.fv_simulate_mfma_noalloc.restype = ctypes.c_int
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
@@ -147,6 +149,33 @@ def _check(status: int):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def simulate_mfma_noalloc(ant_enu, src_lmn, freq_hz, flux, beam, vis, eps: float = 1e-6, flags: int = 0,
+                          stream=None) -> None:
+    """The allocation-free matrix-core direct sum (fv_simulate_mfma_noalloc):
+    torch float64 device tensors as for Context.simulate_dev, on the current
+    device; FV_METHOD_MFMA is added to ``flags``.  No context is needed."""
+    import torch
+    for name, t in (("ant_enu", ant_enu), ("src_lmn", src_lmn), ("freq_hz", freq_hz), ("flux", flux),
+                    ("vis", vis)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if beam is not None and not (beam.is_cuda and beam.dtype == torch.float64 and beam.is_contiguous()):
+        raise ValueError("beam must be a contiguous float64 device tensor")
+    n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
+    sizes = (("ant_enu", ant_enu, 3 * n_ant), ("src_lmn", src_lmn, 3 * n_src), ("freq_hz", freq_hz, n_freq),
+             ("flux", flux, n_freq * n_src), ("vis", vis, 2 * n_freq * n_ant * (n_ant + 1) // 2))
+    if beam is not None:
+        sizes += (("beam", beam, n_freq * n_src),)
+    for name, t, want in sizes:
+        if t.numel() != want:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {want}")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    c = Problem(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
+                freq_hz.data_ptr(), flux.data_ptr() if n_src else None,
+                None if beam is None else beam.data_ptr(), float(eps), int(flags) | METHOD_MFMA)
+    _check(_lib.fv_simulate_mfma_noalloc(ctypes.byref(c), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream)))
 
 
 class HostProblem:

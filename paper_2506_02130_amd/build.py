@@ -30,7 +30,7 @@ HOST_ONLY_FLAGS = ["-ffp-contract=off"]
 SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp", "server.cpp", "tune.cpp", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip",
            "nufft_f64_2d.hip", "nufft_f64_3d.hip", "direct.hip", "zz.hip", "lattice.hip", "frontend.hip",
            "drift.cpp", "beams.hip", "beams.cpp", "polar.hip", "polar.cpp",
-           "basis.hip", "basis.cpp"]
+           "basis.hip", "basis.cpp", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

@@ -34,6 +34,7 @@ struct Error {
     std::string msg;
 };
 [[noreturn]] void fail(fv_status code, const std::string &msg);
+void set_last_error(const std::string &msg);  // the message fv_last_error() returns on this thread
 void hip_check(hipError_t e, const char *what);
 #define FV_HIP(call) ::fv::hip_check((call), #call)
 
