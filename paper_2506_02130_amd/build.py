@@ -30,7 +30,7 @@ HOST_ONLY_FLAGS = ["-ffp-contract=off"]
 SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp", "server.cpp", "tune.cpp", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip",
            "nufft_f64_2d.hip", "nufft_f64_3d.hip", "direct.hip", "zz.hip", "lattice.hip", "frontend.hip",
            "drift.cpp", "beams.hip", "beams.cpp", "polar.hip", "polar.cpp",
-           "basis.hip", "basis.cpp", "noalloc.hip"]
+           "basis.hip", "basis.cpp", "noalloc.hip", "fft_reg.hip", "fft_reg_cols.hip"]
 
 
 def _compile(src: str) -> str:
@@ -57,8 +57,18 @@ def _compile(src: str) -> str:
 
 def build(jobs: int = 8, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    # the FFT plan tables are generated source (committed); regenerated when
+    # the generator is newer than them (the search takes about a minute)
+    gen = os.path.join(CSRC, "gen_fft_plans.py")
+    incs = [os.path.join(CSRC, f"fft_plans_{k}.inc") for k in ("rows", "cols")]
+    if any(not os.path.exists(f) or os.path.getmtime(f) < os.path.getmtime(gen) for f in incs):
+        r = subprocess.run([sys.executable, gen], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"FFT plan generation failed\n{r.stdout}\n{r.stderr}")
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        order = sorted(SOURCES, key=lambda f: 0 if f.startswith("fft_reg") else 1)
+        done = dict(zip(order, ex.map(_compile, order)))
+        objs = [done[f] for f in SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lpthread"]

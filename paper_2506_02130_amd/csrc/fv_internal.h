@@ -57,6 +57,7 @@ struct SnapDev {
     long long bufA, bufB;            // element offsets of the two grid regions
     long long ipsi_base;             // offset of the 1/psi2hat tables (n1[0] | n1[1] | n1[2])
     long long wg_base[3];            // first workgroup of each FFT pass
+    long long reg_base[3];           // first workgroup of each planned FFT pass (fft_reg.h)
     long long order_base;            // offset of this source list's shared order, or -1
     const double *src;               // [n_src][3]
     const double *flux;              // [n_src] this frequency
@@ -321,6 +322,16 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
                      DevCache &cache, hipStream_t s, StageTimer *timer = nullptr, const ExecOpts *opts = nullptr,
                      bool *too_big = nullptr);
 // Workspace bytes nufft_execute would take for these jobs.
+// Planned FP32 FFT passes (fft_reg.hip): whether line length L has a
+// compile-time plan, its lines per workgroup and LDS bytes; and the launches
+// of the row pass (x) and of the column passes (y, z) over every snapshot.
+bool fft_reg_info(int L, bool cols, int *lines_per_wg, size_t *lds_bytes);
+bool fft_reg_info_rows(int L, int *lines_per_wg, size_t *lds_bytes);
+bool fft_reg_info_cols(int L, int *lines_per_wg, size_t *lds_bytes);
+void launch_fft_reg_rows(const SnapDev *snaps, int n_snap, int a, void *grid, long long n_wg, size_t lds,
+                         hipStream_t st, hipEvent_t ea, hipEvent_t eb);
+void launch_fft_reg_cols(const SnapDev *snaps, int n_snap, int a, void *grid, long long n_wg, size_t lds,
+                         hipStream_t st, hipEvent_t ea, hipEvent_t eb);
 size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, bool det = false);
 
 void build_targets(const double *ant_dev, int n_ant, int dim, int fold_axis, const double *b_c, const double *B,

@@ -177,7 +177,9 @@ uint64_t graph_key(const Prepared &P, int n, int dim, int prec_bits, int w) {
                         L.max_wg[2], L.max_tiles, L.max_src, L.max_tgt, L.max_ipsi, L.total_bins,
                         (long long)L.orders.size(), L.max_order_src, L.order_counts, (long long)L.tpb[0],
                         (long long)L.tpb[1], (long long)L.tpb[2], (long long)L.fft_lds[0], (long long)L.fft_lds[1],
-                        (long long)L.fft_lds[2], (long long)L.det})
+                        (long long)L.fft_lds[2], (long long)L.det, (long long)L.reg[0], (long long)L.reg[1],
+                        (long long)L.reg[2], L.reg_wg[0], L.reg_wg[1], L.reg_wg[2], (long long)L.reg_lds[0],
+                        (long long)L.reg_lds[1], (long long)L.reg_lds[2]})
         h = mix(h, (uint64_t)v);
     for (const void *p : {(const void *)P.B.snaps, (const void *)P.B.bins, (const void *)P.B.rank,
                           (const void *)P.B.recs, (const void *)P.B.ipsi, (const void *)P.B.grid,

@@ -1156,6 +1156,10 @@ struct Layout {
     std::vector<OrderGroup> orders;
     long long order_src = 0, order_counts = 0, max_order_src = 0;
     bool det = false;  // deterministic record order (stable ranks inside each sub-bin)
+    // planned FFT passes (FP32, every snapshot's line length has a plan)
+    bool reg[3] = {false, false, false};
+    long long reg_wg[3] = {0, 0, 0};
+    size_t reg_lds[3] = {0, 0, 0};
 };
 
 // Device buffers of one pipeline run.
@@ -1328,6 +1332,33 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         }
         L.snaps.push_back(d);
     }
+    // the planned FFT kernels take a pass when every snapshot's line length
+    // has a plan (FP32 grids; FV_FFT_GENERAL=1 keeps the general kernel)
+    static const bool general_only = env_int("FV_FFT_GENERAL", 0) != 0;
+    for (int a = 0; a < dim && prec_bits == 32 && !general_only && !jobs.empty(); ++a) {
+        bool ok = true;
+        long long wg = 0;
+        size_t lds = 0;
+        for (size_t s = 0; s < jobs.size(); ++s) {
+            const SnapJob &j = jobs[s];
+            int nl = 0;
+            size_t b = 0;
+            if (!fft_reg_info(j.plan.n1[a], a > 0, &nl, &b)) {
+                ok = false;
+                break;
+            }
+            long long F = 1, Sl = 1;
+            for (int c = 0; c < a; ++c) F *= j.plan.M[c];
+            for (int c = a + 1; c < dim; ++c) Sl *= j.plan.n1[c];
+            const long long n = a == 0 ? (Sl + nl - 1) / nl : Sl * ((F + nl - 1) / nl);
+            L.snaps[s].reg_base[a] = wg;  // workgroups of the pass are numbered snapshot by snapshot
+            wg += n;
+            lds = std::max(lds, b);
+        }
+        L.reg[a] = ok;
+        L.reg_wg[a] = ok ? wg : 0;
+        L.reg_lds[a] = ok ? lds : 0;
+    }
     // a shared source order pays off when several snapshots bin the same list
     std::map<std::pair<const double *, int>, std::vector<int>> lists;
     for (int i = 0; i < (int)jobs.size(); ++i)
@@ -1468,9 +1499,21 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     }
     if (stages & 2)
     for (int a = 0; a < D; ++a) {
+        const int fs = FV_STAGE_FFT_X + a;
+        if constexpr (std::is_same<R, float>::value) {
+            if (L.reg[a]) {
+                hipEvent_t ea = nullptr, eb = nullptr;
+                tm->kernel_events(fs, &ea, &eb);
+                if (a == 0)
+                    launch_fft_reg_rows(snaps_dev, n_snap, a, grid, L.reg_wg[a], L.reg_lds[a], st, ea, eb);
+                else
+                    launch_fft_reg_cols(snaps_dev, n_snap, a, grid, L.reg_wg[a], L.reg_lds[a], st, ea, eb);
+                tm->add(fs, L.sbytes[fs], 1);
+                continue;
+            }
+        }
         // a multiple of 8 workgroups along x, so that the XCD of (x, y) is x mod 8
         const dim3 nb((unsigned)((L.max_wg[a] + 7) / 8 * 8), (unsigned)n_snap);
-        const int fs = FV_STAGE_FFT_X + a;
         switch (L.tpb[a]) {
             case 128:
                 ensure_lds((const void *)k_fft<R, 128>, L.fft_lds[a]);
