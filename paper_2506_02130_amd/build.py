@@ -30,7 +30,8 @@ HOST_ONLY_FLAGS = ["-ffp-contract=off"]
 SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp", "server.cpp", "tune.cpp", "nufft.hip", "nufft_f32_2d.hip", "nufft_f32_3d.hip",
            "nufft_f64_2d.hip", "nufft_f64_3d.hip", "direct.hip", "zz.hip", "lattice.hip", "frontend.hip",
            "drift.cpp", "beams.hip", "beams.cpp", "polar.hip", "polar.cpp",
-           "basis.hip", "basis.cpp", "noalloc.hip", "fft_reg.hip", "fft_reg_cols.hip"]
+           "basis.hip", "basis.cpp", "noalloc.hip", "fft_reg.hip", "fft_reg_cols.hip",
+           "fft_plans.cpp", "sizing.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -65,11 +65,9 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
     // sources, block offsets
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     const int nb = frontend_blocks(n_src);
-    const size_t per_time =
-        std::max<size_t>(256, al(24 * (size_t)n_src) + al(8 * (size_t)n_freq * n_src) + al(4 * (size_t)nb));
-    const size_t fixed = al(24 * (size_t)n_ant) + al(8 * (size_t)n_freq) * 2 + al(4 * (size_t)nb);
-    const size_t cap = std::max<size_t>(ctx->budget / 4, per_time + fixed);
-    const int group = (int)std::max<size_t>(1, std::min<size_t>({(size_t)n_time, (cap - fixed) / per_time, 65535}));
+    const DriftSizing dz = drift_sizing(n_ant, n_src, n_freq, n_time, ctx->budget);
+    const size_t per_time = dz.per_time, fixed = dz.fixed;
+    const int group = dz.group;
 
     fv_problem meta;
     std::memset(&meta, 0, sizeof(meta));

@@ -31,6 +31,7 @@
 #include <utility>
 
 #include "dev_common.h"
+#include "fft_plan_math.h"
 #include "fv_internal.h"
 
 namespace fv {
@@ -245,6 +246,8 @@ struct Plan {
     static constexpr int Og(int g) { return g <= 1 ? 0 : Og(g - 1) + Pg(g - 1) * Sg(g - 1); }  // row block offset
     static constexpr int TW = Og(G);
     static constexpr size_t lds_bytes() { return (size_t)(NL * LP + TW) * sizeof(float2); }
+    static constexpr int kF[6] = {F1, F2, F3, F4, F5, F6};
+    static_assert(lds_bytes() == plan_lds_bytes(NL, LP, kF), "host and device plan sizes differ");
     static_assert(F1 * F2 * F3 * F4 * F5 * F6 == L, "radices do not multiply to L");
     static_assert(L % 2 == 0 && G >= 2 && LP >= L, "bad plan");
 };

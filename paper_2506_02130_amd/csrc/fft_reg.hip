@@ -78,42 +78,4 @@ void launch_fft_reg_rows(const SnapDev *snaps, int n_snap, int a, void *grid, lo
     FV_HIP(hipGetLastError());
 }
 
-namespace {
-struct RegPlanInfo {
-    int L, NL;
-    size_t lds;
-};
-const RegPlanInfo kRegPlans[] = {
-#define FV_FFT_PLAN(L, NL, LP, F1, F2, F3, F4, F5, F6) \
-    {L, NL, fftr::Plan<L, NL, LP, F1, F2, F3, F4, F5, F6>::lds_bytes()},
-#if FV_FFT_COLS
-#include "fft_plans_cols.inc"
-#else
-#include "fft_plans_rows.inc"
-#endif
-#undef FV_FFT_PLAN
-};
-}  // namespace
-
-#if FV_FFT_COLS
-bool fft_reg_info_cols(int L, int *lines_per_wg, size_t *lds_bytes)
-#else
-bool fft_reg_info_rows(int L, int *lines_per_wg, size_t *lds_bytes)
-#endif
-{
-    for (const RegPlanInfo &p : kRegPlans)
-        if (p.L == L) {
-            *lines_per_wg = p.NL;
-            *lds_bytes = p.lds;
-            return true;
-        }
-    return false;
-}
-
-#if !FV_FFT_COLS
-bool fft_reg_info(int L, bool cols, int *lines_per_wg, size_t *lds_bytes) {
-    return cols ? fft_reg_info_cols(L, lines_per_wg, lds_bytes) : fft_reg_info_rows(L, lines_per_wg, lds_bytes);
-}
-#endif
-
 }  // namespace fv

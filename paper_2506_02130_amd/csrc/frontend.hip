@@ -24,7 +24,6 @@
 namespace fv {
 namespace {
 
-constexpr int kFeBlock = 256;
 
 __device__ __forceinline__ void fe_rotate(const double *R, double x, double y, double z, double &e, double &n,
                                           double &u) {
@@ -131,7 +130,6 @@ __global__ __launch_bounds__(kFeBlock) void k_frontend(const double *src_eq, int
 
 }  // namespace
 
-int frontend_blocks(int n_src) { return (n_src + kFeBlock - 1) / kFeBlock; }
 
 void launch_frontend_count(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
                            int n_freq, int *bcnt, int *bbad, int *tot, hipStream_t st) {

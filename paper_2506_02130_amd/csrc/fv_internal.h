@@ -326,8 +326,6 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
 // compile-time plan, its lines per workgroup and LDS bytes; and the launches
 // of the row pass (x) and of the column passes (y, z) over every snapshot.
 bool fft_reg_info(int L, bool cols, int *lines_per_wg, size_t *lds_bytes);
-bool fft_reg_info_rows(int L, int *lines_per_wg, size_t *lds_bytes);
-bool fft_reg_info_cols(int L, int *lines_per_wg, size_t *lds_bytes);
 void launch_fft_reg_rows(const SnapDev *snaps, int n_snap, int a, void *grid, long long n_wg, size_t lds,
                          hipStream_t st, hipEvent_t ea, hipEvent_t eb);
 void launch_fft_reg_cols(const SnapDev *snaps, int n_snap, int a, void *grid, long long n_wg, size_t lds,
@@ -397,7 +395,21 @@ void launch_basis_coeffs(const double *M_dev, const double *d_dev, int n_freq, i
                          const double *beam, double *v, hipStream_t st);
 void launch_basis_expand(const double *M_dev, int K, int n_freq, long long n_pairs, const double *F, double *vis,
                          hipStream_t st);
+constexpr int kFeBlock = 256;  // sources per workgroup of the front-end kernels
 int frontend_blocks(int n_src);
+
+// Workspace sizing (sizing.cpp, host only).  Drift scans: the device bytes of
+// the fixed part and of each time of a group, and the times per group for a
+// workspace of a quarter of the HBM budget (at least one).
+struct DriftSizing {
+    size_t per_time = 0, fixed = 0;
+    int group = 1;
+};
+DriftSizing drift_sizing(int n_ant, int n_src, int n_freq, int n_time, size_t budget);
+// Device bytes a request holds while it runs (inputs, outputs, target table
+// and the workspace of its frequencies, which run in groups of at most cap
+// bytes), given its geometry plan g (NUFFT) and the chosen dim and precision.
+size_t footprint_bytes(const fv_problem &p, const GeomPlan &g, int dim, int prec, size_t cap);
 void launch_frontend_count(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
                            int n_freq, int *bcnt, int *bbad, int *tot, hipStream_t st);
 void launch_frontend(const double *src_eq, int n_src, int n_time, const double *rot_dev, const double *flux,
@@ -410,6 +422,20 @@ void launch_direct(const double *ant_dev, int n_ant, const double *src_dev, int 
                    double *vis_dev, hipStream_t s, StageTimer *timer = nullptr);
 // Matrix-core direct sum V = Z diag(c) Z^H.  The workspace holds Z for a chunk
 // of sources sized so that the total stays within `cap` bytes.
+// Matrix-core direct form (zz.hip): tiles of kZTile antennas, the source
+// axis split over kTargetWaves wavefronts per frequency (at least kFoldSrc
+// sources each, kWavesPerBlock splits per workgroup), the sources in chunks
+// whose Z fits the workspace cap with the partial tiles.
+constexpr int kZTile = 32;          // antennas per tile edge (one wavefront: 2 x 2 MFMA tiles)
+constexpr int kFoldSrc = 128;       // FP32 mode: sources per FP32 partial sum
+constexpr int kWavesPerBlock = 4;   // splits of one tile pair per block
+constexpr int kTargetWaves = 8192;  // wavefronts per frequency the split count aims for
+struct ZZShape {
+    int na_pad, ntile, ntp, nsplit;
+    int kc_pad;          // sources per chunk, padded to a multiple of 4
+    size_t z_bytes, c_bytes, part_bytes;
+};
+ZZShape zz_shape(int n_ant, int n_src, int prec_bits, size_t cap);  // sizing.cpp
 size_t zz_work_bytes(int n_ant, int n_src, int prec_bits, size_t cap);
 void launch_zz(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
                int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits, double *vis_dev,

@@ -13,10 +13,6 @@ PipeFn pick(int dim, int prec_bits, int w) {
 
 }  // namespace
 
-size_t nufft_workspace_bytes(const std::vector<SnapJob> &jobs, int dim, int prec_bits, int w, bool det) {
-    Layout L = make_layout(jobs, dim, prec_bits, w, Tuning::defaults(), det);
-    return layout_bytes(L, dim, prec_bits, (int)jobs.size());
-}
 
 namespace {
 struct Prepared {

@@ -44,38 +44,19 @@ struct Server {
     uint64_t next_id = 1;
 };
 
-// Bytes a request holds on the device while it runs.
+// Bytes a request holds on the device while it runs (footprint_bytes, with
+// the geometry plan from the context's cache).
 size_t request_footprint(fv_ctx *ctx, const fv_problem &p) {
-    const long long np = (long long)p.n_ant * (p.n_ant + 1) / 2;
-    const size_t fs = 8 * (size_t)p.n_src * p.n_freq;
-    size_t bytes = 24 * (size_t)p.n_ant + 24 * (size_t)p.n_src + fs * (p.beam ? 2 : 1) + 16 * (size_t)np * p.n_freq;
-    if (p.n_src == 0) return bytes;
-    const unsigned method = p.flags & FV_METHOD_MASK;
     const int dim = choose_dim(p.ant_enu, p.n_ant, p.eps, p.freq_hz, p.n_freq, p.flags);
     const int prec = choose_prec(p.eps, p.flags);
     const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
-    if (method == FV_METHOD_DIRECT) return bytes;
-    if (method == FV_METHOD_MFMA) return bytes + zz_work_bytes(p.n_ant, p.n_src, prec, cap);
-    double s_c[3], S[3];
-    src_box(p.src_lmn, p.n_src, dim, s_c, S);
-    GeomPlan g = ctx_geometry(ctx, p.ant_enu, p.n_ant, dim, p.eps, s_c, S, !(p.flags & FV_NO_FOLD));
-    TargetTable tt;  // sizes only
-    tt.n_tgt = np;
-    tt.dim = dim;
-    size_t ws = 0, ws_max = 0;
-    for (int f = 0; f < p.n_freq; ++f) {
-        SnapJob j;
-        j.plan = plan_snapshot(g, p.freq_hz[f]);
-        j.src = p.src_lmn;
-        j.n_src = p.n_src;
-        j.tt = &tt;
-        const size_t b = nufft_workspace_bytes(std::vector<SnapJob>{j}, dim, prec, g.w,
-                                               (p.flags & FV_DETERMINISTIC) != 0);
-        ws += b;
-        ws_max = std::max(ws_max, b);
+    GeomPlan g;
+    if (p.n_src > 0 && (p.flags & FV_METHOD_MASK) == FV_METHOD_NUFFT) {
+        double s_c[3], S[3];
+        src_box(p.src_lmn, p.n_src, dim, s_c, S);
+        g = ctx_geometry(ctx, p.ant_enu, p.n_ant, dim, p.eps, s_c, S, !(p.flags & FV_NO_FOLD));
     }
-    ws = std::min(ws, std::max(cap, ws_max));  // frequencies run in groups of at most `cap`
-    return bytes + ws + (size_t)np * (16 * (size_t)dim + 4);
+    return footprint_bytes(p, g, dim, prec, cap);
 }
 
 namespace {

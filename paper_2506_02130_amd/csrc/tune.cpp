@@ -9,31 +9,6 @@
 
 namespace fv {
 
-static int env_or(const char *name, int dflt) {
-    const char *e = std::getenv(name);
-    return e ? std::atoi(e) : dflt;
-}
-
-Tuning Tuning::defaults() {
-    static const Tuning t = [] {
-        Tuning d;
-        d.rows = std::max(1, std::min(16, env_or("FV_FFT_ROWS", d.rows)));
-        d.lines = std::max(1, std::min(64, env_or("FV_FFT_MAX_LINES", d.lines)));
-        d.tpb1 = env_or("FV_FFT_TPB1", d.tpb1);
-        d.tpbm = env_or("FV_FFT_TPBM", d.tpbm);
-        d.split = env_or("FV_FFT_SPLIT", d.split) ? 1 : 0;
-        return d;
-    }();
-    return t;
-}
-
-int Tuning::tpb(int line_len, bool multi) const {
-    int t = multi ? tpbm : tpb1;
-    if (t != 128 && t != 256 && t != 512 && t != 1024) t = 0;
-    if (t == 0) t = line_len <= 2048 ? 256 : (line_len <= 4096 ? 512 : 1024);
-    return t;
-}
-
 bool TuneCache::find(const std::string &key, Tuning *t) {
     std::lock_guard<std::mutex> lk(mu);
     auto it = entries.find(key);

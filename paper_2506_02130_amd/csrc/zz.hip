@@ -36,10 +36,6 @@
 namespace fv {
 namespace {
 
-constexpr int kZTile = 32;          // antennas per tile edge (one wavefront: 2 x 2 MFMA tiles)
-constexpr int kFoldSrc = 128;       // FP32 mode: sources per FP32 partial sum
-constexpr int kWavesPerBlock = 4;   // splits of one tile pair per block
-constexpr int kTargetWaves = 8192;  // wavefronts per frequency the split count aims for
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_zbuild(const double *ant, int n_ant, int na_pad, const double *src, int k0,
@@ -180,38 +176,6 @@ __global__ __launch_bounds__(256) void k_zz_out(const double2 *part, int n_ant, 
     vis[2 * p + 1] = im;
 }
 
-struct ZZShape {
-    int na_pad, ntile, ntp, nsplit;
-    int kc_pad;          // sources per chunk, padded to a multiple of 4
-    size_t z_bytes, c_bytes, part_bytes;
-};
-
-ZZShape zz_shape(int n_ant, int n_src, int prec_bits, size_t cap) {
-    ZZShape s;
-    s.na_pad = (n_ant + kZTile - 1) / kZTile * kZTile;
-    s.ntile = s.na_pad / kZTile;
-    s.ntp = s.ntile * (s.ntile + 1) / 2;
-    const size_t csz = prec_bits == 32 ? 8 : 16, rsz = csz / 2;
-    const int k_all = (std::max(n_src, 1) + 3) / 4 * 4;
-    // splits: enough wavefronts to fill the chip, at least kFoldSrc sources
-    // each, partials within half of the cap
-    const size_t tile_bytes = (size_t)s.ntp * kZTile * kZTile * sizeof(double2);
-    int ns = (kTargetWaves + s.ntp - 1) / s.ntp;
-    ns = std::min(ns, std::max(1, k_all / kFoldSrc));
-    ns = std::min<long long>(ns, std::max<long long>(kWavesPerBlock, (long long)(cap / 2 / tile_bytes)));
-    s.nsplit = (ns + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
-    s.part_bytes = (size_t)s.nsplit * tile_bytes;
-    // sources per chunk: Z and c of the chunk in the rest of the cap
-    const size_t per_src = (size_t)s.na_pad * csz + rsz;
-    size_t kc = k_all;
-    const size_t rest = cap > s.part_bytes + 1024 ? cap - s.part_bytes - 1024 : 0;
-    if ((size_t)k_all * per_src > rest) kc = std::max<size_t>(4 * kFoldSrc, rest / per_src / 4 * 4);
-    s.kc_pad = (int)std::min<size_t>(kc, (size_t)k_all);
-    s.z_bytes = (size_t)s.kc_pad * s.na_pad * csz;
-    s.c_bytes = (size_t)s.kc_pad * rsz;
-    return s;
-}
-
 template <typename R>
 void run_zz(const double *ant, int n_ant, const double *src, int n_src, const double *freq_host, int n_freq,
             const double *flux, const double *beam, int dim, int prec_bits, double *vis, void *work, size_t cap,
@@ -257,11 +221,6 @@ void run_zz(const double *ant, int n_ant, const double *src, int n_src, const do
 }
 
 }  // namespace
-
-size_t zz_work_bytes(int n_ant, int n_src, int prec_bits, size_t cap) {
-    const ZZShape s = zz_shape(n_ant, n_src, prec_bits, cap);
-    return (s.z_bytes + 255) / 256 * 256 + (s.c_bytes + 255) / 256 * 256 + s.part_bytes + 256;
-}
 
 void launch_zz(const double *ant_dev, int n_ant, const double *src_dev, int n_src, const double *freq_host,
                int n_freq, const double *flux_dev, const double *beam_dev, int dim, int prec_bits, double *vis_dev,
