@@ -167,6 +167,33 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
 fv_status fv_simulate_batch(fv_ctx *ctx, int n_snap, const fv_problem *snaps, double *const *vis,
                             fv_report *rep);
 
+/* Many snapshots whose arrays are on the device (the per-(time, frequency)
+ * simulations of paper section 5.4 with their inputs already resident).
+ * snaps and vis are host arrays of n_snap entries; every array pointer inside
+ * snaps[i], and vis[i] (16-byte aligned, n_freq x n_pairs complex doubles),
+ * is a device pointer on the context's device.  The call enqueues the input
+ * check of the whole batch (two launches) and one copy of the planning
+ * scalars (antenna positions, frequencies, source box), waits for them, then
+ * enqueues the whole batch on `stream` (a hipStream_t; NULL = the null
+ * stream) and returns:
+ * lattice snapshots of one (precision, kernel width) run as one launch per
+ * stage, and with FV_GRAPH in their flags that launch sequence is captured
+ * once per shape and replayed.  Buffers stay alive until the stream has
+ * completed.  Ordered with the context's other calls as fv_simulate_dev is.
+ * A batch that repeats the previous batch's arguments (the same device
+ * pointers, sizes, eps and flags) is enqueued right behind its input
+ * check, planned on the previous batch's scalars, while the host waits for
+ * the check; when the new scalars differ (the arrays' contents changed) the
+ * batch is enqueued again with the new plan, and when the check fails the
+ * outputs of such a batch may already have been written.
+ * Errors: FV_EINVAL for a null or misaligned pointer, bad sizes or eps, and
+ * invalid values the device check finds (nothing is computed then, except as
+ * said for a repeated batch); FV_EUNSUPPORTED for more than 65535 snapshots, or more than 65535
+ * (snapshot, frequency) rows in one lattice group; FV_ENOMEM / FV_EDEVICE
+ * from the device. */
+fv_status fv_simulate_batch_dev(fv_ctx *ctx, int n_snap, const fv_problem *snaps, double *const *vis, void *stream,
+                                fv_report *rep);
+
 /* Drift scan with the front end on the device (paper section 2.3: between
  * astrometric pre-corrections, a rigid rotation set by the local sidereal
  * time and the latitude takes pre-corrected equatorial positions to the local

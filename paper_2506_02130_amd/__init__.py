@@ -48,7 +48,43 @@ def timing_stage(stage) -> int:
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
                "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar", "fv_simulate_basis",
-               "fv_stage_times", "fv_simulate_mfma_noalloc")
+               "fv_stage_times", "fv_simulate_mfma_noalloc", "fv_simulate_batch_dev")
+
+
+
+def _dev_problem(ant_enu, src_lmn, freq_hz, flux, beam, vis, eps, flags) -> "Problem":
+    """The C struct of one problem whose arrays are torch device tensors;
+    every size is checked here, since the C ABI takes bare device pointers."""
+    import torch
+    for name, t in (("ant_enu", ant_enu), ("src_lmn", src_lmn), ("freq_hz", freq_hz), ("flux", flux),
+                    ("vis", vis)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if beam is not None and not (beam.is_cuda and beam.dtype == torch.float64 and beam.is_contiguous()):
+        raise ValueError("beam must be a contiguous float64 device tensor")
+    n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
+    sizes = (("ant_enu", ant_enu, 3 * n_ant), ("src_lmn", src_lmn, 3 * n_src), ("freq_hz", freq_hz, n_freq),
+             ("flux", flux, n_freq * n_src), ("vis", vis, 2 * n_freq * n_ant * (n_ant + 1) // 2))
+    if beam is not None:
+        sizes += (("beam", beam, n_freq * n_src),)
+    for name, t, want in sizes:
+        if t.numel() != want:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {want}")
+    return Problem(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
+                   freq_hz.data_ptr(), flux.data_ptr() if n_src else None,
+                   None if beam is None else beam.data_ptr(), float(eps), int(flags))
+
+
+class DevBatch:
+    """A batch of device-tensor problems marshalled for fv_simulate_batch_dev."""
+
+    def __init__(self, problems):
+        self.n = len(problems)
+        self.items = list(problems)  # keeps the tensors alive
+        cs = [_dev_problem(q["ant_enu"], q["src_lmn"], q["freq_hz"], q["flux"], q.get("beam"), q["vis"],
+                           q.get("eps", 1e-6), q.get("flags", 0)) for q in problems]
+        self.arr = (Problem * self.n)(*cs)
+        self.ptrs = (ctypes.c_void_p * self.n)(*[q["vis"].data_ptr() for q in problems])
 
 
 class FvError(RuntimeError):
@@ -120,6 +156,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_simulate.argtypes = [vp, P(Problem), vp, P(Report)]
     lib.fv_simulate_dev.argtypes = [vp, P(Problem), vp, vp, P(Report)]
     lib.fv_simulate_batch.argtypes = [vp, ctypes.c_int, P(Problem), P(vp), P(Report)]
+    lib.fv_simulate_batch_dev.argtypes = [vp, ctypes.c_int, P(Problem), P(vp), vp, P(Report)]
     lib.fv_server_start.argtypes = [vp, ctypes.c_int]
     lib.fv_submit.argtypes = [vp, P(Problem), vp, P(ctypes.c_uint64)]
     lib.fv_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, P(Report)]
@@ -133,7 +170,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_stage_times.argtypes = [vp, dp, P(ctypes.c_int), P(ctypes.c_int)]
     lib.fv_simulate_mfma_noalloc.argtypes = [P(Problem), vp, vp]
     lib.fv_simulate_mfma_noalloc.restype = ctypes.c_int
-    for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_server_start",
+    for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_simulate_batch_dev",
+                 "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -245,25 +283,8 @@ class Context:
         enqueued on ``stream`` (a torch.cuda.Stream, default: torch's current
         stream); returns the report."""
         import torch
-        for name, t in (("ant_enu", ant_enu), ("src_lmn", src_lmn), ("freq_hz", freq_hz), ("flux", flux),
-                        ("vis", vis)):
-            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-                raise ValueError(f"{name} must be a contiguous float64 device tensor")
-        if beam is not None and not (beam.is_cuda and beam.dtype == torch.float64 and beam.is_contiguous()):
-            raise ValueError("beam must be a contiguous float64 device tensor")
-        n_ant, n_src, n_freq = ant_enu.shape[0], src_lmn.shape[0], freq_hz.shape[0]
-        # the C ABI takes bare device pointers: every size is checked here
-        sizes = (("ant_enu", ant_enu, 3 * n_ant), ("src_lmn", src_lmn, 3 * n_src), ("freq_hz", freq_hz, n_freq),
-                 ("flux", flux, n_freq * n_src), ("vis", vis, 2 * n_freq * n_ant * (n_ant + 1) // 2))
-        if beam is not None:
-            sizes += (("beam", beam, n_freq * n_src),)
-        for name, t, want in sizes:
-            if t.numel() != want:
-                raise ValueError(f"{name} has {t.numel()} elements, expected {want}")
         st = stream if stream is not None else torch.cuda.current_stream()
-        c = Problem(n_ant, ant_enu.data_ptr(), n_src, src_lmn.data_ptr() if n_src else None, n_freq,
-                    freq_hz.data_ptr(), flux.data_ptr() if n_src else None,
-                    None if beam is None else beam.data_ptr(), float(eps), int(flags))
+        c = _dev_problem(ant_enu, src_lmn, freq_hz, flux, beam, vis, eps, flags)
         rep = Report()
         _check(_lib.fv_simulate_dev(self._h, ctypes.byref(c), vis.data_ptr(), ctypes.c_void_p(st.cuda_stream),
                                     ctypes.byref(rep)))
@@ -419,6 +440,28 @@ class Context:
         _check(_lib.fv_simulate_batch(self._h, n, arr, ptrs, ctypes.byref(rep)))
         self.last_report = rep.as_dict()
         return [o[..., 0] + 1j * o[..., 1] for o in outs]
+
+    def prepare_batch_dev(self, problems: Sequence[dict]) -> "DevBatch":
+        """Checks and marshals a batch of problems whose arrays are torch
+        device tensors: each item is a dict with the keys of simulate_dev
+        (ant_enu, src_lmn, freq_hz, flux, beam, vis, eps, flags).  The result
+        can be run many times (run_batch_dev); it keeps the tensors alive."""
+        return DevBatch(problems)
+
+    def run_batch_dev(self, batch: "DevBatch", stream=None) -> dict:
+        """Enqueues a prepared batch on ``stream`` (default: torch's current
+        stream); returns the batch report."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        rep = Report()
+        _check(_lib.fv_simulate_batch_dev(self._h, batch.n, batch.arr, batch.ptrs, ctypes.c_void_p(st.cuda_stream),
+                                          ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return self.last_report
+
+    def simulate_batch_dev(self, problems: Sequence[dict], stream=None) -> dict:
+        """prepare_batch_dev and run_batch_dev in one call."""
+        return self.run_batch_dev(self.prepare_batch_dev(problems), stream)
 
     # ------------------------------------------------------------------ serving
     def server_start(self, max_slots: int = 4):

@@ -3,6 +3,7 @@
 
 #include <condition_variable>
 #include <deque>
+#include <array>
 #include <list>
 #include <tuple>
 #include <memory>
@@ -34,6 +35,7 @@ struct Slot {
     bool own_stream = false;
     Arena arena;   // NUFFT workspace
     Arena inputs;  // uploaded inputs and the device output
+    Arena lat;     // workspace of batched lattice launches
     StageTimer timer;
     GraphCache graphs;  // launch graphs captured on this slot's workspace
     // end of the last call's work on the caller's stream (device entry
@@ -78,6 +80,17 @@ struct fv_ctx {
         int dim = 0;
         hipEvent_t ev = nullptr;  // the check's copy to the host
     } spec;
+    // The same for fv_simulate_batch_dev: the last batch's arguments and each
+    // problem's planning scalars (box: source box centre, half-width).
+    struct BatchSpec {
+        bool valid = false;
+        std::vector<fv_problem> args;
+        std::vector<double *> vis;
+        std::vector<std::vector<double>> ant, freq;
+        std::vector<std::array<double, 6>> box;
+        std::vector<int> dim;
+        hipEvent_t ev = nullptr;  // the check's copy to the host
+    } bspec;
     fv::TuneCache tunes;     // autotuned FFT launch shapes
     fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
     double *scalars(size_t n_doubles) {
@@ -152,6 +165,13 @@ void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv
 void server_free(Server *s);  // stops the workers (cancelling queued requests) and frees
 size_t request_footprint(fv_ctx *ctx, const fv_problem &p);
 void simulate_batch(fv_ctx *ctx, Slot &slot, int n, const fv_problem *ps, double *const *vis, fv_report *rep);
+// Problems whose inputs are on the device: meta[i] holds host copies of the
+// antenna positions and frequencies, in[i] the device arrays, source box and
+// input-check partials.  Enqueues every problem's work on slot.stream with no
+// host wait between problems.
+// lattice_used (nullable) receives, per problem, whether it took the type-1 path.
+void run_batch_device(fv_ctx *ctx, Slot &slot, int n, const fv_problem *meta, const DevInputs *in, fv_report &r,
+                      std::vector<char> *lattice_used);
 const char *last_error_cstr();
 void set_last_error(const std::string &msg);
 

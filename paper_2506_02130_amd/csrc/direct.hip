@@ -6,6 +6,7 @@
 // FP64.  Plus small utility kernels (input checks, zero fill).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "dev_common.h"
@@ -104,13 +105,14 @@ __device__ __forceinline__ void check_strengths(const double *x, const double *b
     }
 }
 
-__global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, const double *flux,
-                                                  const double *beam, long long n_fs, long long span, double *part) {
+// Block `blk` of `nblk` (256 threads) of the input check of one problem.
+__device__ __forceinline__ void validate_block(const double *src, int n_src, const double *flux, const double *beam,
+                                               long long n_fs, long long span, double *part, int blk, int nblk) {
     __shared__ double red[6][256];
     __shared__ int bsh[2][256];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
-    const long long tid = (long long)blockIdx.x * 256 + threadIdx.x, nth = (long long)gridDim.x * 256;
+    const long long tid = (long long)blk * 256 + threadIdx.x, nth = (long long)nblk * 256;
     for (long long j = tid; j < n_src; j += nth) {
         const double a = src[3 * j], b = src[3 * j + 1], c = src[3 * j + 2];
         if (!(isfinite(a) && isfinite(b) && isfinite(c)) || fabs(sqrt(a * a + b * b + c * c) - 1.0) > 1e-9) ++bad;
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, 
     }
     // this block's contiguous range of the strengths: non-finite count and
     // the largest |flux beam|
-    const long long f0 = min((long long)blockIdx.x * span, n_fs), f1 = min(f0 + span, n_fs);
+    const long long f0 = min((long long)blk * span, n_fs), f1 = min(f0 + span, n_fs);
     int badv = 0;
     double cm = 0.0;
     if (f1 > f0) check_strengths(flux + f0, beam ? beam + f0 : nullptr, f1 - f0, threadIdx.x, 256, badv, cm);
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double *q = part + (size_t)kValStride * blockIdx.x;
+        double *q = part + (size_t)kValStride * blk;
         for (int k = 0; k < 6; ++k) q[k] = red[k][0];
         q[6] = (double)bsh[0][0];
         q[7] = (double)bsh[1][0];
@@ -158,14 +160,26 @@ __global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, 
     }
 }
 
+__global__ __launch_bounds__(256) void k_validate(const double *src, int n_src, const double *flux,
+                                                  const double *beam, long long n_fs, long long span, double *part) {
+    validate_block(src, n_src, flux, beam, n_fs, span, part, blockIdx.x, gridDim.x);
+}
+
+// A batch of problems: blockIdx.y picks the problem, which has its own
+// number of blocks.
+__global__ __launch_bounds__(256) void k_validate_b(const ValItem *items) {
+    const ValItem &v = items[blockIdx.y];
+    if ((int)blockIdx.x >= v.nblk) return;
+    validate_block(v.src, v.n_src, v.flux, v.beam, v.n_fs, v.span, v.part, blockIdx.x, v.nblk);
+}
+
 // The kValReduceThreads threads fold the per-block partials (thread t takes
 // blocks t, t + kValReduceThreads, ...), then a butterfly across each
 // wavefront's lanes and a pass over the wavefronts; every thread also helps
 // gather the frequencies and antenna positions.
 constexpr int kValReduceThreads = 1024;
-__global__ __launch_bounds__(kValReduceThreads) void k_validate_reduce(const double *part, int nblk,
-                                                                       const double *freq, int n_freq,
-                                                                       const double *ant, int n_ant, double *out) {
+__device__ __forceinline__ void validate_reduce(const double *part, int nblk, const double *freq, int n_freq,
+                                                const double *ant, int n_ant, double *out) {
     constexpr int NW = kValReduceThreads / 64;
     __shared__ double wred[NW][8];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -201,6 +215,17 @@ __global__ __launch_bounds__(kValReduceThreads) void k_validate_reduce(const dou
     }
     for (int i = t; i < n_freq; i += kValReduceThreads) out[8 + i] = freq[i];
     for (int i = t; i < 3 * n_ant; i += kValReduceThreads) out[8 + n_freq + i] = ant[i];
+}
+
+__global__ __launch_bounds__(kValReduceThreads) void k_validate_reduce(const double *part, int nblk,
+                                                                       const double *freq, int n_freq,
+                                                                       const double *ant, int n_ant, double *out) {
+    validate_reduce(part, nblk, freq, n_freq, ant, n_ant, out);
+}
+
+__global__ __launch_bounds__(kValReduceThreads) void k_validate_reduce_b(const ValItem *items) {
+    const ValItem &v = items[blockIdx.x];
+    validate_reduce(v.part, v.nblk, v.freq, v.n_freq, v.ant, v.n_ant, v.hdr);
 }
 
 __global__ void k_zero_f64(double *p, long long n) {
@@ -258,6 +283,19 @@ void launch_validate(const double *src, int n_src, const double *flux, const dou
                        n_src > 0 ? flux : nullptr, n_src > 0 ? beam : nullptr, n_fs, validate_span(n_fs), part);
     hipLaunchKernelGGL(k_validate_reduce, dim3(1), dim3(kValReduceThreads), 0, st, (const double *)part, kSrcCheckBlocks, freq,
                        n_freq, ant, n_ant, out);
+    FV_HIP(hipGetLastError());
+}
+
+int validate_blocks_batch(long long n_src, long long n_fs) {
+    // about 16k strengths and 2k directions per block, at least one block
+    const long long b = std::max((n_fs + 16383) / 16384, (n_src + 2047) / 2048);
+    return (int)std::max(1LL, std::min(b, (long long)kSrcCheckBlocks));
+}
+
+void launch_validate_batch(const ValItem *items_dev, int n, int max_blk, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_validate_b, dim3((unsigned)max_blk, (unsigned)n), dim3(256), 0, st, items_dev);
+    hipLaunchKernelGGL(k_validate_reduce_b, dim3((unsigned)n), dim3(kValReduceThreads), 0, st, items_dev);
     FV_HIP(hipGetLastError());
 }
 

@@ -310,6 +310,23 @@ void lattice_grid(const LatticePlan &lp, int w, int nf[2]);       // fine period
 // input check's block partials (each holds the largest |flux beam| of a flat
 // range of cmax_span values), or null to have the spreading kernel find each
 // chunk's largest strength itself.  Enqueues kernels only (no copies).
+// One problem of a batched lattice launch (device inputs, as for launch_lattice).
+struct LatItem {
+    const LatticePlan *lp = nullptr;
+    const double *src = nullptr, *flux = nullptr, *beam = nullptr, *cmax = nullptr, *freq = nullptr;
+    long long cmax_span = 0;
+    int n_src = 0, n_freq = 0, n_ant = 0;
+    double *vis = nullptr;
+};
+// Workspace bytes of a batch (every problem's partials, row and mode arrays,
+// then the parameter array and row maps), and the batch's four launches, one
+// per stage for every (problem, frequency); `stage` is pinned staging for the
+// parameter upload; with `graphs` (non-null, no stage timing) the four launches
+// are captured once per workspace and shape and replayed.  Returns the
+// algorithmic bytes.
+size_t lattice_batch_bytes(const std::vector<LatItem> &items, int prec_bits, int w);
+double launch_lattice_batch(const std::vector<LatItem> &items, int prec_bits, int w, void *work, PinnedBuf &stage,
+                            hipStream_t st, StageTimer *tm, GraphCache *graphs);
 double launch_lattice(const LatticePlan &lp, const double *src_dev, int n_src, const double *freq_dev, int n_freq,
                       const double *flux_dev, const double *beam_dev, const double *cmax_part, long long cmax_span,
                       int n_ant, int prec_bits, int w, double *vis_dev, void *work, hipStream_t st,
@@ -362,6 +379,22 @@ inline const double *validate_partials(const double *out, int n_ant, int n_freq)
 size_t validate_doubles(int n_ant, int n_freq);
 void launch_validate(const double *src, int n_src, const double *flux, const double *beam, int n_freq,
                      const double *ant, int n_ant, const double *freq, double *out, hipStream_t s);
+// The input check of a batch of problems in two launches.  Each problem's
+// nblk blocks write their partials to `part` (kValStride doubles each; block
+// b covers the flat strength range [b span, (b + 1) span)), and the fold
+// writes the 8 check values, the frequencies and the antenna positions to
+// `hdr` (8 + n_freq + 3 n_ant doubles), so that the headers of a batch can be
+// packed together and fetched with one copy.  items_dev is a device array of
+// n entries; max_blk the largest nblk.
+struct ValItem {
+    const double *src, *flux, *beam, *freq, *ant;
+    double *hdr, *part;
+    long long n_fs, span;
+    int n_src, n_freq, n_ant, nblk;
+};
+int validate_blocks_batch(long long n_src, long long n_fs);
+inline long long validate_span_n(long long n_fs, int nblk) { return ((n_fs + nblk - 1) / nblk + 1) & ~1LL; }
+void launch_validate_batch(const ValItem *items_dev, int n, int max_blk, hipStream_t s);
 void launch_zero_c128(double *out, long long n_complex, hipStream_t s);
 
 // Drift-scan front end.  rot_dev [n_time][9] holds the rotations (rows E, N,

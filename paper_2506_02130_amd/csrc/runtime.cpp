@@ -235,8 +235,10 @@ Slot::~Slot() {
     graphs.release();
     arena.host.release();
     inputs.host.release();
+    lat.host.release();
     arena.release();
     inputs.release();
+    lat.release();
     if (done) (void)hipEventDestroy(done);
     if (stream && own_stream) (void)hipStreamDestroy(stream);
 }
@@ -723,6 +725,7 @@ void fv_destroy(fv_ctx *ctx) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
         if (ctx->spec.ev) (void)hipEventDestroy(ctx->spec.ev);
+        if (ctx->bspec.ev) (void)hipEventDestroy(ctx->bspec.ev);
     } catch (...) {
     }
     delete ctx;
