@@ -153,15 +153,6 @@ void simulate_basis(fv_ctx *ctx, const fv_problem *p, int K, double *vis, hipStr
                 j.tt = tt.get();
                 jobs.push_back(j);
             }
-            // FP32 grids hold eps >= 1e-6 only while sources do not crowd into few
-            // cells (as for the per-frequency path)
-            if (key.prec == 32 && !(p->flags & FV_PREC_MASK)) {
-                double occ = 1.0;
-                for (int a = 0; a < dim; ++a)
-                    occ *= std::max(1.0, 2.0 * kSigma / M_PI * jobs[0].plan.X[a] *
-                                             std::max(jobs[0].plan.S[a], 1.0 / jobs[0].plan.X[a]));
-                if ((double)n_src > kMaxSrcPerCell * occ) key.prec = 64;
-            }
             r.model_bytes = execute_jobs(ctx, slot, jobs, key, &tm);
             launch_basis_expand(M_dev, K, n_freq, n_pairs, F, vis, st);
             r.dim = dim;

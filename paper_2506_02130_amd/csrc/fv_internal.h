@@ -23,7 +23,6 @@ constexpr int kMinW = 3;
 constexpr int kQuadHalf = 32;    // positive nodes of the 64-node Gauss-Legendre rule
 constexpr int kSubBin = 8;       // sub-bin edge (cells) of the source sort along x and y
 constexpr int kSubBinZ = 4;      // sub-bin edge along z
-constexpr double kMaxSrcPerCell = 16.0;  // FP32 grids while sources per covered cell stay below this
 constexpr int kSrcCheckBlocks = 2048;  // blocks of the input-check pass (one partial each)
 
 // ---------------------------------------------------------------------------

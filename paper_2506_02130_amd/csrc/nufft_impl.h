@@ -400,6 +400,11 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
         R accr[Cfg::TZ], acci[Cfg::TZ];
 #pragma unroll
         for (int k = 0; k < Cfg::TZ; ++k) accr[k] = acci[k] = 0;
+        // FP32: per-batch sums added in FP64 (as in the matrix-core spread)
+        constexpr bool kBlocked = std::is_same<R, float>::value;
+        double sumr[Cfg::TZ], sumi[Cfg::TZ];
+#pragma unroll
+        for (int k = 0; k < Cfg::TZ; ++k) sumr[k] = sumi[k] = 0.0;
         for (int b0 = 0; b0 < total; b0 += 64) {
             const int e = b0 + lane;
             int ml0x = -1000000, ml0y = -1000000, ml0z = -1000000;
@@ -461,6 +466,14 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
                     }
                 }
             }
+            if constexpr (kBlocked) {
+#pragma unroll
+                for (int k = 0; k < Cfg::TZ; ++k) {
+                    sumr[k] += (double)accr[k];
+                    sumi[k] += (double)acci[k];
+                    accr[k] = acci[k] = 0;
+                }
+            }
             wave_sync();
         }
         // flush: divide by psi2hat at the modes and store each owned cell once
@@ -472,7 +485,11 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
                 const int oz = z0 + k;
                 if (D == 3 && oz >= S.n1[2]) break;
                 const R f = D == 3 ? fxy * iz_t[oz] : fxy;
-                dst[((long long)oz * S.n1[1] + oy) * S.n1[0] + ox] = cmake<R>(accr[k] * f, acci[k] * f);
+                if constexpr (kBlocked)
+                    dst[((long long)oz * S.n1[1] + oy) * S.n1[0] + ox] =
+                        cmake<R>((R)(sumr[k] * (double)f), (R)(sumi[k] * (double)f));
+                else
+                    dst[((long long)oz * S.n1[1] + oy) * S.n1[0] + ox] = cmake<R>(accr[k] * f, acci[k] * f);
             }
         }
     }
@@ -559,6 +576,11 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
         prev = del;
     }
     typename MA::T accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+    // FP32 tiles: each batch of 64 records is summed on the matrix cores from
+    // zero and the batch sums are added in FP64, so the rounding error of a
+    // cell does not grow with the number of records that reach it
+    constexpr bool kBlocked = std::is_same<R, float>::value;
+    double sumr[4] = {0, 0, 0, 0}, sumi[4] = {0, 0, 0, 0};
     const int li = lane & 15, lk = lane >> 4;  // A row / B column index, record slot of the 4
     const int lib = li * (int)sizeof(R);
     // record e of the tile's neighbourhood (a position in its sub-bin rows):
@@ -640,6 +662,15 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
                 acci = MA::step(a[u], bim[u], acci);
             }
         }
+        if constexpr (kBlocked) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sumr[r] += (double)accr[r];
+                sumi[r] += (double)acci[r];
+                accr[r] = 0;
+                acci[r] = 0;
+            }
+        }
         wave_sync();
     }
     // flush: divide by psi2hat at the modes, store each owned cell once
@@ -652,7 +683,10 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
         const int cy_ = y0 + MA::row(lane, r);
         if (cx_ < S.n1[0] && cy_ < S.n1[1]) {
             const R f = ix_t[cx_] * iy_t[cy_];
-            dst[(long long)cy_ * S.n1[0] + cx_] = cmake<R>(accr[r] * f, acci[r] * f);
+            if constexpr (kBlocked)
+                dst[(long long)cy_ * S.n1[0] + cx_] = cmake<R>((R)(sumr[r] * (double)f), (R)(sumi[r] * (double)f));
+            else
+                dst[(long long)cy_ * S.n1[0] + cx_] = cmake<R>(accr[r] * f, acci[r] * f);
         }
     }
 }

@@ -471,20 +471,6 @@ NufftGroupKey append_jobs(fv_ctx *ctx, const fv_problem &p, const DevInputs &in,
         if (p.freq_hz[f] > p.freq_hz[best_f]) best_f = f;
     }
     if (top) *top = jobs[jobs.size() - n_freq + best_f].plan;
-    // FP32 grids sum the sources of a cell in FP32; when the sources crowd into
-    // few cells (more than kMaxSrcPerCell per cell the source box covers, at
-    // the lowest frequency) that sum would no longer hold eps >= 1e-6, so the
-    // grids switch to FP64 unless the caller forced a precision
-    if (k.prec == 32 && !(p.flags & FV_PREC_MASK) && n_src > 0) {
-        int lo_f = 0;
-        for (int f = 0; f < n_freq; ++f)
-            if (p.freq_hz[f] < p.freq_hz[lo_f]) lo_f = f;
-        const SnapPlan &lo = jobs[jobs.size() - n_freq + lo_f].plan;
-        double occ = 1.0;
-        for (int a = 0; a < k.dim; ++a)
-            occ *= std::max(1.0, 2.0 * kSigma / M_PI * lo.X[a] * std::max(lo.S[a], 1.0 / lo.X[a]));
-        if ((double)n_src > kMaxSrcPerCell * occ) k.prec = 64;
-    }
     return k;
 }
 

@@ -252,8 +252,8 @@ def test_fp64_multi_frequency(gpu_lib, ctx):
 
 @pytest.mark.parametrize("n_src", [10, 300, 3000])
 def test_crowded_sources_keep_eps(gpu_lib, ctx, n_src):
-    # every source inside one grid cell of a random array: FP32 cell sums would
-    # lose the 1e-6 contract, so the grids switch to FP64 (unless forced)
+    # every source inside one grid cell of a random array: the grids stay FP32
+    # (batch sums in FP64) and keep the 1e-6 contract
     import dataclasses
     fv = gpu_lib
     p = synth.small_problem(170, n_ant=30, n_src=n_src, n_freq=2)
@@ -262,7 +262,46 @@ def test_crowded_sources_keep_eps(gpu_lib, ctx, n_src):
     src[:, 2] = np.sqrt(1 - src[:, 0] ** 2 - src[:, 1] ** 2)
     q = dataclasses.replace(p, src_lmn=src, beam=None)
     v, rep = _run(fv, ctx, q, eps=1e-6)
-    assert rep["prec_bits"] == (64 if n_src > 16 else 32) and rep["lattice"] == 0
+    assert rep["prec_bits"] == 32 and rep["lattice"] == 0
+    assert oracle.rel_l2(v, oracle.direct_problem(q)) <= 1e-6
+
+
+def _crowded(seed, n_in, n_out, three_d=False):
+    # n_in sources inside one grid cell (0.1 mrad apart), n_out spread over
+    # the disk, so that the source box is large and the mean density low
+    import dataclasses
+    p = synth.small_problem(seed, n_ant=30, n_src=n_in + n_out, n_freq=2, three_d=three_d, radius=60.0)
+    rng = np.random.default_rng(seed)
+    src = np.zeros((n_in + n_out, 3))
+    src[:n_in, 0] = 0.001 + np.linspace(0, 1e-4, n_in)
+    src[:n_in, 1] = 0.002
+    r = np.sqrt(rng.uniform(0, 0.8, n_out))
+    t = rng.uniform(0, 2 * np.pi, n_out)
+    src[n_in:, 0], src[n_in:, 1] = r * np.cos(t), r * np.sin(t)
+    src[:, 2] = np.sqrt(1 - src[:, 0] ** 2 - src[:, 1] ** 2)
+    return dataclasses.replace(p, src_lmn=src, beam=None)
+
+
+@pytest.mark.parametrize("n_in", [3000, 30000])
+@pytest.mark.parametrize("three_d", [False, True])
+def test_fp32_grids_keep_eps_with_a_crowded_cell(gpu_lib, ctx, n_in, three_d):
+    # FP32 grids forced: the spread sums every batch of 64 records in FP32 and
+    # the batches in FP64, so one cell crowded with thousands of records keeps
+    # the 1e-6 contract
+    fv = gpu_lib
+    q = _crowded(172 + three_d, n_in, 0)
+    v, rep = _run(fv, ctx, q, eps=1e-6, flags=fv.PREC_FP32 | fv.NO_LATTICE | (fv.DIM_3D if three_d else fv.DIM_2D))
+    assert rep["prec_bits"] == 32 and rep["lattice"] == 0 and rep["dim"] == (3 if three_d else 2)
+    assert oracle.rel_l2(v, oracle.direct_problem(q)) <= 1e-6
+
+
+def test_dense_cell_plus_outliers_keeps_eps(gpu_lib, ctx):
+    # a clustered sky: 3000 sources in one cell and 300 across the disk (a
+    # large source box with one crowded cell); FP32 grids keep 1e-6
+    fv = gpu_lib
+    q = _crowded(174, 3000, 300)
+    v, rep = _run(fv, ctx, q, eps=1e-6, flags=fv.NO_LATTICE)
+    assert rep["prec_bits"] == 32 and rep["lattice"] == 0
     assert oracle.rel_l2(v, oracle.direct_problem(q)) <= 1e-6
 
 
