@@ -326,6 +326,15 @@ fv_status fv_simulate_mfma_noalloc(const fv_problem *p, double *vis, void *strea
  * ticket. */
 fv_status fv_server_start(fv_ctx *ctx, int max_slots);
 fv_status fv_submit(fv_ctx *ctx, const fv_problem *p, double *vis, uint64_t *ticket);
+/* A request whose arrays are on the device (device pointers in *p, vis as for
+ * fv_simulate_dev), so that a serving loop can keep inputs resident.  The
+ * call copies the antenna positions and frequencies back (two small blocking
+ * copies) to size the request's footprint, with the source box taken as the
+ * whole direction cube; the request runs on its slot's stream: input check,
+ * planning, transform, then the slot waits for it.  The buffers stay alive
+ * until fv_wait returns.  Errors as fv_submit, and argument errors as
+ * fv_simulate_dev. */
+fv_status fv_submit_dev(fv_ctx *ctx, const fv_problem *p, double *vis, uint64_t *ticket);
 /* timeout_s < 0 waits forever.  rep (nullable) receives the request's report
  * with t_total_ms = submit -> completion latency. */
 fv_status fv_wait(fv_ctx *ctx, uint64_t ticket, double timeout_s, fv_report *rep);

@@ -48,7 +48,7 @@ def timing_stage(stage) -> int:
 ABI_SYMBOLS = ("fv_create", "fv_destroy", "fv_last_error", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch",
                "fv_server_start", "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages",
                "fv_simulate_drift", "fv_simulate_beams", "fv_simulate_polar", "fv_simulate_basis",
-               "fv_stage_times", "fv_simulate_mfma_noalloc", "fv_simulate_batch_dev")
+               "fv_stage_times", "fv_simulate_mfma_noalloc", "fv_simulate_batch_dev", "fv_submit_dev")
 
 
 
@@ -157,6 +157,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_simulate_dev.argtypes = [vp, P(Problem), vp, vp, P(Report)]
     lib.fv_simulate_batch.argtypes = [vp, ctypes.c_int, P(Problem), P(vp), P(Report)]
     lib.fv_simulate_batch_dev.argtypes = [vp, ctypes.c_int, P(Problem), P(vp), vp, P(Report)]
+    lib.fv_submit_dev.argtypes = [vp, P(Problem), vp, P(ctypes.c_uint64)]
     lib.fv_server_start.argtypes = [vp, ctypes.c_int]
     lib.fv_submit.argtypes = [vp, P(Problem), vp, P(ctypes.c_uint64)]
     lib.fv_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, P(Report)]
@@ -171,7 +172,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fv_simulate_mfma_noalloc.argtypes = [P(Problem), vp, vp]
     lib.fv_simulate_mfma_noalloc.restype = ctypes.c_int
     for name in ("fv_create", "fv_simulate", "fv_simulate_dev", "fv_simulate_batch", "fv_simulate_batch_dev",
-                 "fv_server_start",
+                 "fv_submit_dev", "fv_server_start",
                  "fv_submit", "fv_wait", "fv_server_stop", "fv_set_tune_cache", "fv_debug_stages"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -466,6 +467,14 @@ class Context:
     # ------------------------------------------------------------------ serving
     def server_start(self, max_slots: int = 4):
         _check(_lib.fv_server_start(self._h, int(max_slots)))
+
+    def submit_dev(self, ant_enu, src_lmn, freq_hz, flux, beam, vis, eps: float = 1e-6, flags: int = 0) -> int:
+        """Submits a request whose arrays are torch device tensors (as for
+        simulate_dev); the tensors must stay alive until wait() returns."""
+        c = _dev_problem(ant_enu, src_lmn, freq_hz, flux, beam, vis, eps, flags)
+        t = ctypes.c_uint64()
+        _check(_lib.fv_submit_dev(self._h, ctypes.byref(c), vis.data_ptr(), ctypes.byref(t)))
+        return int(t.value)
 
     def submit(self, hp: HostProblem, out: np.ndarray) -> int:
         t = ctypes.c_uint64()

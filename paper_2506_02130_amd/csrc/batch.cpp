@@ -203,11 +203,7 @@ void simulate_batch_dev(fv_ctx *ctx, int n, const fv_problem *ps, double *const 
     if (n > 65535) fail(FV_EUNSUPPORTED, "more than 65535 problems in one device batch");
     for (int i = 0; i < n; ++i) {
         const fv_problem &p = ps[i];
-        if (!vis[i]) fail(FV_EINVAL, "null output pointer in batch");
-        if ((uintptr_t)vis[i] & 15) fail(FV_EINVAL, "the outputs must be 16-byte aligned");
-        if (p.n_ant < 1 || p.n_src < 0 || p.n_freq < 1) fail(FV_EINVAL, "bad sizes");
-        if (!p.ant_enu || !p.freq_hz || (p.n_src > 0 && (!p.src_lmn || !p.flux))) fail(FV_EINVAL, "null device array");
-        if (!(p.eps >= 1e-14 && p.eps <= 1e-1)) fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
+        check_dev_args(p, vis[i]);
         if ((p.flags & FV_PREC_MASK) == FV_PREC_FP32 && p.eps < 1e-6)
             fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
     }
@@ -329,24 +325,9 @@ void simulate_batch_dev(fv_ctx *ctx, int n, const fv_problem *ps, double *const 
         std::vector<DevInputs> in(n);
         for (int i = 0; i < n; ++i) {
             const fv_problem &p = ps[i];
-            const double *chk = pin + hoff[i], *pf = chk + 8, *pa = pf + p.n_freq;
-            freq[i].assign(pf, pf + p.n_freq);
-            ant[i].assign(pa, pa + 3 * (size_t)p.n_ant);
-            for (double a : ant[i])
-                if (!std::isfinite(a)) fail(FV_EINVAL, "non-finite antenna position");
-            for (double f : freq[i])
-                if (!(std::isfinite(f) && f > 0)) fail(FV_EINVAL, "frequency must be finite and > 0");
-            if (p.n_src > 0 && (chk[6] != 0.0 || chk[7] != 0.0))
-                fail(FV_EINVAL, "invalid source directions or strengths");
+            dims[i] = check_dev_scalars(p, pin + hoff[i], ant[i], freq[i], box[i].data());
             meta[i].ant_enu = ant[i].data();
             meta[i].freq_hz = freq[i].data();
-            dims[i] = choose_dim(ant[i].data(), p.n_ant, p.eps, freq[i].data(), p.n_freq, p.flags);
-            box[i].fill(0.0);
-            if (p.n_src > 0)
-                for (int a = 0; a < dims[i]; ++a) {
-                    box[i][a] = 0.5 * (chk[2 * a] + chk[2 * a + 1]);
-                    box[i][3 + a] = 0.5 * (chk[2 * a + 1] - chk[2 * a]);
-                }
             in[i] = dev_inputs(i, box[i].data());
         }
         if (ran) {

@@ -36,6 +36,7 @@ struct Slot {
     Arena arena;   // NUFFT workspace
     Arena inputs;  // uploaded inputs and the device output
     Arena lat;     // workspace of batched lattice launches
+    PinnedBuf pin; // host staging of a device request's planning scalars
     StageTimer timer;
     GraphCache graphs;  // launch graphs captured on this slot's workspace
     // end of the last call's work on the caller's stream (device entry
@@ -119,6 +120,17 @@ void validate_host(const fv_problem *p);
 DevInputs upload(Slot &slot, const fv_problem *p, double *s_c, double *S);
 void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevInputs &in, double *vis_dev,
                 fv_report *rep);
+// Argument checks of a problem whose arrays are on the device.
+void check_dev_args(const fv_problem &p, const double *vis);
+// Host side of the device input check: hdr holds the 8 check values, the
+// frequencies and the antenna positions (launch_validate's first doubles).
+// Fails on invalid values; fills the host copies and the source box (centre,
+// half-width per axis); returns the dimension choice.
+int check_dev_scalars(const fv_problem &p, const double *hdr, std::vector<double> &ant, std::vector<double> &freq,
+                      double box[6]);
+// A problem with device arrays on `slot` (its stream, workspaces and staging),
+// blocking until done: the serving loop's device requests.
+void simulate_dev_sync(fv_ctx *ctx, Slot &slot, const fv_problem &p, double *vis, fv_report *rep);
 
 // Kernel family of a group of NUFFT jobs.
 struct NufftGroupKey {
@@ -163,7 +175,9 @@ bool run_lattice(fv_ctx *ctx, Slot &slot, const fv_problem &p, const DevInputs &
                  StageTimer *tm, fv_report &r);
 void simulate_host(fv_ctx *ctx, Slot &slot, const fv_problem *p, double *vis, fv_report *rep);
 void server_free(Server *s);  // stops the workers (cancelling queued requests) and frees
-size_t request_footprint(fv_ctx *ctx, const fv_problem &p);
+// src_on_host false: the source box is taken as the whole direction cube (a
+// device request, whose directions the host does not hold).
+size_t request_footprint(fv_ctx *ctx, const fv_problem &p, bool src_on_host = true);
 void simulate_batch(fv_ctx *ctx, Slot &slot, int n, const fv_problem *ps, double *const *vis, fv_report *rep);
 // Problems whose inputs are on the device: meta[i] holds host copies of the
 // antenna positions and frequencies, in[i] the device arrays, source box and

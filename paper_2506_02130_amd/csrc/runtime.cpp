@@ -236,6 +236,7 @@ Slot::~Slot() {
     arena.host.release();
     inputs.host.release();
     lat.host.release();
+    pin.release();
     arena.release();
     inputs.release();
     lat.release();
@@ -554,6 +555,74 @@ void fill_report(StageTimer &tm, fv_report &r) {
     }
 }
 
+int check_dev_scalars(const fv_problem &p, const double *hdr, std::vector<double> &ant, std::vector<double> &freq,
+                      double box[6]) {
+    const double *pf = hdr + 8, *pa = pf + p.n_freq;
+    freq.assign(pf, pf + p.n_freq);
+    ant.assign(pa, pa + 3 * (size_t)p.n_ant);
+    for (double a : ant)
+        if (!std::isfinite(a)) fail(FV_EINVAL, "non-finite antenna position");
+    for (double f : freq)
+        if (!(std::isfinite(f) && f > 0)) fail(FV_EINVAL, "frequency must be finite and > 0");
+    if (p.n_src > 0 && (hdr[6] != 0.0 || hdr[7] != 0.0)) fail(FV_EINVAL, "invalid source directions or strengths");
+    if ((p.flags & FV_PREC_MASK) == FV_PREC_FP32 && p.eps < 1e-6) fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
+    const int dim = choose_dim(ant.data(), p.n_ant, p.eps, freq.data(), p.n_freq, p.flags);
+    for (int a = 0; a < 6; ++a) box[a] = 0.0;
+    if (p.n_src > 0)
+        for (int a = 0; a < dim; ++a) {
+            box[a] = 0.5 * (hdr[2 * a] + hdr[2 * a + 1]);
+            box[3 + a] = 0.5 * (hdr[2 * a + 1] - hdr[2 * a]);
+        }
+    return dim;
+}
+
+void check_dev_args(const fv_problem &p, const double *vis) {
+    if (!vis) fail(FV_EINVAL, "null output pointer");
+    if ((uintptr_t)vis & 15) fail(FV_EINVAL, "the output must be 16-byte aligned");
+    if (p.n_ant < 1 || p.n_src < 0 || p.n_freq < 1) fail(FV_EINVAL, "bad sizes");
+    if (!p.ant_enu || !p.freq_hz || (p.n_src > 0 && (!p.src_lmn || !p.flux))) fail(FV_EINVAL, "null device array");
+    if (!(p.eps >= 1e-14 && p.eps <= 1e-1)) fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
+}
+
+void simulate_dev_sync(fv_ctx *ctx, Slot &slot, const fv_problem &p, double *vis, fv_report *rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    check_dev_args(p, vis);
+    FV_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = slot.stream;
+    const size_t nval = validate_doubles(p.n_ant, p.n_freq), nhdr = 8 + (size_t)p.n_freq + 3 * (size_t)p.n_ant;
+    slot.inputs.ensure(nval * sizeof(double) + 256);
+    slot.inputs.reset();
+    double *dev = (double *)slot.inputs.take(nval * sizeof(double));
+    double *pin = (double *)slot.pin.get(nhdr * sizeof(double));
+    launch_validate(p.src_lmn, p.n_src, p.flux, p.beam, p.n_freq, p.ant_enu, p.n_ant, p.freq_hz, dev, st);
+    FV_HIP(hipMemcpyAsync(pin, dev, nhdr * sizeof(double), hipMemcpyDeviceToHost, st));
+    FV_HIP(hipStreamSynchronize(st));
+    std::vector<double> ant, freq;
+    double box[6];
+    check_dev_scalars(p, pin, ant, freq, box);
+    fv_problem meta = p;
+    meta.ant_enu = ant.data();
+    meta.freq_hz = freq.data();
+    DevInputs in;
+    in.ant = p.ant_enu;
+    in.freq = p.freq_hz;
+    in.src = p.src_lmn;
+    in.flux = p.flux;
+    in.beam = p.beam;
+    in.vis = vis;
+    for (int a = 0; a < 3; ++a) {
+        in.s_c[a] = box[a];
+        in.S[a] = box[3 + a];
+    }
+    in.cmax = validate_partials(dev, p.n_ant, p.n_freq);
+    in.cmax_span = validate_span((long long)p.n_src * p.n_freq);
+    fv_report r;
+    run_device(ctx, slot, meta, in, vis, &r);
+    FV_HIP(hipStreamSynchronize(st));
+    r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+}
+
 // Everything the device path needs once the inputs are on the device and the
 // planning scalars (antenna positions, frequencies, source box) on the host.
 void run_device(fv_ctx *ctx, Slot &slot, const fv_problem &host_meta, const DevInputs &in, double *vis_dev,
@@ -731,11 +800,7 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     FV_GUARD_BEGIN
     auto t0 = std::chrono::steady_clock::now();
     if (!ctx || !p || !vis) fv::fail(FV_EINVAL, "null argument");
-    if ((uintptr_t)vis & 15) fv::fail(FV_EINVAL, "the output must be 16-byte aligned");
-    if (p->n_ant < 1 || p->n_src < 0 || p->n_freq < 1) fv::fail(FV_EINVAL, "bad sizes");
-    if (!p->ant_enu || !p->freq_hz || (p->n_src > 0 && (!p->src_lmn || !p->flux)))
-        fv::fail(FV_EINVAL, "null device array");
-    if (!(p->eps >= 1e-14 && p->eps <= 1e-1)) fv::fail(FV_EINVAL, "eps out of [1e-14, 1e-1]");
+    fv::check_dev_args(*p, vis);
     FV_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     // input check and planning scalars in one pass, one copy through pinned
@@ -792,26 +857,12 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
         } else {
             FV_HIP(hipStreamSynchronize(st));
         }
-        double *host_chk = pin, *pfreq = pin + 8, *pant = pfreq + p->n_freq;
-        const std::vector<double> ant(pant, pant + n_ant3), freq(pfreq, pfreq + p->n_freq);
+        std::vector<double> ant, freq;
+        double box[6];
+        const int dim = fv::check_dev_scalars(*p, pin, ant, freq, box);
         fv_problem meta = *p;
         meta.ant_enu = ant.data();
         meta.freq_hz = freq.data();
-        for (double a : ant)
-            if (!std::isfinite(a)) fv::fail(FV_EINVAL, "non-finite antenna position");
-        for (double f : freq)
-            if (!(std::isfinite(f) && f > 0)) fv::fail(FV_EINVAL, "frequency must be finite and > 0");
-        if (p->n_src > 0 && (host_chk[6] != 0.0 || host_chk[7] != 0.0))
-            fv::fail(FV_EINVAL, "invalid source directions or strengths");
-        if ((p->flags & FV_PREC_MASK) == FV_PREC_FP32 && p->eps < 1e-6)
-            fv::fail(FV_EUNSUPPORTED, "FP32 grids need eps >= 1e-6");
-        const int dim = fv::choose_dim(ant.data(), p->n_ant, p->eps, freq.data(), p->n_freq, p->flags);
-        double box[6] = {0, 0, 0, 0, 0, 0};
-        if (p->n_src > 0)
-            for (int a = 0; a < dim; ++a) {
-                box[a] = 0.5 * (host_chk[2 * a] + host_chk[2 * a + 1]);
-                box[3 + a] = 0.5 * (host_chk[2 * a + 1] - host_chk[2 * a]);
-            }
         const fv::DevInputs in = dev_inputs(box);
         if (ran) {
             // the speculation holds when the geometry is the last call's and its

@@ -22,6 +22,7 @@ struct Request {
     uint64_t id = 0;
     fv_problem p;
     double *vis = nullptr;
+    bool dev = false;  // arrays (and vis) on the device
     size_t footprint = 0;
     Clock::time_point t_submit;
     bool done = false;
@@ -46,14 +47,16 @@ struct Server {
 
 // Bytes a request holds on the device while it runs (footprint_bytes, with
 // the geometry plan from the context's cache).
-size_t request_footprint(fv_ctx *ctx, const fv_problem &p) {
+// With src_on_host false the whole direction cube is an upper bound of the
+// grid, and so of the footprint.
+size_t request_footprint(fv_ctx *ctx, const fv_problem &p, bool src_on_host) {
     const int dim = choose_dim(p.ant_enu, p.n_ant, p.eps, p.freq_hz, p.n_freq, p.flags);
     const int prec = choose_prec(p.eps, p.flags);
     const size_t cap = std::max<size_t>(ctx->chunk_bytes, 1 << 20);
     GeomPlan g;
     if (p.n_src > 0 && (p.flags & FV_METHOD_MASK) == FV_METHOD_NUFFT) {
-        double s_c[3], S[3];
-        src_box(p.src_lmn, p.n_src, dim, s_c, S);
+        double s_c[3] = {0, 0, 0}, S[3] = {1, 1, 1};
+        if (src_on_host) src_box(p.src_lmn, p.n_src, dim, s_c, S);
         g = ctx_geometry(ctx, p.ant_enu, p.n_ant, dim, p.eps, s_c, S, !(p.flags & FV_NO_FOLD));
     }
     return footprint_bytes(p, g, dim, prec, cap);
@@ -96,7 +99,10 @@ void worker(Server *S, Slot *slot) {
         fv_report rep;
         std::memset(&rep, 0, sizeof(rep));
         try {
-            simulate_host(S->ctx, *slot, &r->p, r->vis, &rep);
+            if (r->dev)
+                simulate_dev_sync(S->ctx, *slot, r->p, r->vis, &rep);
+            else
+                simulate_host(S->ctx, *slot, &r->p, r->vis, &rep);
         } catch (const Error &e) {
             st = e.code;
             err = e.msg;
@@ -196,6 +202,25 @@ fv_status fv_server_start(fv_ctx *ctx, int max_slots) {
     })
 }
 
+}  // extern "C"
+
+namespace {
+fv_status enqueue(fv_ctx *ctx, std::shared_ptr<Request> r, uint64_t *ticket) {
+    Server *S = ctx->server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stopped || S->stopping) fail(FV_EBUSY, "server not running");
+    if (S->queue.size() >= 65536) fail(FV_EBUSY, "queue full");
+    r->id = S->next_id++;
+    S->reqs[r->id] = r;
+    S->queue.push_back(r);
+    *ticket = r->id;
+    S->cv_work.notify_one();
+    return FV_OK;
+}
+}  // namespace
+
+extern "C" {
+
 fv_status fv_submit(fv_ctx *ctx, const fv_problem *p, double *vis, uint64_t *ticket) {
     FV_SERVER_GUARD({
         if (!ctx || !p || !vis || !ticket) fail(FV_EINVAL, "null argument");
@@ -207,14 +232,37 @@ fv_status fv_submit(fv_ctx *ctx, const fv_problem *p, double *vis, uint64_t *tic
         r->vis = vis;
         r->t_submit = Clock::now();
         r->footprint = request_footprint(ctx, *p);
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (S->queue.size() >= 65536) fail(FV_EBUSY, "queue full");
-        r->id = S->next_id++;
-        S->reqs[r->id] = r;
-        S->queue.push_back(r);
-        *ticket = r->id;
-        S->cv_work.notify_one();
-        return FV_OK;
+        return enqueue(ctx, r, ticket);
+    })
+}
+
+fv_status fv_submit_dev(fv_ctx *ctx, const fv_problem *p, double *vis, uint64_t *ticket) {
+    FV_SERVER_GUARD({
+        if (!ctx || !p || !ticket) fail(FV_EINVAL, "null argument");
+        Server *S = ctx->server;
+        if (!S || S->stopped || S->stopping) fail(FV_EBUSY, "server not running");
+        check_dev_args(*p, vis);
+        auto r = std::make_shared<Request>();
+        r->p = *p;
+        r->vis = vis;
+        r->dev = true;
+        r->t_submit = Clock::now();
+        // the footprint needs the array and the frequencies on the host: two
+        // small copies now (the full check runs on the request's slot)
+        FV_HIP(hipSetDevice(ctx->device));
+        std::vector<double> ant(3 * (size_t)p->n_ant);
+        std::vector<double> freq((size_t)p->n_freq);
+        FV_HIP(hipMemcpy(ant.data(), p->ant_enu, ant.size() * sizeof(double), hipMemcpyDeviceToHost));
+        FV_HIP(hipMemcpy(freq.data(), p->freq_hz, freq.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (double a : ant)
+            if (!std::isfinite(a)) fail(FV_EINVAL, "non-finite antenna position");
+        for (double f : freq)
+            if (!(std::isfinite(f) && f > 0)) fail(FV_EINVAL, "frequency must be finite and > 0");
+        fv_problem meta = *p;
+        meta.ant_enu = ant.data();
+        meta.freq_hz = freq.data();
+        r->footprint = request_footprint(ctx, meta, false);
+        return enqueue(ctx, r, ticket);
     })
 }
 

@@ -138,3 +138,58 @@ def test_wait_timeout_then_completion_and_bad_submit(gpu_lib):
         assert ei.value.status == fv.EINVAL
         assert c.wait(123456789)[0] == fv.EINVAL
         c.server_stop()
+
+
+def test_device_requests_mixed_with_host_requests(gpu_lib):
+    """Requests with device-resident inputs (fv_submit_dev) run in the same
+    serving mix as host requests; each result matches the oracle and its solo
+    device run, and a bad device request fails alone."""
+    import torch
+    fv = gpu_lib
+    probs = _mix()
+    dev = "cuda:0"
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    def dev_args(p):
+        return (t(p.ant_enu), t(p.src_lmn).reshape(-1, 3), t(p.freq_hz), t(p.flux.reshape(p.n_freq, p.n_src)),
+                None if p.beam is None else t(p.beam))
+
+    with fv.Context(0) as c:
+        args = [dev_args(p) for p, _, _ in probs]
+        vis = [torch.zeros((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev) for p, _, _ in probs]
+        solo = []
+        for (p, e, f), a in zip(probs, args):
+            v = torch.zeros((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+            c.simulate_dev(*a, v, eps=e, flags=f)
+            torch.cuda.synchronize()
+            solo.append(v.cpu().numpy())
+        hps = [fv.HostProblem.of(p, eps=e, flags=f) for p, e, f in probs]
+        houts = [_out(p) for p, _, _ in probs]
+        c.server_start(3)
+        tickets = []
+        for i, ((p, e, f), a, v) in enumerate(zip(probs, args, vis)):
+            tickets.append(c.submit_dev(*a, v, eps=e, flags=f))
+            if i % 2 == 0:
+                tickets.append(c.submit(hps[i], houts[i]))
+        # a device request with a NaN flux fails on its own
+        bad = dev_args(probs[0][0])
+        bad[3][0, 0] = float("nan")
+        bv = torch.zeros_like(vis[0])
+        tb = c.submit_dev(*bad, bv, eps=1e-6)
+        for tk in tickets:
+            st, rep = c.wait(tk)
+            assert st == 0
+        st, _ = c.wait(tb)
+        assert st == -1
+        torch.cuda.synchronize()
+        for (p, e, f), v, s in zip(probs, vis, solo):
+            got = v.cpu().numpy()
+            if p.n_src == 0:
+                assert np.all(got == 0)
+                continue
+            assert oracle.rel_l2(_c(got), oracle.direct_problem(p)) <= e, p.name
+            assert oracle.rel_l2(_c(got), _c(s)) <= max(e / 10, 1e-13), p.name
+        for i, (p, e, f) in enumerate(probs):
+            if i % 2 == 0 and p.n_src:
+                assert oracle.rel_l2(_c(houts[i]), oracle.direct_problem(p)) <= e, p.name
+        c.server_stop()
