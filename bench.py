@@ -50,6 +50,18 @@ PATH_SOURCES = {"type1": ["lattice.hip", "dev_common.h"],
                           "nufft_f64_3d.hip", "dev_common.h"]}
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def _kernel_source_hash(files=None) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2506_02130_amd", "csrc")
@@ -163,54 +175,165 @@ def stats_md(path: str):
               f"{100 * int(r['TotalDurationNs']) / tot:.1f} |")
 
 
-def serving_leg(fv, synth, np, n_req: int) -> dict:
+def overlap_md(path: str) -> None:
+    """Kernel concurrency across streams in a kernel trace: per stream, the
+    union of its kernels' intervals; then the time during which 1, 2, ...
+    streams have a kernel running.  The plain paths run on one stream; the
+    server's slots each have their own."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    by = {}
+    for r in rows:
+        by.setdefault(r["Stream_Id"], []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    ev = []
+    for sid, iv in by.items():
+        iv.sort()
+        cs, ce = iv[0]
+        for a, b in iv[1:]:
+            if a > ce:
+                ev += [(cs, 1), (ce, -1)]
+                cs, ce = a, b
+            else:
+                ce = max(ce, b)
+        ev += [(cs, 1), (ce, -1)]
+    ev.sort()
+    hist, cur, last = {}, 0, None
+    for t, d in ev:
+        if last is not None and cur > 0:
+            hist[cur] = hist.get(cur, 0) + (t - last)
+        cur += d
+        last = t
+    busy = sum(hist.values())
+    print(f"Kernel trace `{os.path.basename(path)}`: {len(rows)} kernels on {len(by)} streams; "
+          f"GPU time with at least one kernel running: {busy / 1e6:.1f} ms.\n")
+    print("| streams with a kernel running | ms | share of busy time |")
+    print("|---|---|---|")
+    for k in sorted(hist):
+        print(f"| {k} | {hist[k] / 1e6:.1f} | {100 * hist[k] / busy:.1f}% |")
+    per = sorted(((sum(b - a for a, b in iv), sid, len(iv)) for sid, iv in by.items()), reverse=True)
+    print("\n| stream | kernels | kernel ms (sum of durations) |")
+    print("|---|---|---|")
+    for tot, sid, n in per:
+        print(f"| {sid} | {n} | {tot / 1e6:.1f} |")
+
+
+def serving_leg(fv, synth, np, torch, n_req: int, slots: int = 4) -> dict:
     """The serving mix: the first n_req requests of the seeded request stream
-    (hex arrays of 37-350 antennas, 1e3-1e6 sources, 1-64 frequencies, eps in
-    {1e-4, 1e-6, 1e-10}), host buffers.  The plain path runs them one after
-    the other; the server then replays them with Poisson arrivals at 0.7 of
-    the plain path's measured capacity.  Latency = arrival (submit) to
-    completion."""
+    (hex arrays of 37-350 antennas, log-uniform 1e3-1e6 sources, 1-64
+    frequencies, eps in {1e-4, 1e-6, 1e-10}, Poisson arrivals at 100 Hz),
+    drawn on the device.  One arrival trace is replayed by a single-stream FIFO
+    of plain blocking calls and by the server, each once with host buffers and
+    once with device-resident inputs; a saturation run then submits every
+    request at t = 0 to each.  Latency = completion - scheduled arrival, so
+    queueing counts in every mode.  gpu_busy_ms sums each request's stage
+    event time; above the makespan it shows requests overlapping on the device."""
     reqs = synth.config5_requests(n_req)
-    probs = [r.materialize() for r in reqs]
-    hps = [fv.HostProblem.of(q) for q in probs]
-    pairs = sum(float(q.n_src) * q.n_pairs * q.n_freq for q in probs)
-    with fv.Context(0) as c:
-        for h in hps[:4]:
-            c.simulate_problem(h)  # warm: tables and code objects
-        t0 = time.perf_counter()
-        plain_lat = []
-        for h in hps:
-            ta = time.perf_counter()
-            c.simulate_problem(h)
-            plain_lat.append((time.perf_counter() - ta) * 1e3)
-        t_plain = time.perf_counter() - t0
-        rate = 0.7 * len(hps) / t_plain
-        rng = np.random.default_rng(np.random.PCG64(2506021305))
-        arrive = np.cumsum(rng.exponential(1.0 / rate, len(hps)))
-        arrive -= arrive[0]
-        outs = [np.empty((q.n_freq, q.n_pairs, 2)) for q in probs]
-        c.server_start(4)
-        tickets = []
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    din = [r.materialize_torch(dev) for r in reqs]
+    torch.cuda.synchronize()
+    hin = [tuple(x.cpu().numpy() for x in d) for d in din]
+    t_mat = time.perf_counter() - t0
+    npair = [r.n_ant * (r.n_ant + 1) // 2 for r in reqs]
+    pairs = sum(float(r.n_src) * q * r.n_freq for r, q in zip(reqs, npair))
+    trace = np.array([r.arrival_s for r in reqs])
+    hps = [fv.HostProblem(*h, eps=r.eps, flags=fv.TIMING) for h, r in zip(hin, reqs)]
+    houts = [np.empty((r.n_freq, q, 2)) for r, q in zip(reqs, npair)]
+    douts = [torch.empty((r.n_freq, q, 2), dtype=torch.float64, device=dev) for r, q in zip(reqs, npair)]
+    in_bytes = sum(sum(x.numel() * 8 for x in d) for d in din)
+
+    def summary(lat_ms, done_s, busy_ms, arr):
+        span = max(done_s) - min(arr)
+        return {"pairs_per_s": pairs / span, "makespan_s": span,
+                "latency_ms": {"p50": _pct(lat_ms, 0.5), "p90": _pct(lat_ms, 0.9), "p99": _pct(lat_ms, 0.99)},
+                "gpu_busy_ms": busy_ms, "gpu_busy_over_makespan": busy_ms * 1e-3 / span}
+
+    st = torch.cuda.Stream(device=dev)
+
+    def plain(arr, device=False):
+        lat, done, busy = [], [], 0.0
         ts = time.perf_counter()
-        for h, o, at in zip(hps, outs, arrive):
-            dt = ts + at - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            tickets.append(c.submit(h, o))
-        lat = []
-        for t in tickets:
-            st, rep = c.wait(t)
+        for k, at in enumerate(arr):
+            now = time.perf_counter() - ts
+            if now < at:
+                time.sleep(at - now)
+            if device:
+                a = din[k]
+                rep = c.simulate_dev(a[0], a[1], a[2], a[3], a[4], douts[k], eps=reqs[k].eps, flags=fv.TIMING,
+                                     stream=st)
+                st.synchronize()
+            else:
+                rep = c.simulate_into(hps[k], houts[k])
+            t_done = time.perf_counter() - ts
+            lat.append((t_done - at) * 1e3)
+            done.append(t_done)
+            busy += sum(rep["t_stage_ms"])
+        return summary(lat, done, busy, arr)
+
+    def served(arr, device):
+        c.server_start(slots)
+        sub = []
+        ts = time.perf_counter()
+        for k, at in enumerate(arr):
+            now = time.perf_counter() - ts
+            if now < at:
+                time.sleep(at - now)
+            t_sub = time.perf_counter() - ts
+            if device:
+                a = din[k]
+                tk = c.submit_dev(a[0], a[1], a[2], a[3], a[4], douts[k], eps=reqs[k].eps, flags=fv.TIMING)
+            else:
+                tk = c.submit(hps[k], houts[k])
+            sub.append((tk, t_sub))
+        lat, done, busy = [], [], 0.0
+        for k, (tk, t_sub) in enumerate(sub):
+            st, rep = c.wait(tk)
             if st != 0:
-                raise RuntimeError(f"serving request failed with status {st}")
-            lat.append(rep["t_total_ms"])
-        t_serve = time.perf_counter() - ts
+                raise RuntimeError(f"serving request {k} failed with status {st}")
+            t_done = t_sub + rep["t_total_ms"] * 1e-3
+            lat.append((t_done - arr[k]) * 1e3)
+            done.append(t_done)
+            busy += sum(rep["t_stage_ms"])
         c.server_stop()
-    return {"requests": len(hps), "slots": 4, "arrival_rate_hz": rate, "pairs": pairs,
-            "latency_ms": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99)},
-            "pairs_per_s": pairs / t_serve,
-            "plain": {"pairs_per_s": pairs / t_plain,
-                      "latency_ms": {"p50": _pct(plain_lat, 0.5), "p99": _pct(plain_lat, 0.99)}},
-            "note": "host buffers (PCIe included); latency from submit to completion"}
+        return summary(lat, done, busy, arr)
+
+    with fv.Context(0) as c:
+        seen = set()
+        for k, r in enumerate(reqs):  # warm: code objects and the tables of each (array, eps)
+            if (r.n_ant, r.eps) not in seen:
+                seen.add((r.n_ant, r.eps))
+                c.simulate_into(hps[k], houts[k])
+        res = {"trace": {"plain_fifo": plain(trace), "server_host": served(trace, False),
+                         "plain_fifo_device": plain(trace, True), "server_device": served(trace, True)}}
+        zero = np.zeros_like(trace)
+        res["saturation"] = {"plain_fifo": plain(zero), "server_host": served(zero, False),
+                             "plain_fifo_device": plain(zero, True), "server_device": served(zero, True)}
+    torch.cuda.synchronize()
+    for m in ("trace", "saturation"):
+        for k in res[m].values():
+            k.pop("latency_ms") if m == "saturation" else None
+    res.update({"requests": len(reqs), "slots": slots, "arrival_rate_hz": len(reqs) / float(trace[-1] - trace[0]),
+                "pairs": pairs, "input_bytes": in_bytes, "materialize_s": t_mat,
+                "mix": {"n_ant": [min(r.n_ant for r in reqs), max(r.n_ant for r in reqs)],
+                        "n_src": [min(r.n_src for r in reqs), max(r.n_src for r in reqs)],
+                        "n_freq": [min(r.n_freq for r in reqs), max(r.n_freq for r in reqs)],
+                        "eps": sorted({r.eps for r in reqs})},
+                "note": "plain_fifo: one blocking fv_simulate per request in arrival order on one stream; "
+                        "plain_fifo_device: the same with fv_simulate_dev on inputs resident in HBM; "
+                        "server_host: fv_submit with host buffers (PCIe in the latency); server_device: "
+                        "fv_submit_dev with inputs resident in HBM; latency from scheduled arrival to "
+                        "completion; saturation: all requests at t = 0"})
+    return res
+
+
+def print_serving(res: dict) -> None:
+    for mode in ("trace", "saturation"):
+        for k, v in res[mode].items():
+            lat = v.get("latency_ms")
+            print(f"bench: serving {mode} {k}: {v['pairs_per_s']:.3e} pairs/s, makespan {v['makespan_s']:.2f} s, "
+                  f"GPU busy/makespan {v['gpu_busy_over_makespan']:.2f}"
+                  + (f", p50 {lat['p50']:.1f} ms p99 {lat['p99']:.1f} ms" if lat else ""), file=sys.stderr,
+                  flush=True)
 
 
 def batch_device_leg(fv, probs, np, torch, stream, tune) -> dict:
@@ -425,7 +548,11 @@ def main():
                     help="after the steps, one device copy of this many MiB (reference for byte counters)")
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
-    ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving mix leg")
+    ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving mix leg")
+    ap.add_argument("--only", choices=("serving",), help="run one extra leg alone (for a profiler) and print it")
+    ap.add_argument("--overlap-md", metavar="KERNEL_TRACE_CSV",
+                    help="no run: print how much of the serving slots' kernel time overlaps across streams, "
+                         "from a rocprofv3 --kernel-trace CSV of a --only serving run")
     ap.add_argument("--path", choices=("type3", "auto"), default="type3",
                     help="type3: the type-3 NUFFT (every step of the hot path; the default); auto: the "
                          "library's choice, which is the type-1 path for this lattice array")
@@ -436,6 +563,9 @@ def main():
     args = ap.parse_args()
     if args.stats_md:
         stats_md(args.stats_md)
+        return
+    if args.overlap_md:
+        overlap_md(args.overlap_md)
         return
     if args.reduce_traffic:
         cmd = ("rocprofv3 --pmc COUNTER --output-format csv -d <out> -o run -- python3 bench.py --profile "
@@ -463,6 +593,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.only == "serving":
+        res = serving_leg(fv, synth, np, torch, args.serve_requests)
+        print_serving(res)
+        print(json.dumps({"serving": res}))
+        return
     dev = torch.device("cuda:0")
     p = synth.config2(n_src=args.n_src, n_freq=args.n_freq)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
@@ -555,7 +690,7 @@ def main():
         tc1 = time.perf_counter()
         cpu_pairs = float(p.n_src) * len(sub) * len(fsel)
         cpu = {"value": cpu_pairs / (tc1 - tc0), "unit": "src×baseline pairs/s", "cores": threads,
-               "kind": "oracle", "sample": f"{len(sub)} seeded pairs x {p.n_src} sources x {len(fsel)} of "
+               "cpu_model": _cpu_model(), "kind": "oracle", "sample": f"{len(sub)} seeded pairs x {p.n_src} sources x {len(fsel)} of "
                                            f"{p.n_freq} frequencies ({cpu_pairs:.2e} pairs, {tc1 - tc0:.1f} s)"}
         out = vis.cpu().numpy()
         got = out[fsel][:, sub, 0] + 1j * out[fsel][:, sub, 1]
@@ -656,7 +791,8 @@ def main():
               f"{tb * 1e3:.1f} ms (host buffers), {extras['batch_config4_device']['ms']:.2f} ms wall, "
               f"{extras['batch_config4_device']['gpu_stage_ms']:.2f} ms GPU stages (inputs in HBM, captured)",
               file=sys.stderr, flush=True)
-        extras["serving"] = serving_leg(fv, synth, np, args.serve_requests)
+        extras["serving"] = serving_leg(fv, synth, np, torch, args.serve_requests)
+        print_serving(extras["serving"])
         extras["disk1000_3d"] = disk3d_leg(fv, synth, np, torch, stream)
         extras["drift_config4"] = drift_leg(fv, synth, np, torch, stream)
         extras.update(multivector_legs(fv, synth, np, torch, stream))

@@ -269,6 +269,16 @@ class Context:
         hp = HostProblem(ant_enu, src_lmn, freq_hz, flux, beam, eps, flags)
         return self.simulate_problem(hp)
 
+    def simulate_into(self, hp: HostProblem, out: np.ndarray) -> dict:
+        """fv_simulate into a caller's float64 [n_freq, n_pairs, 2] array;
+        returns the report."""
+        if out.dtype != np.float64 or not out.flags.c_contiguous or out.size != 2 * hp.freq.shape[0] * hp.n_pairs:
+            raise ValueError("out must be a contiguous float64 [n_freq, n_pairs, 2] array")
+        rep = Report()
+        _check(_lib.fv_simulate(self._h, ctypes.byref(hp.c), out.ctypes.data, ctypes.byref(rep)))
+        self.last_report = rep.as_dict()
+        return self.last_report
+
     def simulate_problem(self, hp: HostProblem) -> np.ndarray:
         out = np.empty((hp.freq.shape[0], hp.n_pairs, 2), dtype=np.float64)
         rep = Report()

@@ -324,6 +324,35 @@ class Request:
         return Problem(f"req{self.rid}", ant, src, freq, flux, gaussian_beam(src, freq), self.eps)
 
 
+    def materialize_torch(self, device):
+        """The same request drawn on a torch device (for large serving runs):
+        the distributions of materialize(), from a torch generator seeded with
+        the request's seed, so the values differ from materialize()'s.
+        Returns (ant, src, freq, flux, beam) float64 tensors."""
+        import torch
+        g = torch.Generator(device=device)
+        g.manual_seed(self.seed)
+        f64 = dict(dtype=torch.float64, device=device)
+        ant = torch.from_numpy(hex_array(self.n_ant)).to(device)
+        up = 1.0 - torch.rand(self.n_src, generator=g, **f64)
+        ph = 2 * math.pi * torch.rand(self.n_src, generator=g, **f64)
+        rho = torch.sqrt(torch.clamp(1 - up * up, min=0.0))
+        src = torch.stack([rho * torch.cos(ph), rho * torch.sin(ph), up], dim=1)
+        src = src / torch.linalg.norm(src, dim=1, keepdim=True)
+        freq = (torch.linspace(100e6, 200e6, self.n_freq, **f64) if self.n_freq > 1
+                else torch.full((1,), 150e6, **f64))
+        a, smin, smax = -0.8, 0.01, 100.0  # slope -1.8 power law by inverse CDF
+        u = torch.rand(self.n_src, generator=g, **f64)
+        s150 = (smin ** a + u * (smax ** a - smin ** a)) ** (1.0 / a)
+        alpha = -0.8 + 0.2 * torch.randn(self.n_src, generator=g, **f64)
+        flux = s150[None, :] * (freq[:, None] / 150e6) ** alpha[None, :]
+        theta = torch.arccos(torch.clamp(src[:, 2], -1.0, 1.0))
+        sig = math.radians(10.0) * (150e6 / freq) / math.sqrt(8 * math.log(2))
+        beam = torch.exp(-theta[None, :] ** 2 / (2 * sig[:, None] ** 2))
+        beam[:, src[:, 2] <= 0] = 0.0
+        return ant, src.contiguous(), freq, flux.contiguous(), beam.contiguous()
+
+
 SERVING_ARRAYS = (37, 61, 91, 127, 169, 217, 271, 331, 350)
 
 
