@@ -549,7 +549,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving mix leg")
-    ap.add_argument("--only", choices=("serving",), help="run one extra leg alone (for a profiler) and print it")
+    ap.add_argument("--only", choices=("serving", "basis"), help="run one extra leg alone and print it")
     ap.add_argument("--overlap-md", metavar="KERNEL_TRACE_CSV",
                     help="no run: print how much of the serving slots' kernel time overlaps across streams, "
                          "from a rocprofv3 --kernel-trace CSV of a --only serving run")
@@ -597,6 +597,9 @@ def main():
         res = serving_leg(fv, synth, np, torch, args.serve_requests)
         print_serving(res)
         print(json.dumps({"serving": res}))
+        return
+    if args.only == "basis":
+        print(json.dumps(basis_leg(fv, synth, np, torch, torch.cuda.Stream())))
         return
     dev = torch.device("cuda:0")
     p = synth.config2(n_src=args.n_src, n_freq=args.n_freq)

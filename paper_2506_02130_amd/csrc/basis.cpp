@@ -3,8 +3,9 @@
 // with the basis's structure constants, and one type-3 transform per basis
 // function, planned at the top frequency, evaluates the result at every
 // frequency's baselines (all frequencies are targets of the one transform);
-// the basis expansion then gives the visibilities.  K transforms replace
-// n_freq of them.
+// the interpolation reads the K grids at each target's cells with one set of
+// weights and writes the basis expansion, the visibilities, directly.  K
+// transforms replace n_freq of them.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -101,13 +102,11 @@ void simulate_basis(fv_ctx *ctx, const fv_problem *p, int K, double *vis, hipStr
 
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     const size_t bM = 8 * M.size(), bd = 8 * d.size(), bv = 8 * (size_t)K * n_src + 8;
-    const size_t bF = 16 * (size_t)K * n_freq * n_pairs;
-    slot.inputs.ensure(al(bM) + al(bd) + al(bv) + al(bF) + 2048);
+    slot.inputs.ensure(al(bM) + al(bd) + al(bv) + 2048);
     slot.inputs.reset();
     double *M_dev = (double *)slot.inputs.take(bM);
     double *d_dev = (double *)slot.inputs.take(bd);
     double *v = (double *)slot.inputs.take(bv);
-    double *F = (double *)slot.inputs.take(bF);
     {
         char *h = (char *)slot.inputs.host.get(bM + bd);
         std::memcpy(h, M.data(), bM);
@@ -149,12 +148,19 @@ void simulate_basis(fv_ctx *ctx, const fv_problem *p, int K, double *vis, hipStr
                 j.n_src = n_src;
                 j.flux = v + (size_t)k * n_src;
                 j.beam = nullptr;
-                j.out = F + 2 * (size_t)k * n_freq * n_pairs;
+                j.out = vis;  // not written: the interpolation below writes vis directly
                 j.tt = tt.get();
                 jobs.push_back(j);
             }
-            r.model_bytes = execute_jobs(ctx, slot, jobs, key, &tm);
-            launch_basis_expand(M_dev, K, n_freq, n_pairs, F, vis, st);
+            // one launch group (all K grids are read per target): no workspace cap
+            ExecOpts opts;
+            opts.autotune = (p->flags & FV_AUTOTUNE) != 0;
+            opts.tunes = &ctx->tunes;
+            opts.graphs = &slot.graphs;
+            opts.basis_M = M_dev;
+            opts.basis_vis = vis;
+            opts.basis_np = n_pairs;
+            r.model_bytes = nufft_execute(jobs, dim, key.prec, key.w, slot.arena, ctx->cache, st, &tm, &opts);
             r.dim = dim;
             r.prec_bits = key.prec;
             r.w = g.w;

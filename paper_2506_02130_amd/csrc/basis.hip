@@ -1,11 +1,10 @@
 // Spectral basis (paper appendix A): per-source product coefficients in an
-// orthonormal spectral basis, and the expansion of the basis transforms back
-// to the frequencies.
+// orthonormal spectral basis.  (The expansion of the basis transforms back to
+// the frequencies is part of the interpolation, k_interp_basis.)
 //
 //   k_basis_coeffs  per source: s_hat = M^T flux, b_hat = M^T beam (M has
 //                   orthonormal columns, so (M^T M)^-1 M^T = M^T), then
 //                   v_k = sum_ij s_hat_i b_hat_j d_ijk (FP64)
-//   k_basis_expand  per (frequency, pair): V = sum_k M_qk F_k
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,48 +16,78 @@ namespace {
 
 constexpr int kMaxBasis = 16;
 
+// A workgroup takes 64 sources; its 4 wavefronts split the frequencies
+// (wavefront w takes q = w mod 4) so that each lane keeps several loads in
+// flight, then the partial projections meet in LDS and wavefront w forms the
+// outputs k = w mod 4.
 __global__ __launch_bounds__(256) void k_basis_coeffs(const double *M, const double *d, int n_freq, int K, int n_src,
                                                       const double *flux, const double *beam, double *v) {
-    extern __shared__ double sm[];  // M [n_freq][K], d [K][K][K]
-    double *sM = sm, *sd = sm + n_freq * K;
+    extern __shared__ double sm[];  // M [n_freq][K], d [K][K][K], partials [4][2K][64]
+    double *sM = sm, *sd = sm + n_freq * K, *part = sd + K * K * K;
     for (int i = threadIdx.x; i < n_freq * K; i += 256) sM[i] = M[i];
     for (int i = threadIdx.x; i < K * K * K; i += 256) sd[i] = d[i];
     __syncthreads();
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n_src) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s = blockIdx.x * 64 + lane;
+    const bool act = s < n_src;
     double sh[kMaxBasis], bh[kMaxBasis];
-    for (int i = 0; i < K; ++i) sh[i] = bh[i] = 0.0;
-    for (int q = 0; q < n_freq; ++q) {
-        const double f = flux[(size_t)q * n_src + s], b = beam ? beam[(size_t)q * n_src + s] : 1.0;
-        for (int i = 0; i < K; ++i) {
-            sh[i] += sM[q * K + i] * f;
-            bh[i] += sM[q * K + i] * b;
+#pragma unroll
+    for (int i = 0; i < kMaxBasis; ++i) sh[i] = bh[i] = 0.0;
+    if (act) {
+        constexpr int U = 4;  // frequencies per lane whose loads are issued together
+        for (int q0 = wave; q0 < n_freq; q0 += 4 * U) {
+            double f[U], b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + 4 * u;
+                f[u] = q < n_freq ? flux[(size_t)q * n_src + s] : 0.0;
+                b[u] = q < n_freq ? (beam ? beam[(size_t)q * n_src + s] : 1.0) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + 4 * u;
+                if (q >= n_freq) break;
+#pragma unroll
+                for (int i = 0; i < kMaxBasis; ++i)
+                    if (i < K) {
+                        sh[i] += sM[q * K + i] * f[u];
+                        bh[i] += sM[q * K + i] * b[u];
+                    }
+            }
         }
     }
-    for (int k = 0; k < K; ++k) {
-        double acc = 0.0;
-        for (int i = 0; i < K; ++i) {
-            double t = 0.0;
-            for (int j = 0; j < K; ++j) t += bh[j] * sd[(i * K + j) * K + k];
-            acc += sh[i] * t;
+#pragma unroll
+    for (int i = 0; i < kMaxBasis; ++i)
+        if (i < K) {
+            part[(wave * 2 * K + i) * 64 + lane] = sh[i];
+            part[(wave * 2 * K + K + i) * 64 + lane] = bh[i];
         }
+    __syncthreads();
+    if (!act) return;
+#pragma unroll
+    for (int i = 0; i < kMaxBasis; ++i)
+        if (i < K) {
+            double a = 0.0, c = 0.0;
+            for (int w = 0; w < 4; ++w) {
+                a += part[(w * 2 * K + i) * 64 + lane];
+                c += part[(w * 2 * K + K + i) * 64 + lane];
+            }
+            sh[i] = a;
+            bh[i] = c;
+        }
+    for (int k = wave; k < K; k += 4) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i)
+            if (i < K) {
+                double t = 0.0;
+#pragma unroll
+                for (int j = 0; j < kMaxBasis; ++j)
+                    if (j < K) t += bh[j] * sd[(i * K + j) * K + k];
+                acc += sh[i] * t;
+            }
         v[(size_t)k * n_src + s] = acc;
     }
-}
-
-__global__ __launch_bounds__(256) void k_basis_expand(const double *M, int K, int n_freq, long long n_pairs,
-                                                      const double2 *F, double2 *vis) {
-    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-    const int q = blockIdx.y;
-    if (p >= n_pairs) return;
-    double re = 0.0, im = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double m = M[q * K + k];
-        const double2 f = F[((size_t)k * n_freq + q) * n_pairs + p];
-        re += m * f.x;
-        im += m * f.y;
-    }
-    vis[(size_t)q * n_pairs + p] = make_double2(re, im);
 }
 
 }  // namespace
@@ -69,19 +98,11 @@ void launch_basis_coeffs(const double *M_dev, const double *d_dev, int n_freq, i
                          const double *beam, double *v, hipStream_t st) {
     if (n_src <= 0) return;
     if (K < 1 || K > kMaxBasis) fail(FV_EINVAL, "basis size out of range");
-    const size_t lds = sizeof(double) * ((size_t)n_freq * K + (size_t)K * K * K);
+    const size_t lds = sizeof(double) * ((size_t)n_freq * K + (size_t)K * K * K + (size_t)4 * 2 * K * 64);
     if (lds > 160 * 1024) fail(FV_EUNSUPPORTED, "basis tables exceed LDS (too many frequencies for this basis size)");
     ensure_lds((const void *)k_basis_coeffs, lds);
-    hipLaunchKernelGGL(k_basis_coeffs, dim3((unsigned)((n_src + 255) / 256)), dim3(256), lds, st, M_dev, d_dev, n_freq,
+    hipLaunchKernelGGL(k_basis_coeffs, dim3((unsigned)((n_src + 63) / 64)), dim3(256), lds, st, M_dev, d_dev, n_freq,
                        K, n_src, flux, beam, v);
-    FV_HIP(hipGetLastError());
-}
-
-void launch_basis_expand(const double *M_dev, int K, int n_freq, long long n_pairs, const double *F, double *vis,
-                         hipStream_t st) {
-    if (n_pairs <= 0) return;
-    hipLaunchKernelGGL(k_basis_expand, dim3((unsigned)((n_pairs + 255) / 256), (unsigned)n_freq), dim3(256), 0, st,
-                       M_dev, K, n_freq, n_pairs, (const double2 *)F, (double2 *)vis);
     FV_HIP(hipGetLastError());
 }
 

@@ -257,6 +257,13 @@ struct ExecOpts {
     GraphCache *graphs = nullptr;
     size_t cap = 0;          // > 0: refuse (set *too_big) when the workspace exceeds cap bytes
     bool det = false;        // deterministic record order in the spread (FV_DETERMINISTIC)
+    // spectral basis: the jobs are the K basis transforms of one plan and one
+    // target table (all n_freq frequencies' pairs); with basis_vis set, the
+    // interpolation writes vis[q][p] = sum_k M[q][k] V_k directly (K = the
+    // number of jobs, M [n_freq][K] on the device)
+    const double *basis_M = nullptr;
+    double *basis_vis = nullptr;
+    long long basis_np = 0;
 };
 
 // Lattice of a coplanar array (paper section 2.2.1): every antenna offset
@@ -419,14 +426,11 @@ void launch_beam_select(const double *tmp, const int *vec_dev, long long n_pairs
 void launch_polar_strengths(const double *stokes, const double *jones, long long n_fs, double *out, hipStream_t st);
 void launch_polar_combine(const double *tmp, long long n_fp, double *vis, hipStream_t st);
 // Spectral basis: v [K][n_src] = product coefficients of flux and beam (null
-// = 1) per source, from M [n_freq][K] (orthonormal columns) and d [K][K][K];
-// vis [n_freq][n_pairs] = sum_k M[q][k] F[k][q][pair] (complex).  K is at most
-// basis_max().
+// = 1) per source, from M [n_freq][K] (orthonormal columns) and d [K][K][K].
+// K is at most basis_max().
 int basis_max();
 void launch_basis_coeffs(const double *M_dev, const double *d_dev, int n_freq, int K, int n_src, const double *flux,
                          const double *beam, double *v, hipStream_t st);
-void launch_basis_expand(const double *M_dev, int K, int n_freq, long long n_pairs, const double *F, double *vis,
-                         hipStream_t st);
 constexpr int kFeBlock = 256;  // sources per workgroup of the front-end kernels
 int frontend_blocks(int n_src);
 

@@ -180,8 +180,10 @@ uint64_t graph_key(const Prepared &P, int n, int dim, int prec_bits, int w) {
     for (const void *p : {(const void *)P.B.snaps, (const void *)P.B.bins, (const void *)P.B.rank,
                           (const void *)P.B.recs, (const void *)P.B.ipsi, (const void *)P.B.grid,
                           (const void *)P.B.perm, (const void *)P.B.order_counts, (const void *)P.B.src_ord,
-                          (const void *)P.B.orders, (const void *)P.B.recs_tmp, (const void *)P.B.srcid})
+                          (const void *)P.B.orders, (const void *)P.B.recs_tmp, (const void *)P.B.srcid,
+                          (const void *)P.B.basis_M, (const void *)P.B.basis_vis})
         h = mix(h, (uint64_t)(uintptr_t)p);
+    h = mix(h, (uint64_t)P.B.basis_np);
     return h;
 }
 }  // namespace
@@ -209,6 +211,11 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
         if (have) layout = make_layout(jobs, dim, prec_bits, w, tune, det);
     }
     Prepared P = prepare_layout(std::move(layout), jobs, dim, prec_bits, w, arena, cache, st);
+    if (opts && opts->basis_vis) {
+        P.B.basis_M = opts->basis_M;
+        P.B.basis_vis = opts->basis_vis;
+        P.B.basis_np = opts->basis_np;
+    }
     const int n = (int)jobs.size();
     // graphs need a capturable (non-null) stream; per-stage timing stays eager
     const bool graph = opts && opts->graph && opts->graphs && st != nullptr && !(timer && timer->on);

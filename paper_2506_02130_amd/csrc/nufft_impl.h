@@ -996,20 +996,15 @@ __global__ __launch_bounds__(TPB) void k_fft(const SnapDev *snaps, int a, cplx<R
 // DEG: some snapshot of the launch has a clamped axis, whose psi1hat is
 // evaluated here by quadrature (a variant of its own: the quadrature's
 // registers would halve the occupancy of the common case).
-template <typename R, int D, int W, bool DEG>
-__global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, int n_snap, const cplx<R> *grid,
-                                                EsPoly ep) {
-    int bx, sy;
-    if (!snap_block(gx, n_snap, bx, sy)) return;
-    const SnapDev &S = snaps[sy];
-    const int t = bx * 256 + threadIdx.x;
-    if (t >= S.n_tgt) return;
-    const cplx<R> *g = grid + (D == 2 ? S.bufA : S.bufB);
+//
+// Kernel weights of target t of snapshot S: per axis the W weights and the
+// first cell of the window (from the window corner), and the target's
+// coordinates b.
+template <typename R, int D, int W>
+__device__ __forceinline__ void interp_weights(const SnapDev &S, int t, const EsPoly &ep, R (&kw)[D][W],
+                                               int (&p0)[3], double (&bb)[3]) {
     const R beta = (R)S.beta;
     const R inv_hw = (R)(2.0 / W);
-    double bb[3] = {0, 0, 0};
-    int p0[3] = {0, 0, 0};
-    R kw[D][W];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const double b = S.tb[(long long)a * S.n_tgt + t];
@@ -1032,7 +1027,14 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, in
             for (int i = 0; i < W; ++i) kw[a][i] = es_phi((R)((R)i - off) * inv_hw, beta);
         p0[a] = p + S.P[a];
     }
-    R ar = 0, ai = 0;
+}
+
+// The weighted sum of the W^D window cells of grid g (window dims of S).
+template <typename R, int D, int W>
+__device__ __forceinline__ void interp_sum(const SnapDev &S, const cplx<R> *g, const R (&kw)[D][W], const int (&p0)[3],
+                                           R &ar, R &ai) {
+    ar = 0;
+    ai = 0;
     const long long My = S.M[1], Mx = S.M[0];
 #pragma unroll 1
     for (int iz = 0; iz < (D == 3 ? W : 1); ++iz) {
@@ -1059,7 +1061,14 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, in
             ai = zi;
         }
     }
-    double fac = S.post_norm;
+}
+
+// Target t's factor after the sum: 1/psi1hat and the normalisation (fac),
+// and the centring phase as (cos, sin).
+template <int D, bool DEG>
+__device__ __forceinline__ void interp_post(const SnapDev &S, int t, const double (&bb)[3], double &fac, double &cs,
+                                            double &sn) {
+    fac = S.post_norm;
     double dot = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -1072,8 +1081,25 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, in
         fac /= ph;
         dot += bb[a] * S.s_c[a];
     }
-    double sn, cs;
     sincos_turns(S.post_turn * dot, &sn, &cs);
+}
+
+template <typename R, int D, int W, bool DEG>
+__global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, int n_snap, const cplx<R> *grid,
+                                                EsPoly ep) {
+    int bx, sy;
+    if (!snap_block(gx, n_snap, bx, sy)) return;
+    const SnapDev &S = snaps[sy];
+    const int t = bx * 256 + threadIdx.x;
+    if (t >= S.n_tgt) return;
+    R kw[D][W];
+    int p0[3] = {0, 0, 0};
+    double bb[3] = {0, 0, 0};
+    interp_weights<R, D, W>(S, t, ep, kw, p0, bb);
+    R ar, ai;
+    interp_sum<R, D, W>(S, grid + (D == 2 ? S.bufA : S.bufB), kw, p0, ar, ai);
+    double fac, cs, sn;
+    interp_post<D, DEG>(S, t, bb, fac, cs, sn);
     const double vr = (double)ar, vi = (double)ai;
     double re = fac * (vr * cs - vi * sn);
     double im = fac * (vr * sn + vi * cs);
@@ -1081,6 +1107,41 @@ __global__ __launch_bounds__(256) void k_interp(const SnapDev *snaps, int gx, in
     if (ti < 0) im = -im;
     double2 *o = (double2 *)S.out;
     o[ti & 0x7fffffff] = make_double2(re, im);
+}
+
+// Spectral basis (paper appendix A): the K snapshots of the launch are the K
+// basis transforms of one plan and one target table (every frequency's
+// baselines).  Per target the weights and the factor after the sum are
+// formed once; the K grids are read at the same cells and combined with the
+// basis values of the target's frequency q (vis = sum_k M[q][k] V_k), so the
+// visibilities are written directly, with no per-basis output.
+template <typename R, int D, int W, bool DEG>
+__global__ __launch_bounds__(256) void k_interp_basis(const SnapDev *snaps, int K, const cplx<R> *grid, EsPoly ep,
+                                                      const double *M, long long n_pairs, double2 *vis) {
+    const SnapDev &S = snaps[0];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= S.n_tgt) return;
+    R kw[D][W];
+    int p0[3] = {0, 0, 0};
+    double bb[3] = {0, 0, 0};
+    interp_weights<R, D, W>(S, t, ep, kw, p0, bb);
+    const int ti = S.tidx[t];
+    const long long o = ti & 0x7fffffff;
+    const double *Mq = M + (o / n_pairs) * K;
+    double re = 0.0, im = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+        R ar, ai;
+        interp_sum<R, D, W>(S, grid + (D == 2 ? snaps[k].bufA : snaps[k].bufB), kw, p0, ar, ai);
+        re += Mq[k] * (double)ar;
+        im += Mq[k] * (double)ai;
+    }
+    double fac, cs, sn;
+    interp_post<D, DEG>(S, t, bb, fac, cs, sn);
+    double vr = fac * (re * cs - im * sn);
+    double vi = fac * (re * sn + im * cs);
+    if (ti < 0) vi = -vi;
+    vis[o] = make_double2(vr, vi);
 }
 
 // Target table of one array geometry.
@@ -1149,6 +1210,11 @@ struct Bufs {
     OrderGroup *orders = nullptr;                  // device copy of Layout::orders
     void *recs_tmp = nullptr;                      // deterministic mode: records in scatter order
     int *srcid = nullptr;                          // deterministic mode: source index per scatter position
+    // spectral basis: the snapshots are the basis transforms of one plan, and
+    // the interpolation writes vis = sum_k M[q][k] V_k directly
+    const double *basis_M = nullptr;  // [n_freq][K]
+    double *basis_vis = nullptr;      // [n_freq][n_pairs] complex
+    long long basis_np = 0;
 };
 
 // Snapshot-per-XCD launches when the snapshots fill the 8 XCDs evenly enough
@@ -1290,7 +1356,16 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
         }
         tm->add(FV_STAGE_FFT_X + a, L.sbytes[FV_STAGE_FFT_X + a], 1);
     }
-    if ((stages & 4) && L.max_tgt) {
+    if ((stages & 4) && L.max_tgt && B.basis_vis) {
+        const dim3 g(blocks(L.snaps[0].n_tgt, 256));
+        if (L.any_degenerate)
+            launch_stage(tm, FV_STAGE_INTERP, k_interp_basis<R, D, W, true>, g, dim3(256), 0, st, snaps_dev, n_snap,
+                         (const cplx<R> *)grid, es_poly(W), B.basis_M, B.basis_np, (double2 *)B.basis_vis);
+        else
+            launch_stage(tm, FV_STAGE_INTERP, k_interp_basis<R, D, W, false>, g, dim3(256), 0, st, snaps_dev, n_snap,
+                         (const cplx<R> *)grid, es_poly(W), B.basis_M, B.basis_np, (double2 *)B.basis_vis);
+        tm->add(FV_STAGE_INTERP, L.sbytes[FV_STAGE_INTERP], 1);
+    } else if ((stages & 4) && L.max_tgt) {
         const long long gx = blocks(L.max_tgt, 256);
         if (L.any_degenerate)
             launch_stage(tm, FV_STAGE_INTERP, k_interp<R, D, W, true>, sgrid(gx), dim3(256), 0, st, snaps_dev,
