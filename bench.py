@@ -379,6 +379,45 @@ def batch_device_leg(fv, probs, np, torch, stream, tune) -> dict:
                     "checks the inputs on the device and waits once for the planning scalars"}
 
 
+def fp64_leg(fv, synth, np, torch, stream) -> dict:
+    """The 350-antenna workload at eps = 1e-10 (FP64 grids, the paper's own
+    arithmetic), type-3 path and the library's default (type-1) path: inputs in
+    HBM, best of two calls after a warm-up; rel l2 against the oracle's exact
+    sum on 512 seeded pairs x 4 frequencies."""
+    import oracle
+    p = synth.config2()
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    args = (g(p.ant_enu), g(p.src_lmn), g(p.freq_hz), g(p.flux), g(p.beam))
+    vis = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
+    sub = synth.subset_pairs(p.n_ant, 512, 11)
+    fsel = np.array([0, 21, 42, 63])
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    ref = oracle.direct_vis(p.ant_enu, p.src_lmn, p.freq_hz[fsel], p.flux[fsel], p.beam[fsel], pairs=sub,
+                            threads=threads)
+    pairs = float(p.n_src) * p.n_pairs * p.n_freq
+    out = {}
+    with fv.Context(0) as c:
+        for name, fl in (("type3", fv.NO_LATTICE), ("default", 0)):
+            c.simulate_dev(*args, vis, eps=1e-10, flags=fl, stream=stream)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(2):
+                t0 = time.perf_counter()
+                rep = c.simulate_dev(*args, vis, eps=1e-10, flags=fl | fv.TIMING, stream=stream)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            o = vis.cpu().numpy()
+            got = o[fsel][:, sub, 0] + 1j * o[fsel][:, sub, 1]
+            out[name] = {"ms": min(ts) * 1e3, "pairs_per_s": pairs / min(ts), "prec_bits": rep["prec_bits"],
+                         "w": rep["w"], "lattice": rep["lattice"], "n1": rep["n1"],
+                         "rel_l2_vs_oracle": oracle.rel_l2(got, ref),
+                         "stages_ms": {n: round(rep["t_stage_ms"][i], 3) for i, n in enumerate(fv.STAGES)
+                                       if rep["stage_launches"][i] > 0}}
+    return {"workload": "hex350, 1e5 sources, 64 freqs 100-200 MHz, eps 1e-10 (FP64 grids), inputs in HBM",
+            **out}
+
+
 def disk3d_leg(fv, synth, np, torch, stream) -> dict:
     """1000 antennas in a 500 m disk (3-D), 393k pixels, 16 frequencies:
     inputs in HBM, two timed calls after one warm-up call."""
@@ -549,7 +588,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving mix leg")
-    ap.add_argument("--only", choices=("serving", "basis"), help="run one extra leg alone and print it")
+    ap.add_argument("--only", choices=("serving", "basis", "fp64"), help="run one extra leg alone and print it")
     ap.add_argument("--overlap-md", metavar="KERNEL_TRACE_CSV",
                     help="no run: print how much of the serving slots' kernel time overlaps across streams, "
                          "from a rocprofv3 --kernel-trace CSV of a --only serving run")
@@ -600,6 +639,9 @@ def main():
         return
     if args.only == "basis":
         print(json.dumps(basis_leg(fv, synth, np, torch, torch.cuda.Stream())))
+        return
+    if args.only == "fp64":
+        print(json.dumps(fp64_leg(fv, synth, np, torch, torch.cuda.Stream())))
         return
     dev = torch.device("cuda:0")
     p = synth.config2(n_src=args.n_src, n_freq=args.n_freq)
@@ -797,6 +839,11 @@ def main():
         extras["serving"] = serving_leg(fv, synth, np, torch, args.serve_requests)
         print_serving(extras["serving"])
         extras["disk1000_3d"] = disk3d_leg(fv, synth, np, torch, stream)
+        extras["hex350_fp64_eps1e-10"] = fp64_leg(fv, synth, np, torch, stream)
+        x = extras["hex350_fp64_eps1e-10"]
+        print(f"bench: eps 1e-10 (FP64) type-3 {x['type3']['ms']:.2f} ms (rel l2 {x['type3']['rel_l2_vs_oracle']:.1e}), "
+              f"default path {x['default']['ms']:.2f} ms (rel l2 {x['default']['rel_l2_vs_oracle']:.1e})",
+              file=sys.stderr, flush=True)
         extras["drift_config4"] = drift_leg(fv, synth, np, torch, stream)
         extras.update(multivector_legs(fv, synth, np, torch, stream))
         extras.update(basis_leg(fv, synth, np, torch, stream))
