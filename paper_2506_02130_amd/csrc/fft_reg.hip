@@ -9,6 +9,13 @@
 #ifndef FV_FFT_COLS
 #define FV_FFT_COLS 0
 #endif
+// the two orientations carry their own kernel names (so that profiles tell
+// the passes apart)
+#if FV_FFT_COLS
+#define FV_FFT_KERNEL k_fft_cols
+#else
+#define FV_FFT_KERNEL k_fft_rows
+#endif
 
 namespace fv {
 namespace {
@@ -22,8 +29,8 @@ __device__ __forceinline__ long long xcd_order_reg(long long b, long long nblk) 
 
 // One workgroup per line group of one snapshot, numbered snapshot by snapshot
 // (reg_base); the snapshot of a workgroup is found by binary search.
-__global__ __launch_bounds__(fftr::kTpb) void k_fft_reg(const SnapDev *snaps, int n_snap, int a, float2 *grid,
-                                                         long long n_wg) {
+__global__ __launch_bounds__(fftr::kTpb) void FV_FFT_KERNEL(const SnapDev *snaps, int n_snap, int a, float2 *grid,
+                                                             long long n_wg) {
     extern __shared__ __align__(16) char smem[];
     const long long wl = xcd_order_reg((long long)blockIdx.x, (long long)gridDim.x);
     if (wl >= n_wg) return;
@@ -63,7 +70,7 @@ void launch_fft_reg_rows(const SnapDev *snaps, int n_snap, int a, void *grid, lo
 {
     static bool raised = false;
     if (!raised) {
-        FV_HIP(hipFuncSetAttribute((const void *)k_fft_reg, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        FV_HIP(hipFuncSetAttribute((const void *)FV_FFT_KERNEL, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         raised = true;
     }
     if (n_wg <= 0) return;
@@ -71,10 +78,10 @@ void launch_fft_reg_rows(const SnapDev *snaps, int n_snap, int a, void *grid, lo
     const unsigned gx = (unsigned)((n_wg + 7) / 8 * 8);
     float2 *g = (float2 *)grid;
     if (ea)
-        hipExtLaunchKernelGGL(k_fft_reg, dim3(gx), dim3(fftr::kTpb), (uint32_t)lds, st, ea, eb, 0u, snaps, n_snap, a,
-                              g, n_wg);
+        hipExtLaunchKernelGGL(FV_FFT_KERNEL, dim3(gx), dim3(fftr::kTpb), (uint32_t)lds, st, ea, eb, 0u, snaps, n_snap,
+                              a, g, n_wg);
     else
-        hipLaunchKernelGGL(k_fft_reg, dim3(gx), dim3(fftr::kTpb), lds, st, snaps, n_snap, a, g, n_wg);
+        hipLaunchKernelGGL(FV_FFT_KERNEL, dim3(gx), dim3(fftr::kTpb), lds, st, snaps, n_snap, a, g, n_wg);
     FV_HIP(hipGetLastError());
 }
 
