@@ -821,6 +821,22 @@ def main():
             step(gfl)
         torch.cuda.synchronize()
         g_ms = (time.perf_counter() - tg0) * 1e3 / n_extra
+        # FV_DETERMINISTIC: records ranked by source index inside each sub-bin
+        dfl = fv.DETERMINISTIC | fv.NO_LATTICE | tune | fv.TIMING
+        for _ in range(2):
+            step(dfl)
+        torch.cuda.synchronize()
+        td0 = time.perf_counter()
+        for _ in range(n_extra):
+            rd = step(dfl)
+        torch.cuda.synchronize()
+        d_ms = (time.perf_counter() - td0) * 1e3 / n_extra
+        extras["deterministic"] = {"ms_per_step": d_ms, "pairs_per_s": pairs_per_step / (d_ms * 1e-3),
+                                   "stages_ms": {n: round(rd["t_stage_ms"][i], 4) for i, n in enumerate(fv.STAGES)
+                                                 if rd["stage_launches"][i] > 0},
+                                   "note": "type-3 path with FV_DETERMINISTIC (bit-reproducible spread order), "
+                                           "per-call stage events"}
+        print(f"bench: deterministic {d_ms:.3f} ms/step", file=sys.stderr, flush=True)
         extras["graph_replay"] = {"ms_per_step": g_ms, "pairs_per_s": pairs_per_step / (g_ms * 1e-3),
                                   "note": "type-3 path of the same workload, launch sequence replayed as a HIP "
                                           "graph, no stage events"}
