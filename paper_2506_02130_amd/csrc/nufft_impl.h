@@ -537,10 +537,11 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
     const int x0 = (blk % nbx) * Cfg::BX + Cfg::T * wave;
     if (x0 >= S.n1[0]) return;
     const int y0 = (blk / nbx) * Cfg::BY;
+    using R2 = typename std::conditional<std::is_same<R, float>::value, float2, double2>::type;
     char *wbase = smem + wave * Cfg::WAVE_BYTES;
-    int *sl0x = (int *)wbase, *sl0y = sl0x + 64;
-    R *scr = (R *)(sl0y + 64), *sci = scr + 64;
-    R *skx = sci + 64, *sky = skx + 64 * W;  // [64][W] kernel weights per staged record
+    R2 *sc = (R2 *)wbase;                 // strength (re, im) per staged record
+    int2 *sl0 = (int2 *)(sc + 64);        // first-cell offsets (x, y) per staged record
+    R *skx = (R *)(sl0 + 64), *sky = skx + 64 * W;  // [64][W] kernel weights per staged record
     const R beta = (R)S.beta;
     const R inv_hw = (R)(2.0 / W);
     const Rec<R, 2> *rs = recs + S.src_base;
@@ -601,10 +602,9 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
         if (e < total) {
             const Rec<R, 2> r = nxt;
             // first-cell offsets from the tile corner, in bytes of R
-            sl0x[lane] = (r.l0[0] - x0) * (int)sizeof(R);
-            sl0y[lane] = (r.l0[1] - y0) * (int)sizeof(R);
-            scr[lane] = r.cr;
-            sci[lane] = r.ci;
+            sl0[lane] = make_int2((r.l0[0] - x0) * (int)sizeof(R), (r.l0[1] - y0) * (int)sizeof(R));
+            sc[lane].x = r.cr;
+            sc[lane].y = r.ci;
             R wx[W], wy[W];
             bool exact = true;
             if constexpr (std::is_same<R, float>::value && W <= kPolyMaxW) {
@@ -632,8 +632,9 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
         } else {
             // past the last record: a corner no tile cell reaches, so the
             // steps below read in-bounds weights and contribute zero
-            sl0x[lane] = sl0y[lane] = kFarCell * (int)sizeof(R);
-            scr[lane] = sci[lane] = 0;
+            sl0[lane] = make_int2(kFarCell * (int)sizeof(R), kFarCell * (int)sizeof(R));
+            sc[lane].x = 0;
+            sc[lane].y = 0;
         }
         wave_sync();
         if (e + 64 < total) nxt = fetch(e + 64);
@@ -647,14 +648,16 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
             for (int u = 0; u < 4; ++u) {
                 const int rr = g0 + 4 * u + lk;
                 constexpr unsigned kSpan = W * sizeof(R);
-                const int dy = lib - sl0y[rr], dx = lib - sl0x[rr];  // bytes
+                const int2 o = sl0[rr];
+                const R2 c = sc[rr];
+                const int dy = lib - o.y, dx = lib - o.x;  // bytes
                 const bool iny = (unsigned)dy < kSpan, inx = (unsigned)dx < kSpan;
                 const R ky = *(const R *)((const char *)(sky + rr * W) + (iny ? dy : 0));
                 const R kx = *(const R *)((const char *)(skx + rr * W) + (inx ? dx : 0));
                 a[u] = iny ? ky : (R)0;
                 const R k = inx ? kx : (R)0;
-                bre[u] = scr[rr] * k;
-                bim[u] = sci[rr] * k;
+                bre[u] = c.x * k;
+                bim[u] = c.y * k;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
