@@ -62,8 +62,11 @@ def next_smooth_even(n: int) -> int:
 
 def fold_targets(b: np.ndarray, axis: int):
     """Reflect baselines into b[axis] >= 0 (ties broken by the remaining axes
-    in order).  Returns (folded baselines, bool flag 'was reflected')."""
+    in order).  Returns (folded baselines, bool flag 'was reflected').
+    axis = -1: no folding (the paper's plain targets)."""
     d = b.shape[1]
+    if axis < 0:
+        return b.copy(), np.zeros(b.shape[0], dtype=bool)
     order = [axis] + [a for a in range(d) if a != axis]
     flip = np.zeros(b.shape[0], dtype=bool)
     decided = np.zeros(b.shape[0], dtype=bool)
@@ -99,7 +102,9 @@ def baselines(ant: np.ndarray) -> np.ndarray:
     return ant[i] - ant[j]
 
 
-def make_plan(ant: np.ndarray, src: np.ndarray, freq: np.ndarray, eps: float, dim: int) -> Plan:
+def make_plan(ant: np.ndarray, src: np.ndarray, freq: np.ndarray, eps: float, dim: int, fold: bool = True) -> Plan:
+    """fold=False keeps the targets as the paper states them (section 2.2, the
+    type-3 targets): no reflection into a half-space, fold_axis = -1."""
     w = kernel_width(eps)
     s = src[:, :dim]
     b = baselines(ant)[:, :dim]
@@ -110,7 +115,7 @@ def make_plan(ant: np.ndarray, src: np.ndarray, freq: np.ndarray, eps: float, di
     s_c = 0.5 * (smin + smax)
     S = 0.5 * (smax - smin)
     ext = b.max(0) - b.min(0)
-    axis = int(np.argmax(ext * np.maximum(S, 1e-300)))
+    axis = int(np.argmax(ext * np.maximum(S, 1e-300))) if fold else -1
     bf, _ = fold_targets(b, axis)
     bmin, bmax = bf.min(0), bf.max(0)
     b_c = 0.5 * (bmin + bmax)
@@ -214,10 +219,10 @@ def interp_and_correct(plan: Plan, f: int, g: np.ndarray, freq_hz: float, b: np.
 
 
 def type3_vis(ant: np.ndarray, src: np.ndarray, freq: np.ndarray, c: np.ndarray, eps: float,
-              dim: int, pairs: np.ndarray | None = None) -> np.ndarray:
+              dim: int, pairs: np.ndarray | None = None, fold: bool = True) -> np.ndarray:
     """Whole type-3 pipeline for every frequency.  c: [n_freq, n_src] real.
     Returns complex128 [n_freq, n_out]."""
-    plan = make_plan(ant, src, freq, eps, dim)
+    plan = make_plan(ant, src, freq, eps, dim, fold)
     b = baselines(ant)
     if pairs is not None:
         b = b[pairs]

@@ -87,13 +87,16 @@ def test_ragged_sizes_and_beamless(gpu_lib, ctx):
 
 
 # ---------------------------------------------------------------- stages
-@pytest.mark.parametrize("eps,dim", [(1e-6, 2), (1e-10, 2), (1e-6, 3)])
-def test_stage_parity_against_type3_steps(gpu_lib, ctx, eps, dim):
+@pytest.mark.parametrize("eps,dim,fold", [(1e-6, 2, True), (1e-10, 2, True), (1e-6, 3, True), (1e-6, 2, False),
+                                          (1e-10, 3, False)])
+def test_stage_parity_against_type3_steps(gpu_lib, ctx, eps, dim, fold):
+    # fold=False: the paper's plain targets on both sides (no reflection into
+    # a half-space), so the stages are checked without the fold
     p = synth.small_problem(37, n_ant=14, n_src=90, n_freq=2, three_d=(dim == 3), radius=70.0, zhalf=2.0)
-    flags = gpu_lib.DIM_3D if dim == 3 else gpu_lib.DIM_2D
+    flags = (gpu_lib.DIM_3D if dim == 3 else gpu_lib.DIM_2D) | (0 if fold else gpu_lib.NO_FOLD)
     hp = gpu_lib.HostProblem.of(p, eps=eps, flags=flags)
     info, spread, fft = ctx.debug_stages(hp, f=1)
-    pl = type3.make_plan(p.ant_enu, p.src_lmn, p.freq_hz, eps, dim)
+    pl = type3.make_plan(p.ant_enu, p.src_lmn, p.freq_hz, eps, dim, fold)
     # plan: integers bit-exact
     assert info["w"] == pl.w and info["fold_axis"] == pl.fold_axis
     assert info["n1"] == [int(v) for v in pl.n1[1]]

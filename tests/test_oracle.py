@@ -287,6 +287,23 @@ def test_type3_steps_within_eps_of_direct_sum(dim, eps):
     assert oracle.rel_l2(V3, V) <= eps
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_unfolded_type3_steps_within_eps_of_direct_sum(dim):
+    # the paper's plain targets (no reflection into a half-space): the same
+    # steps on the unfolded baseline box stay within eps of the exact sum, and
+    # that box is the tight box of the baselines as given
+    p = synth.small_problem(40 + dim, n_ant=13, n_src=70, n_freq=2, three_d=(dim == 3), radius=70.0)
+    V = oracle.direct_problem(p)
+    V3 = type3.type3_vis(p.ant_enu, p.src_lmn, p.freq_hz, p.strengths(), 1e-8, dim, fold=False)
+    assert oracle.rel_l2(V3, V) <= 1e-8
+    pu = type3.make_plan(p.ant_enu, p.src_lmn, p.freq_hz, 1e-8, dim, fold=False)
+    pf = type3.make_plan(p.ant_enu, p.src_lmn, p.freq_hz, 1e-8, dim)
+    assert pu.fold_axis == -1 and pf.fold_axis >= 0
+    b = type3.baselines(p.ant_enu)[:, :dim]
+    assert np.allclose(pu.b_c - pu.B, b.min(0), rtol=0, atol=1e-12)
+    assert np.allclose(pu.b_c + pu.B, b.max(0), rtol=0, atol=1e-12)
+
+
 def test_type3_error_falls_with_eps():
     p = synth.config1()
     V = oracle.direct_problem(p)
