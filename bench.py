@@ -492,11 +492,12 @@ def multivector_legs(fv, synth, np, torch, stream) -> dict:
     pats = g(np.sqrt(p.beam)[None] * rng.uniform(0.8, 1.0, (3, 1, p.n_src)))
     which = rng.integers(0, 3, p.n_ant)
     stokes = g(np.concatenate([p.flux[None], rng.uniform(-0.1, 0.1, (3, 1, 1)) * p.flux[None]]))
+    flux = g(p.flux)
     vis_b = torch.empty((p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
     vis_p = torch.empty((4, p.n_freq, p.n_pairs, 2), dtype=torch.float64, device=dev)
     out = {}
     with fv.Context(0) as c:
-        calls = {"beams_3_patterns": lambda: c.simulate_beams(ant, src, freq, g(p.flux), pats, which, vis_b,
+        calls = {"beams_3_patterns": lambda: c.simulate_beams(ant, src, freq, flux, pats, which, vis_b,
                                                              eps=p.eps, stream=stream),
                  "polarised_4_products": lambda: c.simulate_polar(ant, src, freq, stokes, None, vis_p, eps=p.eps,
                                                                   stream=stream)}
@@ -590,7 +591,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving mix leg")
-    ap.add_argument("--only", choices=("serving", "basis", "fp64"), help="run one extra leg alone and print it")
+    ap.add_argument("--only", choices=("serving", "basis", "fp64", "drift", "vectors"),
+                    help="run one extra leg alone and print it")
     ap.add_argument("--overlap-md", metavar="KERNEL_TRACE_CSV",
                     help="no run: print how much of the serving slots' kernel time overlaps across streams, "
                          "from a rocprofv3 --kernel-trace CSV of a --only serving run")
@@ -644,6 +646,12 @@ def main():
         return
     if args.only == "fp64":
         print(json.dumps(fp64_leg(fv, synth, np, torch, torch.cuda.Stream())))
+        return
+    if args.only == "drift":
+        print(json.dumps(drift_leg(fv, synth, np, torch, torch.cuda.Stream())))
+        return
+    if args.only == "vectors":
+        print(json.dumps(multivector_legs(fv, synth, np, torch, torch.cuda.Stream())))
         return
     dev = torch.device("cuda:0")
     p = synth.config2(n_src=args.n_src, n_freq=args.n_freq)

@@ -1,7 +1,8 @@
 // Per-antenna beams (paper section 2.2.3): one transform per pattern pair
-// that occurs among the antenna pairs, each through the device path of
-// fv_simulate_dev with the product strengths, then one gather of every
-// visibility from its pattern pair's transform.
+// that occurs among the antenna pairs, with the product strengths, all pairs'
+// transforms batched (each stage one launch over every pattern pair and
+// frequency), then one gather of every visibility from its pattern pair's
+// transform.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -56,33 +57,41 @@ void run_vectors(fv_ctx *ctx, Slot &slot, hipStream_t st, const double *ant_dev,
     meta.flags = flags & ~FV_GRAPH;  // several transforms share the workspace: no replay
     const int dim = choose_dim(ant.data(), n_ant, eps, freq.data(), n_freq, flags);
     std::memset(&total, 0, sizeof(total));
+    total.fold_axis = -1;
+    // every vector is one problem of a batch: the transforms of all vectors
+    // and frequencies share each stage's launch
+    std::vector<fv_problem> metas(n_vec, meta);
+    std::vector<DevInputs> ins(n_vec);
+    for (int v = 0; v < n_vec; ++v) {
+        DevInputs &in = ins[v];
+        in.ant = ant_dev;
+        in.freq = freq_dev;
+        in.src = src_dev;
+        in.flux = fl(v);
+        in.beam = bm(v);
+        in.vis = tmp + 2 * (size_t)v * n_freq * n_pairs;
+        if (n_src > 0)
+            for (int a = 0; a < dim; ++a) {  // the same directions for every vector
+                in.s_c[a] = 0.5 * (pin[2 * a] + pin[2 * a + 1]);
+                in.S[a] = 0.5 * (pin[2 * a + 1] - pin[2 * a]);
+            }
+        in.cmax = validate_partials(scal + (size_t)v * nvd, n_ant, n_freq);
+        in.cmax_span = validate_span(n_fs);
+    }
+    StageTimer &tm = slot.timer;
+    tm.reset((flags & (FV_TIMING | FV_TIMING_ACCUM)) != 0, (flags & FV_TIMING_ACCUM) != 0,
+             (flags & FV_TIMING_ONE_STAGE) ? FV_TIMING_STAGE_OF(flags) : -1);
     hipStream_t keep = slot.stream;
     slot.stream = st;
     try {
-        for (int v = 0; v < n_vec; ++v) {
-            DevInputs in;
-            in.ant = ant_dev;
-            in.freq = freq_dev;
-            in.src = src_dev;
-            in.flux = fl(v);
-            in.beam = bm(v);
-            in.vis = tmp + 2 * (size_t)v * n_freq * n_pairs;
-            if (n_src > 0)
-                for (int a = 0; a < dim; ++a) {  // the same directions for every vector
-                    in.s_c[a] = 0.5 * (pin[2 * a] + pin[2 * a + 1]);
-                    in.S[a] = 0.5 * (pin[2 * a + 1] - pin[2 * a]);
-                }
-            in.cmax = validate_partials(scal + (size_t)v * nvd, n_ant, n_freq);
-            in.cmax_span = validate_span(n_fs);
-            fv_report r;
-            run_device(ctx, slot, meta, in, in.vis, &r);
-            accumulate_report(r, total, v == 0);
-        }
+        run_batch_device(ctx, slot, n_vec, metas.data(), ins.data(), total, nullptr);
     } catch (...) {
         slot.stream = keep;
         throw;
     }
     slot.stream = keep;
+    fill_report(tm, total);
+    total.method = FV_METHOD_NUFFT;
 }
 
 void simulate_beams(fv_ctx *ctx, const fv_beams *b, double *vis, hipStream_t st, fv_report *rep) {

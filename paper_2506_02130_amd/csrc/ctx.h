@@ -152,10 +152,10 @@ void fill_report(StageTimer &tm, fv_report &r);
 // r (the first sub-call's report is copied whole).
 void accumulate_report(const fv_report &a, fv_report &r, bool first);
 // n_vec transforms of one geometry (all arrays on the device), the v-th with
-// strengths flux * prod[v] (or prod[v] alone when flux is null), each through
-// run_device into tmp + v [n_freq][n_pairs] complex; one input check per
-// vector and one wait for all their planning scalars.  `total` sums the
-// reports.
+// strengths flux * prod[v] (or prod[v] alone when flux is null), into tmp + v
+// [n_freq][n_pairs] complex, run as one batch (each stage one launch over
+// every vector and frequency); one input check per vector and one wait for
+// all their planning scalars.  `total` is the batch's report.
 void run_vectors(fv_ctx *ctx, Slot &slot, hipStream_t st, const double *ant_dev, int n_ant, const double *src_dev,
                  int n_src, const double *freq_dev, int n_freq, double eps, unsigned flags, const double *flux,
                  const double *prod, int n_vec, double *tmp, fv_report &total);

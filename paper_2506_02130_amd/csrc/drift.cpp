@@ -3,9 +3,10 @@
 // the sources above the horizon at each time (and checks the inputs), one copy
 // brings the counts to the host, one launch rotates the visible sources to ENU
 // and forms their strengths with the beam (paper sections 2.3 and 2.4), packed;
-// one input-check pass per time gathers the planning scalars, one copy brings
-// them all to the host, and each time then runs the device path of
-// fv_simulate_dev on its visible sky.
+// one input check of every time's visible sky (two launches) gathers the
+// planning scalars, one copy brings them all to the host, and the times then
+// run as one batch on their visible skies (each stage one launch over every
+// time and frequency of the group).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -60,7 +61,6 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
     FV_HIP(hipStreamWaitEvent(st, slot.done, 0));  // the previous call (any stream) is done with the workspace
     const int n_ant = d->n_ant, n_src = d->n_src, n_freq = d->n_freq, n_time = d->n_time;
     const long long n_pairs = (long long)n_ant * (n_ant + 1) / 2;
-    const size_t nvd = validate_doubles(n_ant, n_freq);
     // per-time workspace: packed directions and strengths of the visible
     // sources, block offsets
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
@@ -124,42 +124,75 @@ void simulate_drift(fv_ctx *ctx, const fv_drift *d, double *vis, hipStream_t st,
             const std::vector<int> vis_src(cnt, cnt + nt);
             launch_frontend(d->src_eq, n_src, nt, rot_dev, d->flux, n_freq, kb_dev, unit_beam, bcnt, tot, dir,
                             dir_stride, str, str_stride, st);
-            // planning scalars of every visible snapshot, then one copy of all of them
-            double *scal = ctx->scalars(nvd * (size_t)nt);
-            for (int t = 0; t < nt; ++t)
-                launch_validate(dir + t * dir_stride, vis_src[t], str + t * str_stride, nullptr, n_freq, ant_dev, n_ant,
-                                freq_dev, scal + (size_t)t * nvd, st);
-            double *pin = (double *)ctx->plan_pin.get(8 * sizeof(double) * (size_t)nt);
-            for (int t = 0; t < nt; ++t)
-                FV_HIP(hipMemcpyAsync(pin + 8 * t, scal + (size_t)t * nvd, 8 * sizeof(double), hipMemcpyDeviceToHost,
-                                      st));
+            // the input check of every visible snapshot in two launches (an
+            // item table per time), its results brought back in one copy
+            auto al32 = [](size_t v) { return (v + 31) / 32 * 32; };  // doubles: 256-byte alignment
+            std::vector<int> nblk(nt);
+            std::vector<size_t> poff(nt + 1, 0);
+            int max_blk = 1;
+            for (int t = 0; t < nt; ++t) {
+                nblk[t] = validate_blocks_batch(vis_src[t], (long long)vis_src[t] * n_freq);
+                max_blk = std::max(max_blk, nblk[t]);
+                poff[t + 1] = poff[t] + al32((size_t)kValStride * nblk[t]);
+            }
+            const size_t d_part = al32(8 * (size_t)nt), d_tab = d_part + poff[nt];
+            const size_t tab_doubles = al32((sizeof(ValItem) * (size_t)nt + 7) / 8);
+            double *scal = ctx->scalars(d_tab + tab_doubles);
+            double *pin = (double *)ctx->plan_pin.get((d_part + tab_doubles) * sizeof(double));
+            ValItem *tabh = (ValItem *)(pin + d_part);
+            for (int t = 0; t < nt; ++t) {
+                ValItem &v = tabh[t];
+                v = ValItem{};
+                v.n_src = vis_src[t];
+                v.n_fs = (long long)vis_src[t] * n_freq;
+                v.src = v.n_src > 0 ? dir + t * dir_stride : nullptr;
+                v.flux = v.n_fs > 0 ? str + t * str_stride : nullptr;
+                v.hdr = scal + 8 * (size_t)t;  // the 8 check values only (no frequencies or antennas)
+                v.part = scal + d_part + poff[t];
+                v.span = validate_span_n(v.n_fs, nblk[t]);
+                v.nblk = nblk[t];
+            }
+            ValItem *tabd = (ValItem *)(scal + d_tab);
+            FV_HIP(hipMemcpyAsync(tabd, tabh, sizeof(ValItem) * (size_t)nt, hipMemcpyHostToDevice, st));
+            launch_validate_batch(tabd, nt, max_blk, st);
+            FV_HIP(hipMemcpyAsync(pin, scal, 8 * sizeof(double) * (size_t)nt, hipMemcpyDeviceToHost, st));
             FV_HIP(hipStreamSynchronize(st));
+            // every time of the group is one problem of a batch: each stage
+            // one launch over all times and frequencies
+            const int dim = choose_dim(d->ant_enu, n_ant, d->eps, d->freq_hz, n_freq, d->flags);
+            std::vector<fv_problem> metas(nt, meta);
+            std::vector<DevInputs> ins(nt);
             for (int t = 0; t < nt; ++t) {
                 const double *chk = pin + 8 * t;
                 const int ns = vis_src[t];
                 if (ns > 0 && (chk[6] != 0.0 || chk[7] != 0.0))
                     fail(FV_EINVAL, "invalid source vectors or fluxes (directions must be unit vectors)");
-                DevInputs in;
+                DevInputs &in = ins[t];
                 in.ant = ant_dev;
                 in.freq = freq_dev;
                 in.src = dir + t * dir_stride;
                 in.flux = str + t * str_stride;
                 in.beam = nullptr;
                 in.vis = vis + 2 * (size_t)(t0g + t) * n_freq * n_pairs;
-                const int dim = choose_dim(d->ant_enu, n_ant, d->eps, d->freq_hz, n_freq, d->flags);
                 if (ns > 0)
                     for (int a = 0; a < dim; ++a) {
                         in.s_c[a] = 0.5 * (chk[2 * a] + chk[2 * a + 1]);
                         in.S[a] = 0.5 * (chk[2 * a + 1] - chk[2 * a]);
                     }
-                in.cmax = validate_partials(scal + (size_t)t * nvd, n_ant, n_freq);
-                in.cmax_span = validate_span((long long)ns * n_freq);
-                fv_problem mt = meta;
-                mt.n_src = ns;
-                fv_report r;
-                run_device(ctx, slot, mt, in, in.vis, &r);
-                accumulate_report(r, total, t0g == 0 && t == 0);
+                in.cmax = scal + d_part + poff[t];
+                in.cmax_span = validate_span_n((long long)ns * n_freq, nblk[t]);
+                metas[t].n_src = ns;
             }
+            StageTimer &tm = slot.timer;
+            tm.reset((d->flags & (FV_TIMING | FV_TIMING_ACCUM)) != 0, (d->flags & FV_TIMING_ACCUM) != 0,
+                     (d->flags & FV_TIMING_ONE_STAGE) ? FV_TIMING_STAGE_OF(d->flags) : -1);
+            fv_report r;
+            std::memset(&r, 0, sizeof(r));
+            r.fold_axis = -1;
+            run_batch_device(ctx, slot, nt, metas.data(), ins.data(), r, nullptr);
+            fill_report(tm, r);
+            r.method = FV_METHOD_NUFFT;
+            accumulate_report(r, total, t0g == 0);
         }
     } catch (...) {
         slot.stream = keep;
