@@ -92,6 +92,10 @@ struct fv_ctx {
         std::vector<int> dim;
         hipEvent_t ev = nullptr;  // the check's copy to the host
     } bspec;
+    // side stream of a repeated type-3 call's input check, and the event that
+    // forks it from the caller's stream (default priority, like every stream)
+    hipStream_t side = nullptr;
+    hipEvent_t side_fork = nullptr;
     fv::TuneCache tunes;     // autotuned FFT launch shapes
     fv::Server *server = nullptr;  // owned; created by fv_server_start, freed by fv_server_stop
     double *scalars(size_t n_doubles) {

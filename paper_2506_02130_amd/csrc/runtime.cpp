@@ -781,6 +781,8 @@ void fv_destroy(fv_ctx *ctx) {
         (void)hipDeviceSynchronize();
         if (ctx->spec.ev) (void)hipEventDestroy(ctx->spec.ev);
         if (ctx->bspec.ev) (void)hipEventDestroy(ctx->bspec.ev);
+        if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
+        if (ctx->side) (void)hipStreamDestroy(ctx->side);
     } catch (...) {
     }
     delete ctx;
@@ -812,14 +814,30 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
     FV_HIP(hipStreamWaitEvent(st, slot.done, 0));  // the previous call (any stream) is done with the workspace
     double *pin = (double *)ctx->plan_pin.get(nscal * sizeof(double));
     double *dev = ctx->scalars(fv::validate_doubles(p->n_ant, p->n_freq));
-    fv::launch_validate(p->src_lmn, p->n_src, p->flux, p->beam, p->n_freq, p->ant_enu, p->n_ant, p->freq_hz, dev,
-                        st);
-    FV_HIP(hipMemcpyAsync(pin, dev, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
     auto &sp = ctx->spec;
     const void *ptrs[5] = {p->ant_enu, p->freq_hz, p->src_lmn, p->flux, p->beam};
     const bool speculate = sp.valid && std::memcmp(sp.ptr, ptrs, sizeof(ptrs)) == 0 && sp.n_ant == p->n_ant &&
                            sp.n_freq == p->n_freq && sp.n_src == p->n_src && sp.eps == p->eps && sp.flags == p->flags;
     sp.valid = false;  // set again below once this call's scalars are known
+    if (!sp.ev) FV_HIP(hipEventCreateWithFlags(&sp.ev, hipEventDisableTiming));
+    // A repeated call whose last path was type 3 runs its input check on the
+    // context's side stream, beside the speculative transform: type 3 reads
+    // nothing the check writes.  The caller's stream joins the check before
+    // anything that may read it (a path change after the check) and before
+    // the call ends.
+    const bool side = speculate && !sp.lattice;
+    hipStream_t vs = st;
+    if (side) {
+        if (!ctx->side) FV_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        if (!ctx->side_fork) FV_HIP(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming));
+        FV_HIP(hipEventRecord(ctx->side_fork, st));  // after the wait for the previous call
+        FV_HIP(hipStreamWaitEvent(ctx->side, ctx->side_fork, 0));
+        vs = ctx->side;
+    }
+    fv::launch_validate(p->src_lmn, p->n_src, p->flux, p->beam, p->n_freq, p->ant_enu, p->n_ant, p->freq_hz, dev,
+                        vs);
+    FV_HIP(hipMemcpyAsync(pin, dev, nscal * sizeof(double), hipMemcpyDeviceToHost, vs));
+    if (speculate) FV_HIP(hipEventRecord(sp.ev, vs));  // the check's copy
     // the device inputs; the source box is filled from the host-side check
     auto dev_inputs = [&](const double *box) {
         fv::DevInputs in;
@@ -843,8 +861,6 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
         fv_report rs;
         bool ran = false;
         if (speculate) {
-            if (!sp.ev) FV_HIP(hipEventCreateWithFlags(&sp.ev, hipEventDisableTiming));
-            FV_HIP(hipEventRecord(sp.ev, st));
             fv_problem meta = *p;
             meta.ant_enu = sp.ant.data();
             meta.freq_hz = sp.freq.data();
@@ -852,6 +868,7 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
             std::memcpy(box, sp.s_c, sizeof(sp.s_c));
             std::memcpy(box + 3, sp.S, sizeof(sp.S));
             fv::run_device(ctx, slot, meta, dev_inputs(box), vis, &rs);  // the last call's path and plan
+            if (side) FV_HIP(hipStreamWaitEvent(st, sp.ev, 0));  // the join
             FV_HIP(hipEventSynchronize(sp.ev));
             ran = true;
         } else {
@@ -895,6 +912,7 @@ fv_status fv_simulate_dev(fv_ctx *ctx, const fv_problem *p, double *vis, void *s
         }
     } catch (...) {
         slot.stream = keep;
+        if (side) (void)hipStreamWaitEvent(st, sp.ev, 0);  // the side stream's check joins first
         (void)hipEventRecord(slot.done, st);  // work already enqueued must finish before the workspace is reused
         throw;
     }
