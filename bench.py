@@ -591,7 +591,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT launch shape on the first warm-up call")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph-replay and batch legs")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving mix leg")
-    ap.add_argument("--only", choices=("serving", "basis", "fp64", "drift", "vectors"),
+    ap.add_argument("--only", choices=("serving", "basis", "fp64", "drift", "vectors", "disk3d"),
                     help="run one extra leg alone and print it")
     ap.add_argument("--overlap-md", metavar="KERNEL_TRACE_CSV",
                     help="no run: print how much of the serving slots' kernel time overlaps across streams, "
@@ -646,6 +646,9 @@ def main():
         return
     if args.only == "fp64":
         print(json.dumps(fp64_leg(fv, synth, np, torch, torch.cuda.Stream())))
+        return
+    if args.only == "disk3d":
+        print(json.dumps(disk3d_leg(fv, synth, np, torch, torch.cuda.Stream())))
         return
     if args.only == "drift":
         print(json.dumps(drift_leg(fv, synth, np, torch, torch.cuda.Stream())))

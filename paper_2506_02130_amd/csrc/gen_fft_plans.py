@@ -5,9 +5,11 @@ The oversampled FFT of the type-3 path (paper section 2.2, step 2) runs, per
 line of n1 = L modes, two L-point transforms (the even and odd outputs of the
 zero-padded 2L-point transform).  A plan fixes, for one L:
 
-  NL     lines per workgroup of 256 threads (a power of two for columns);
-  LP     line stride in LDS: odd for rows; for columns 16/NL mod 16, so that
-         the NL lines of 16 lanes (columns first) fall in distinct banks;
+  NL     lines per workgroup of 256 threads (a power of two for columns, up
+         to 128, so that short columns still give a workgroup enough work);
+  LP     line stride in LDS: odd for rows; for columns 16/NL mod 16 (1 mod 16
+         past 16 lines), so that the lines of 16 lanes (columns first) fall in
+         distinct banks;
   F[g]   the radix of each group (2 to 16), prod F = L: group g is a Stockham
          step of radix F whose F-point DFT runs in registers, so a line goes
          through LDS only between groups.  Group g's L / F_g butterflies per
@@ -19,7 +21,9 @@ zero-padded 2L-point transform).  A plan fixes, for one L:
 
 The search minimises an estimate of the instructions per point -- the small
 DFTs, the twiddle products, LDS and index work, counted over every round of
-the 256 threads so that idle lanes cost -- with a penalty when the LDS a
+the 256 threads so that idle lanes cost, and for columns a fixed cost per
+workgroup (its set-up and twiddle rows) spread over its points -- with a
+penalty when the LDS a
 workgroup holds leaves fewer than 16 wavefronts per compute unit (the passes
 wait on memory and barriers), and a small one per group (one barrier pair
 each), and the LDS accesses of every group are weighted by their bank-conflict
@@ -40,6 +44,10 @@ GMAX, GMAX_HARD = 4, 6
 HOLD = 24      # points a middle group holds across its barrier
 HOLD_IN = 32   # points a thread loads before its first DFT
 HOLD_OUT = 16  # even-phase outputs kept until the odd phase stores both
+# Plans that fit the LDS cap exist up to 2430 points, but a column pass of
+# such lines holds one line per workgroup (8-byte segments per row): the
+# 2250-point y pass of the 3-D disk workload took 75 ms against 60 ms with the
+# general kernel, so the table stops at 2048.
 LMIN, LMAX = 16, 2048
 
 # real operations per point of a small DFT (additions and multiplications,
@@ -90,10 +98,14 @@ def sequences(L: int, gmax: int):
     return out
 
 
+COL_NL = (1, 2, 4, 8, 16, 32, 64, 128)
+COL_WG_FIXED = 256 * 40.0  # per-workgroup set-up of a column plan, in the cost's units
+
+
 def line_stride(L: int, NL: int, cols: bool) -> int:
     if not cols:
         return L + 1 if L % 2 == 0 else L
-    want = (16 // NL) % 16
+    want = (16 // NL) % 16 if NL <= 16 else 1
     n = L
     while n % 16 != want:
         n += 1
@@ -161,7 +173,7 @@ def plan(L: int, cols: bool, gmax: int = GMAX):
     best = None
     for Fs in sequences(L, gmax):
         G = len(Fs)
-        for NL in ((1, 2, 4, 8, 16) if cols else range(1, 33)):
+        for NL in (COL_NL if cols else range(1, 33)):
             LP = line_stride(L, NL, cols)
             lds = (NL * LP + twiddle_entries(Fs)) * 8
             if lds > LDS_CAP:
@@ -181,7 +193,7 @@ def plan(L: int, cols: bool, gmax: int = GMAX):
                 if g == G - 1:
                     per += 1.5 * F  # output window and addresses
                 work += R[g] * TPB * per
-            cost = work / (NL * L)
+            cost = (work + (COL_WG_FIXED if cols else 0.0)) / (NL * L)
             waves = min(LDS_CU // lds, 2048 // TPB) * TPB // 64
             # LDS accesses (two per point and group boundary) at their conflict degree
             lds_cost = 2.0 * (G - 1) * 2.0 * lds_conflict_factor(L, NL, LP, Fs, cols)
