@@ -422,7 +422,9 @@ struct T1Shape {
     size_t part_bytes, t_bytes, mode_bytes;
 };
 
-T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w) {
+// chunk > 0 fixes the sources per spreading workgroup (a batch of problems
+// sizes its chunks over the whole batch); 0 sizes them for this problem alone.
+T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int prec_bits, int w, int chunk = 0) {
     T1Shape s;
     for (int a = 0; a < 2; ++a) {
         s.N[a] = 2 * lp.K[a] + 1;
@@ -436,9 +438,13 @@ T1Shape t1_shape(const LatticePlan &lp, int n_src, int n_freq, int n_ant, int pr
     // kT1MinChunk sources each
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, 160 * 1024 / (s.lds + kT1IdBytes + 1024)));
     const int slots = kT1Cus * per_cu;
-    s.nchunk = std::max(1, (slots + n_freq / 2) / std::max(n_freq, 1));
-    s.nchunk = std::max(1, std::min(s.nchunk, n_src / kT1MinChunk));
-    s.chunk = std::max(1, (n_src + s.nchunk - 1) / s.nchunk);
+    if (chunk > 0) {
+        s.chunk = chunk;
+    } else {
+        s.nchunk = std::max(1, (slots + n_freq / 2) / std::max(n_freq, 1));
+        s.nchunk = std::max(1, std::min(s.nchunk, n_src / kT1MinChunk));
+        s.chunk = std::max(1, (n_src + s.nchunk - 1) / s.nchunk);
+    }
     s.nchunk = std::max(1, (n_src + s.chunk - 1) / s.chunk);
     const size_t cells = (size_t)s.nf[0] * s.nf[1];
     s.part_bytes = (size_t)n_freq * s.nchunk * (cells * 8 + 8);
@@ -636,9 +642,22 @@ struct LatBatchShape {
 
 LatBatchShape lat_batch_shape(const std::vector<LatItem> &items, int prec_bits, int w) {
     LatBatchShape b;
+    // one chunk size over the whole batch: about four rounds of workgroups
+    // over the device for all its (source, frequency) records, so that
+    // workgroups carry similar work whatever each problem's source count, and
+    // each problem writes only as many partial grids as its sources need
+    double recs = 0.0;
+    int per_cu = 1;
+    for (const LatItem &it : items) {
+        recs += (double)it.n_src * it.n_freq;
+        const T1Shape s1 = t1_shape(*it.lp, 1, 1, 1, prec_bits, w);
+        per_cu = std::max(per_cu, (int)std::max<size_t>(1, std::min<size_t>(8, 160 * 1024 / (s1.lds + kT1IdBytes + 1024))));
+    }
+    const double target = 4.0 * kT1Cus * per_cu;
+    const int chunk = (int)std::max<double>(kT1MinChunk, std::ceil(recs / target));
     size_t off = 0;
     for (const LatItem &it : items) {
-        const T1Shape sh = t1_shape(*it.lp, it.n_src, it.n_freq, it.n_ant, prec_bits, w);
+        const T1Shape sh = t1_shape(*it.lp, it.n_src, it.n_freq, it.n_ant, prec_bits, w, chunk);
         b.sh.push_back(sh);
         b.off.push_back(off);
         off += al256(sh.part_bytes) + al256(sh.t_bytes) + al256(sh.mode_bytes);
