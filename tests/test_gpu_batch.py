@@ -212,3 +212,33 @@ def test_repeated_device_batch_still_reports_bad_values(gpu_lib, ctx):
     ctx.simulate_batch_dev(items)
     torch.cuda.synchronize()
     assert oracle.rel_l2(_cplx(items[0]["vis"]), oracle.direct_problem(p)) <= p.eps
+
+
+def test_device_batch_mixed_methods_and_graph(gpu_lib, ctx):
+    # one device batch with every method and path: lattice and type-3 NUFFT,
+    # the vector direct sum and the matrix-core direct sum, FP64 and FP32, an
+    # empty sky; the lattice group captured (FV_GRAPH) and replayed
+    import torch
+    fv = gpu_lib
+    cases = [
+        (synth.small_problem(77, n_ant=19, n_src=600, n_freq=3, hex_layout=True), 1e-6, fv.GRAPH),
+        (synth.small_problem(78, n_ant=19, n_src=400, n_freq=2, hex_layout=True), 1e-10, fv.GRAPH),
+        (synth.small_problem(79, n_ant=16, n_src=300, n_freq=2, three_d=True, radius=90.0), 1e-6, 0),
+        (synth.small_problem(80, n_ant=13, n_src=250, n_freq=2), 1e-6, fv.METHOD_DIRECT),
+        (synth.small_problem(81, n_ant=21, n_src=350, n_freq=2), 1e-6, fv.METHOD_MFMA),
+        (synth.small_problem(82, n_ant=9, n_src=0, n_freq=2), 1e-6, 0),
+    ]
+    items = [_dev(torch, p, flags=f, eps=e) for p, e, f in cases]
+    batch = ctx.prepare_batch_dev(items)
+    for rep_i in range(3):
+        for it in items:
+            it["vis"].zero_()
+        ctx.run_batch_dev(batch)
+        torch.cuda.synchronize()
+        for (p, e, f), it in zip(cases, items):
+            v = _cplx(it["vis"])
+            if p.n_src == 0:
+                assert np.all(v == 0)
+                continue
+            tol = e if (f & 0x30) == 0 else max(e, 1e-6)  # the direct sums: FP32 at eps 1e-6
+            assert oracle.rel_l2(v, oracle.direct_problem(p)) <= tol, (rep_i, p.name)
