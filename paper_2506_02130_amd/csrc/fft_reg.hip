@@ -13,8 +13,10 @@
 // the passes apart)
 #if FV_FFT_COLS
 #define FV_FFT_KERNEL k_fft_cols
+#define FV_FFT_WAVES __attribute__((amdgpu_waves_per_eu(4)))
 #else
 #define FV_FFT_KERNEL k_fft_rows
+#define FV_FFT_WAVES
 #endif
 
 namespace fv {
@@ -29,7 +31,7 @@ __device__ __forceinline__ long long xcd_order_reg(long long b, long long nblk) 
 
 // One workgroup per line group of one snapshot, numbered snapshot by snapshot
 // (reg_base); the snapshot of a workgroup is found by binary search.
-__global__ __launch_bounds__(fftr::kTpb) void FV_FFT_KERNEL(const SnapDev *snaps, int n_snap, int a, float2 *grid,
+__global__ __launch_bounds__(fftr::kTpb) FV_FFT_WAVES void FV_FFT_KERNEL(const SnapDev *snaps, int n_snap, int a, float2 *grid,
                                                              long long n_wg) {
     extern __shared__ __align__(16) char smem[];
     const long long wl = xcd_order_reg((long long)blockIdx.x, (long long)gridDim.x);
