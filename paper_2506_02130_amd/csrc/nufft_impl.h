@@ -142,23 +142,42 @@ __global__ __launch_bounds__(256) void k_bin(const SnapDev *snaps, int gx, int n
     rank[S.src_base + i] = wave_rank(bins + S.bin_base, key);
 }
 
-// Exclusive scan of n counts in place (b[n] receives the total), by one
-// 1024-thread workgroup, 4 counts per thread per chunk.
+// Exclusive scan of nb counts in place (b[nb] receives the total), by one
+// 1024-thread workgroup.  Chunks of 1024 x 16 counts: each thread takes 16
+// consecutive counts, with all its loads in flight before any is used (16-byte
+// loads when b is 16-byte aligned), scans them in registers, and adds the
+// prefix of the thread sums before it (wavefront shuffles, then one value per
+// wavefront through LDS).  A snapshot of up to 16384 sub-bins is one chunk,
+// one round trip to memory.
 __device__ void scan_counts(int *b, long long nb) {
+    constexpr int PT = 16;
+    constexpr long long CH = 1024LL * PT;
     __shared__ int wsum[16];
     __shared__ int carry_sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const bool vec = ((unsigned long long)b & 15ull) == 0;
     if (tid == 0) carry_sh = 0;
     __syncthreads();
-    for (long long base = 0; base < nb; base += 4096) {
-        int v[4];
+    for (long long base = 0; base < nb; base += CH) {
+        const long long i0 = base + (long long)PT * tid;
+        int v[PT];
+        if (vec && i0 + PT <= nb) {
+            const int4 *q4 = (const int4 *)(b + i0);
+#pragma unroll
+            for (int q = 0; q < PT / 4; ++q) {
+                const int4 t = q4[q];
+                v[4 * q] = t.x;
+                v[4 * q + 1] = t.y;
+                v[4 * q + 2] = t.z;
+                v[4 * q + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PT; ++q) v[q] = i0 + q < nb ? b[i0 + q] : 0;
+        }
         int tsum = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            long long i = base + 4 * tid + q;
-            v[q] = i < nb ? b[i] : 0;
-            tsum += v[q];
-        }
+        for (int q = 0; q < PT; ++q) tsum += v[q];
         // inclusive scan of tsum across the wave
         int x = tsum;
 #pragma unroll
@@ -176,10 +195,19 @@ __device__ void scan_counts(int *b, long long nb) {
         }
         int run = carry_sh + wpre + x - tsum;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            long long i = base + 4 * tid + q;
-            if (i < nb) b[i] = run;
-            run += v[q];
+        for (int q = 0; q < PT; ++q) {
+            const int c = v[q];
+            v[q] = run;
+            run += c;
+        }
+        if (vec && i0 + PT <= nb) {
+            int4 *q4 = (int4 *)(b + i0);
+#pragma unroll
+            for (int q = 0; q < PT / 4; ++q) q4[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < PT; ++q)
+                if (i0 + q < nb) b[i0 + q] = v[q];
         }
         __syncthreads();
         if (tid == 0) carry_sh += total;

@@ -139,7 +139,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         d.src_base = L.total_src;
         L.total_src += j.n_src;
         d.bin_base = L.total_bins;
-        L.total_bins += nb + 1;
+        L.total_bins += (nb + 1 + 3) / 4 * 4;  // 16-byte aligned per snapshot (vector scan loads)
         d.ipsi_base = L.total_ipsi;
         L.total_ipsi += nipsi;
         // grid regions (elements)
@@ -284,7 +284,7 @@ inline Layout make_layout(const std::vector<SnapJob> &jobs, int dim, int prec_bi
         for (int a = 0; a < dim; ++a) G.nb *= L.snaps[best].nsb[a];
         for (int i : kv.second) L.snaps[i].order_base = G.base;
         L.order_src += G.n_src;
-        L.order_counts += G.nb + 1;
+        L.order_counts += (G.nb + 1 + 3) / 4 * 4;
         L.max_order_src = std::max<long long>(L.max_order_src, G.n_src);
         L.orders.push_back(G);
     }
