@@ -531,7 +531,10 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
 // by v_mfma_{f32,f64}_16x16x4 (A = y weights of 4 records, B = strength-scaled
 // x weights, real and imaginary parts in two accumulators).  Each lane stages
 // one record at a time in LDS with its 2 W kernel weights (evaluated once per
-// record and tile), then builds one A and one B element per step by lookup.
+// record and tile), then builds one A and one B element per step by lookup:
+// its cell's byte offset from the record's first cell, taken as unsigned and
+// capped at the row's end, where a zero sits (cells before or past the
+// footprint both land there).
 template <typename R, int W>
 struct SpreadMfmaCfg {
     static constexpr int T = 16;            // tile edge
@@ -540,8 +543,10 @@ struct SpreadMfmaCfg {
     static constexpr int WPB = 1;           // wavefronts (tiles) per block, along x
     static constexpr int BX = T * WPB, BY = T;
     static constexpr int MAXROWS = 8;       // sub-bin rows per tile
-    // staged records: l0x, l0y (int), cr, ci (R), W x weights, W y weights (R)
-    static constexpr int WAVE_BYTES = 64 * (2 * (int)sizeof(int) + (2 + 2 * W) * (int)sizeof(R));
+    // staged records: l0x, l0y (int), cr, ci (R), W x weights and W y weights
+    // (R), each weight row followed by a zero
+    static constexpr int WS = W + 1;        // weight row stride
+    static constexpr int WAVE_BYTES = 64 * (2 * (int)sizeof(int) + (2 + 2 * WS) * (int)sizeof(R));
     static_assert((T + W - 1 + kSubBin - 1) / kSubBin + 1 <= MAXROWS, "too many sub-bin rows per tile");
 };
 // first-cell offset of the staged slots past a batch's last record
@@ -569,7 +574,9 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
     char *wbase = smem + wave * Cfg::WAVE_BYTES;
     R2 *sc = (R2 *)wbase;                 // strength (re, im) per staged record
     int2 *sl0 = (int2 *)(sc + 64);        // first-cell offsets (x, y) per staged record
-    R *skx = (R *)(sl0 + 64), *sky = skx + 64 * W;  // [64][W] kernel weights per staged record
+    R *skx = (R *)(sl0 + 64), *sky = skx + 64 * Cfg::WS;  // [64][W + 1] kernel weights per staged record
+    skx[lane * Cfg::WS + W] = 0;  // the zero after each row, never overwritten
+    sky[lane * Cfg::WS + W] = 0;
     const R beta = (R)S.beta;
     const R inv_hw = (R)(2.0 / W);
     const Rec<R, 2> *rs = recs + S.src_base;
@@ -654,8 +661,8 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
             }
 #pragma unroll
             for (int i = 0; i < W; ++i) {
-                skx[lane * W + i] = wx[i];
-                sky[lane * W + i] = wy[i];
+                skx[lane * Cfg::WS + i] = wx[i];
+                sky[lane * Cfg::WS + i] = wy[i];
             }
         } else {
             // past the last record: a corner no tile cell reaches, so the
@@ -678,12 +685,10 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
                 constexpr unsigned kSpan = W * sizeof(R);
                 const int2 o = sl0[rr];
                 const R2 c = sc[rr];
-                const int dy = lib - o.y, dx = lib - o.x;  // bytes
-                const bool iny = (unsigned)dy < kSpan, inx = (unsigned)dx < kSpan;
-                const R ky = *(const R *)((const char *)(sky + rr * W) + (iny ? dy : 0));
-                const R kx = *(const R *)((const char *)(skx + rr * W) + (inx ? dx : 0));
-                a[u] = iny ? ky : (R)0;
-                const R k = inx ? kx : (R)0;
+                // bytes from the record's first cell, or the row's zero
+                const unsigned dy = min((unsigned)(lib - o.y), kSpan), dx = min((unsigned)(lib - o.x), kSpan);
+                const R k = *(const R *)((const char *)(skx + rr * Cfg::WS) + dx);
+                a[u] = *(const R *)((const char *)(sky + rr * Cfg::WS) + dy);
                 bre[u] = c.x * k;
                 bim[u] = c.y * k;
             }
