@@ -220,22 +220,25 @@ struct Dft {
 };
 
 // ---------------------------------------------------------------------------
-// A plan: L points per line, NL lines per workgroup of kTpb threads, line
+// A plan: L points per line, NL lines per workgroup of TPB threads, line
 // stride LP in LDS, and the radices of the groups (1 past the last).  Group g
 // has Q_g = L / F_g butterflies per line; the workgroup's NL Q_g butterflies
-// are dealt to its threads in R_g rounds (butterfly b = thread + kTpb r).
-constexpr int kTpb = 256;
+// are dealt to its threads in R_g rounds (butterfly b = thread + TPB r).
+// Row workgroups have 256 threads; column workgroups 512, so that twice the
+// columns share each row segment in global memory (64 bytes) for the same
+// work per thread.
+constexpr int kTpbRows = 256, kTpbCols = 512;
 
-template <int L_, int NL_, int LP_, int F1, int F2, int F3, int F4, int F5, int F6>
+template <int L_, int NL_, int LP_, int F1, int F2, int F3, int F4, int F5, int F6, int TPB_>
 struct Plan {
-    static constexpr int L = L_, NL = NL_, LP = LP_;
+    static constexpr int L = L_, NL = NL_, LP = LP_, TPB = TPB_;
     static constexpr int G = (F1 > 1) + (F2 > 1) + (F3 > 1) + (F4 > 1) + (F5 > 1) + (F6 > 1);
     static constexpr int Fg(int g) {
         return g == 0 ? F1 : g == 1 ? F2 : g == 2 ? F3 : g == 3 ? F4 : g == 4 ? F5 : F6;
     }
     static constexpr int Pg(int g) { return g == 0 ? 1 : Pg(g - 1) * Fg(g - 1); }  // product of earlier radices
     static constexpr int Qg(int g) { return L / Fg(g); }
-    static constexpr int Rg(int g) { return (NL * Qg(g) + kTpb - 1) / kTpb; }
+    static constexpr int Rg(int g) { return (NL * Qg(g) + TPB - 1) / TPB; }
     // Twiddle rows in LDS: a middle group g has one row per k < p_g holding
     // W_L^(j k Q_g / p_g) for j = 1 .. F_g - 1; the last group one row per
     // butterfly i holding (-1)^i W_L^(i j) for j = 0 .. F - 1 (the sign is
@@ -287,8 +290,8 @@ __device__ __forceinline__ void load_first(unsigned tid, const Lines &ln, float2
     sfor<R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
         sfor<F>([&](auto jc) { xin[r][decltype(jc)::value] = c2(0.f, 0.f); });
-        const unsigned b = tid + kTpb * r;
-        if ((r + 1) * kTpb <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
+        const unsigned b = tid + P::TPB * r;
+        if ((r + 1) * P::TPB <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
             unsigned l, i;
             decode<P, COLS, 0>(b, l, i);
             if ((int)l < ln.nvalid) {
@@ -312,8 +315,8 @@ __device__ __forceinline__ void group_first(unsigned tid, int par, const float2 
     constexpr int F = P::Fg(0), Q = P::Qg(0), R = P::Rg(0);
     sfor<R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        const unsigned b = tid + kTpb * r;
-        if ((r + 1) * kTpb <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
+        const unsigned b = tid + P::TPB * r;
+        if ((r + 1) * P::TPB <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
             unsigned l, i;
             decode<P, COLS, 0>(b, l, i);
             float2 x[F];
@@ -342,8 +345,8 @@ __device__ __forceinline__ void group_mid(unsigned tid, float2 *lines, const flo
     float2 x[R][F];
     sfor<R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        const unsigned b = tid + kTpb * r;
-        if ((r + 1) * kTpb <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
+        const unsigned b = tid + P::TPB * r;
+        if ((r + 1) * P::TPB <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
             unsigned l, i;
             decode<P, false, g>(b, l, i);
             const float2 *src = lines + l * P::LP + i;
@@ -353,8 +356,8 @@ __device__ __forceinline__ void group_mid(unsigned tid, float2 *lines, const flo
     __syncthreads();  // every input read before any position is overwritten
     sfor<R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        const unsigned b = tid + kTpb * r;
-        if ((r + 1) * kTpb <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
+        const unsigned b = tid + P::TPB * r;
+        if ((r + 1) * P::TPB <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
             unsigned l, i;
             decode<P, false, g>(b, l, i);
             const unsigned hq = i / (unsigned)p, k = i - hq * p;
@@ -386,8 +389,8 @@ __device__ __forceinline__ void group_last(unsigned tid, int par, int Pa, const 
     static_assert(P::Pg(g) == Q, "last group");
     sfor<R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        const unsigned b = tid + kTpb * r;
-        if ((r + 1) * kTpb <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
+        const unsigned b = tid + P::TPB * r;
+        if ((r + 1) * P::TPB <= P::NL * Q || b < (unsigned)(P::NL * Q)) {
             unsigned l, i;
             decode<P, COLS, g>(b, l, i);
             __builtin_assume(i < (unsigned)Q);  // b < NL Q here
@@ -434,7 +437,7 @@ template <class P, int g>
 __device__ __forceinline__ void fill_rows(float2 *tw, const float2 *tw2) {
     if constexpr (g < P::G) {
         constexpr int S = P::Sg(g), W = P::Wg(g), n = P::Pg(g) * S, step = P::Qg(g) / P::Pg(g);
-        for (unsigned e = threadIdx.x; e < (unsigned)n; e += kTpb) {
+        for (unsigned e = threadIdx.x; e < (unsigned)n; e += P::TPB) {
             const unsigned k = e / (unsigned)S, c = e - k * S;
             float2 v = c2(0.f, 0.f);
             if (g == P::G - 1) {
@@ -494,7 +497,7 @@ __device__ __forceinline__ void run_plan(const SnapDev &S, int a, long long wl, 
         // every group would all stay live in registers
         unsigned tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        __builtin_assume(tid < (unsigned)kTpb);
+        __builtin_assume(tid < (unsigned)P::TPB);
         // every round's loads in flight at once (the second phase reads the
         // same lines again, from cache)
         float2 xin[P::Rg(0)][P::Fg(0)];

@@ -13,9 +13,11 @@
 // the passes apart)
 #if FV_FFT_COLS
 #define FV_FFT_KERNEL k_fft_cols
+#define FV_FFT_TPB fftr::kTpbCols
 #define FV_FFT_WAVES __attribute__((amdgpu_waves_per_eu(4)))
 #else
 #define FV_FFT_KERNEL k_fft_rows
+#define FV_FFT_TPB fftr::kTpbRows
 #define FV_FFT_WAVES
 #endif
 
@@ -31,7 +33,7 @@ __device__ __forceinline__ long long xcd_order_reg(long long b, long long nblk) 
 
 // One workgroup per line group of one snapshot, numbered snapshot by snapshot
 // (reg_base); the snapshot of a workgroup is found by binary search.
-__global__ __launch_bounds__(fftr::kTpb) FV_FFT_WAVES void FV_FFT_KERNEL(const SnapDev *snaps, int n_snap, int a, float2 *grid,
+__global__ __launch_bounds__(FV_FFT_TPB) FV_FFT_WAVES void FV_FFT_KERNEL(const SnapDev *snaps, int n_snap, int a, float2 *grid,
                                                              long long n_wg) {
     extern __shared__ __align__(16) char smem[];
     const long long wl = xcd_order_reg((long long)blockIdx.x, (long long)gridDim.x);
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(fftr::kTpb) FV_FFT_WAVES void FV_FFT_KERNEL(const S
     switch (S.n1[a]) {
 #define FV_FFT_PLAN(L, NL, LP, F1, F2, F3, F4, F5, F6)                                                 \
     case L:                                                                                           \
-        fftr::run_plan<fftr::Plan<L, NL, LP, F1, F2, F3, F4, F5, F6>, FV_FFT_COLS != 0>(S, a, w, grid, smem); \
+        fftr::run_plan<fftr::Plan<L, NL, LP, F1, F2, F3, F4, F5, F6, FV_FFT_TPB>, FV_FFT_COLS != 0>(S, a, w, grid, smem); \
         break;
 #if FV_FFT_COLS
 #include "fft_plans_cols.inc"
@@ -80,10 +82,10 @@ void launch_fft_reg_rows(const SnapDev *snaps, int n_snap, int a, void *grid, lo
     const unsigned gx = (unsigned)((n_wg + 7) / 8 * 8);
     float2 *g = (float2 *)grid;
     if (ea)
-        hipExtLaunchKernelGGL(FV_FFT_KERNEL, dim3(gx), dim3(fftr::kTpb), (uint32_t)lds, st, ea, eb, 0u, snaps, n_snap,
+        hipExtLaunchKernelGGL(FV_FFT_KERNEL, dim3(gx), dim3(FV_FFT_TPB), (uint32_t)lds, st, ea, eb, 0u, snaps, n_snap,
                               a, g, n_wg);
     else
-        hipLaunchKernelGGL(FV_FFT_KERNEL, dim3(gx), dim3(fftr::kTpb), lds, st, snaps, n_snap, a, g, n_wg);
+        hipLaunchKernelGGL(FV_FFT_KERNEL, dim3(gx), dim3(FV_FFT_TPB), lds, st, snaps, n_snap, a, g, n_wg);
     FV_HIP(hipGetLastError());
 }
 

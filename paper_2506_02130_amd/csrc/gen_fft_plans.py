@@ -5,8 +5,10 @@ The oversampled FFT of the type-3 path (paper section 2.2, step 2) runs, per
 line of n1 = L modes, two L-point transforms (the even and odd outputs of the
 zero-padded 2L-point transform).  A plan fixes, for one L:
 
-  NL     lines per workgroup of 256 threads (a power of two for columns, up
-         to 128, so that short columns still give a workgroup enough work);
+  NL     lines per workgroup (256 threads for rows, 512 for columns, so that
+         a column workgroup's row segments in global memory are twice as
+         long for the same work per thread); a power of two for columns, up
+         to 128, so that short columns still give a workgroup enough work;
   LP     line stride in LDS: odd for rows; for columns 16/NL mod 16 (1 mod 16
          past 16 lines), so that the lines of 16 lanes (columns first) fall in
          distinct banks;
@@ -21,7 +23,7 @@ zero-padded 2L-point transform).  A plan fixes, for one L:
 
 The search minimises an estimate of the instructions per point -- the small
 DFTs, the twiddle products, LDS and index work, counted over every round of
-the 256 threads so that idle lanes cost, and for columns a fixed cost per
+the workgroup's threads so that idle lanes cost, and for columns a fixed cost per
 workgroup (its set-up and twiddle rows) spread over its points -- with a
 penalty when the LDS a
 workgroup holds leaves fewer than 16 wavefronts per compute unit (the passes
@@ -36,8 +38,10 @@ import math
 import os
 import sys
 
-TPB = 256
-LDS_CAP = 40 * 1024  # four workgroups (16 wavefronts) per compute unit
+TPB_ROWS, TPB_COLS = 256, 512
+# LDS per workgroup: 16 wavefronts per compute unit (four row workgroups, two
+# column workgroups)
+LDS_CAP_ROWS, LDS_CAP_COLS = 40 * 1024, 80 * 1024
 LDS_CU = 160 * 1024
 RADICES = (2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16)
 GMAX, GMAX_HARD = 4, 6
@@ -99,7 +103,7 @@ def sequences(L: int, gmax: int):
 
 
 COL_NL = (1, 2, 4, 8, 16, 32, 64, 128)
-COL_WG_FIXED = 256 * 40.0  # per-workgroup set-up of a column plan, in the cost's units
+COL_WG_FIXED = TPB_COLS * 40.0  # per-workgroup set-up of a column plan, in the cost's units
 
 
 def line_stride(L: int, NL: int, cols: bool) -> int:
@@ -170,6 +174,8 @@ def lds_conflict_factor(L: int, NL: int, LP: int, Fs, cols: bool) -> float:
 
 
 def plan(L: int, cols: bool, gmax: int = GMAX):
+    TPB = TPB_COLS if cols else TPB_ROWS
+    LDS_CAP = LDS_CAP_COLS if cols else LDS_CAP_ROWS
     best = None
     for Fs in sequences(L, gmax):
         G = len(Fs)
