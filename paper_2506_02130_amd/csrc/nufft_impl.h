@@ -98,27 +98,26 @@ __global__ void k_fill_int(int *p, long long n, int v) {
 // Rank of this lane's key among the lanes of its wavefront that share the key,
 // plus the count already in counts[key]: one returning atomic per distinct key
 // in the wavefront (lanes of a spatially ordered source list mostly share a
-// few sub-bins).  The groups of equal keys are found with ballots first; then
-// the first lane of every group adds its group's size in one atomic
-// instruction for all groups, and each lane reads its group's old count from
-// its leader.  Every active lane of the wavefront must call it.
+// few sub-bins).  The groups of equal keys are found with ballots first (the
+// first remaining lane's key read into a scalar register; each lane keeps its
+// own group's mask); then the first lane of every group adds its group's size
+// in one atomic instruction for all groups, and each lane reads its group's
+// old count from its leader.  Every active lane of the wavefront must call it.
 __device__ __forceinline__ int wave_rank(int *counts, int key) {
     const int lane = threadIdx.x & 63;
-    unsigned long long todo = __ballot(1);
-    int leader = lane, below = 0, size = 0;
+    unsigned long long todo = __ballot(1), mine = 0;
     while (todo) {
-        const int l = __ffsll((long long)todo) - 1;
-        const int lk = __shfl(key, l, 64);
+        const int l = __ffsll((long long)todo) - 1;  // wave-uniform
+        const int lk = readlane_i(key, l);             // a scalar read, no LDS round trip
         const unsigned long long m = __ballot(key == lk) & todo;
-        if ((m >> lane) & 1ull) {
-            leader = l;
-            below = __popcll(m & ((1ull << lane) - 1ull));
-        }
-        if (lane == l) size = __popcll(m);
+        // a lane whose group was taken earlier never meets its key again
+        if (key == lk) mine = m;
         todo &= ~m;
     }
+    const int leader = __ffsll((long long)mine) - 1;
+    const int below = __popcll(mine & ((1ull << lane) - 1ull));
     int old = 0;
-    if (lane == leader) old = atomicAdd(&counts[key], size);
+    if (lane == leader) old = atomicAdd(&counts[key], __popcll(mine));
     return __shfl(old, leader, 64) + below;
 }
 
