@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_bin(const SnapDev *snaps, int gx, int n
     const SnapDev &S = snaps[sy];
     const int i = bx * 256 + threadIdx.x;
     if (i >= S.n_src) return;
-    const double *sp = S.order_base >= 0 ? src_ord + 3 * (S.order_base + i) : S.src + 3 * (size_t)i;
+    const double *sp = S.order_base >= 0 ? src_ord + D * (S.order_base + i) : S.src + 3 * (size_t)i;
     double s[3], g[3];
     int l0[3];
     for (int a = 0; a < D; ++a) s[a] = sp[a];
@@ -251,10 +251,10 @@ __global__ __launch_bounds__(256) void k_order_place(const SnapDev *snaps, const
     if (j >= G.n_src) return;
     double s[3], g[3];
     int l0[3];
-    for (int a = 0; a < 3; ++a) s[a] = S.src[3 * (size_t)j + a];
+    for (int a = 0; a < D; ++a) s[a] = S.src[3 * (size_t)j + a];
     const long long pos = G.base + starts[G.cnt_base + src_cell<D>(S, s, g, l0)] + rank[G.base + j];
     perm[pos] = j;
-    for (int a = 0; a < 3; ++a) src_ord[3 * pos + a] = s[a];
+    for (int a = 0; a < D; ++a) src_ord[D * pos + a] = s[a];  // D coordinates per source
 }
 
 template <typename R, int D>
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_scatter(const SnapDev *snaps, int gx, i
     if (i >= S.n_src) return;
     const bool ord = S.order_base >= 0;
     const int j = ord ? perm[S.order_base + i] : i;
-    const double *sp = ord ? src_ord + 3 * (S.order_base + i) : S.src + 3 * (size_t)i;
+    const double *sp = ord ? src_ord + D * (S.order_base + i) : S.src + 3 * (size_t)i;
     double s[3], g[3];
     int l0[3];
     for (int a = 0; a < D; ++a) s[a] = sp[a];

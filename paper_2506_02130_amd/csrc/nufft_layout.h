@@ -46,7 +46,7 @@ __host__ __device__ inline int sub_bin_edge(int a) { return a < 2 ? kSubBin : kS
 struct OrderGroup {
     int snap;              // snapshot whose sub-bins define the order
     int n_src;
-    long long base;        // offset in perm / rank scratch (and 3x in src_ord)
+    long long base;        // offset in perm / rank scratch (and D x in src_ord: D coordinates per source)
     long long cnt_base;    // offset of the list's nb + 1 counts
     long long nb;          // sub-bins of that snapshot
 };
