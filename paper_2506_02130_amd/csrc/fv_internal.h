@@ -137,8 +137,18 @@ struct Arena {
     char *base = nullptr;
     size_t cap = 0, used = 0;
     PinnedBuf host;  // staging of the per-launch snapshot table
+    // The snapshot and order tables the last type-3 launch uploaded to the
+    // start of this arena (their bytes, back to back), so that a repeated
+    // launch with the same plan and buffers skips the upload.  Dropped by
+    // reset() and by reallocation: any other use of the arena may overwrite
+    // that memory, and only the type-3 set-up takes the record out before
+    // its own reset().
+    std::vector<char> tables;
     void ensure(size_t bytes);          // reallocate (contents lost) if smaller
-    void reset() { used = 0; }
+    void reset() {
+        used = 0;
+        tables.clear();
+    }
     void *take(size_t bytes, size_t align = 256);
     void release();
 };

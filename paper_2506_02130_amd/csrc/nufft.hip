@@ -41,7 +41,13 @@ Prepared prepare_layout(Layout &&layout, const std::vector<SnapJob> &jobs, int d
     }
     const int n = (int)jobs.size();
     const size_t need = layout_bytes(L, dim, prec_bits, n);
+    // what the last launch uploaded here (empty if the arena was used or
+    // reallocated since)
+    std::vector<char> prev;
+    prev.swap(arena.tables);
+    const size_t cap0 = arena.cap;
     arena.ensure(need);
+    if (arena.cap != cap0) prev.clear();  // reallocated: contents lost
     arena.reset();
     SnapDev *snaps_dev = (SnapDev *)arena.take(n * sizeof(SnapDev));
     P.B.snaps = snaps_dev;
@@ -62,14 +68,23 @@ Prepared prepare_layout(Layout &&layout, const std::vector<SnapJob> &jobs, int d
         P.B.srcid = (int *)arena.take(std::max<long long>(L.total_src, 1) * 4);
     }
     // the tables go up from pinned staging; the staging is reused only after
-    // this copy has completed (PinnedBuf::get waits for it)
+    // this copy has completed (PinnedBuf::get waits for it).  The same bytes
+    // at the same places as the last upload to this arena are already there
+    // (same layout, so the same offsets; nothing else has used the arena).
     const size_t tb = n * sizeof(SnapDev), ob = ng * sizeof(OrderGroup);
-    char *stage = (char *)arena.host.get(tb + ob);
-    std::memcpy(stage, L.snaps.data(), tb);
-    if (ng) std::memcpy(stage + tb, L.orders.data(), ob);
-    FV_HIP(hipMemcpyAsync(snaps_dev, stage, tb, hipMemcpyHostToDevice, st));
-    if (ng) FV_HIP(hipMemcpyAsync(P.B.orders, stage + tb, ob, hipMemcpyHostToDevice, st));
-    arena.host.record(st);
+    const void *where[3] = {arena.base, snaps_dev, P.B.orders};
+    std::vector<char> bytes(tb + ob + sizeof(where));
+    std::memcpy(bytes.data(), L.snaps.data(), tb);
+    if (ng) std::memcpy(bytes.data() + tb, L.orders.data(), ob);
+    std::memcpy(bytes.data() + tb + ob, where, sizeof(where));
+    if (bytes != prev) {
+        char *stage = (char *)arena.host.get(tb + ob);
+        std::memcpy(stage, bytes.data(), tb + ob);
+        FV_HIP(hipMemcpyAsync(snaps_dev, stage, tb, hipMemcpyHostToDevice, st));
+        if (ng) FV_HIP(hipMemcpyAsync(P.B.orders, stage + tb, ob, hipMemcpyHostToDevice, st));
+        arena.host.record(st);
+    }
+    arena.tables.swap(bytes);
     return P;
 }
 

@@ -73,6 +73,7 @@ void PinnedBuf::release() {
 void Arena::ensure(size_t bytes) {
     if (bytes <= cap) return;
     release();
+    tables.clear();
     size_t want = std::max(bytes, cap + cap / 2);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, want);
