@@ -317,3 +317,22 @@ def test_device_output_must_be_16_byte_aligned(gpu_lib, ctx):
     vis = flat[1:].view(1, p.n_pairs, 2)
     with pytest.raises(fv.FvError, match="EINVAL"):
         ctx.simulate_dev(d(p.ant_enu), d(p.src_lmn), d(p.freq_hz), d(p.flux), d(p.beam), vis, eps=1e-6)
+
+
+def test_repeated_type3_after_other_paths_share_the_workspace(gpu_lib, ctx):
+    """A type-3 launch whose tables match the last ones uploaded to its
+    workspace skips the upload.  Between two identical calls the workspace is
+    used by the lattice path, the matrix-core direct sum and a smaller type-3
+    layout, each of which overwrites its start; the second call must upload
+    again and give the first call's result bit for bit (deterministic order)."""
+    fl = gpu_lib.NO_LATTICE | gpu_lib.DETERMINISTIC
+    p = synth.config1()
+    v0, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=fl)
+    v1, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=fl)  # tables unchanged: no upload
+    assert np.array_equal(v0, v1)
+    small = synth.small_problem(5, n_ant=9, n_src=30, n_freq=1)
+    for other, ofl in ((p, 0), (p, gpu_lib.METHOD_MFMA), (small, fl)):
+        _run(gpu_lib, ctx, other, eps=1e-6, flags=ofl)
+        v2, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=fl)
+        assert np.array_equal(v0, v2)
+    assert oracle.rel_l2(v0, oracle.direct_problem(p)) < 1e-6
