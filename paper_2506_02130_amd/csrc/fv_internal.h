@@ -144,10 +144,12 @@ struct Arena {
     // that memory, and only the type-3 set-up takes the record out before
     // its own reset().
     std::vector<char> tables;
+    bool ipsi = false;  // and a launch with those tables has computed its deconvolution tables
     void ensure(size_t bytes);          // reallocate (contents lost) if smaller
     void reset() {
         used = 0;
         tables.clear();
+        ipsi = false;
     }
     void *take(size_t bytes, size_t align = 256);
     void release();

@@ -45,6 +45,8 @@ Prepared prepare_layout(Layout &&layout, const std::vector<SnapJob> &jobs, int d
     // reallocated since)
     std::vector<char> prev;
     prev.swap(arena.tables);
+    const bool prev_ipsi = arena.ipsi;
+    arena.ipsi = false;  // set again once a launch with these tables is enqueued
     const size_t cap0 = arena.cap;
     arena.ensure(need);
     if (arena.cap != cap0) prev.clear();  // reallocated: contents lost
@@ -77,6 +79,7 @@ Prepared prepare_layout(Layout &&layout, const std::vector<SnapJob> &jobs, int d
     std::memcpy(bytes.data(), L.snaps.data(), tb);
     if (ng) std::memcpy(bytes.data() + tb, L.orders.data(), ob);
     std::memcpy(bytes.data() + tb + ob, where, sizeof(where));
+    P.B.ipsi_ready = prev_ipsi && bytes == prev;
     if (bytes != prev) {
         char *stage = (char *)arena.host.get(tb + ob);
         std::memcpy(stage, bytes.data(), tb + ob);
@@ -236,8 +239,10 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
     const bool graph = opts && opts->graph && opts->graphs && st != nullptr && !(timer && timer->on);
     if (!graph) {
         P.fn(P.L, P.B, n, st, 7, timer);
+        arena.ipsi = true;
         return P.L.model_bytes;
     }
+    P.B.ipsi_ready = false;  // a captured sequence always computes them
     const uint64_t key = graph_key(P, n, dim, prec_bits, w);
     hipGraphExec_t ex = opts->graphs->find(key);
     if (!ex) {
@@ -257,6 +262,7 @@ double nufft_execute(const std::vector<SnapJob> &jobs, int dim, int prec_bits, i
         opts->graphs->put(key, ex);
     }
     FV_HIP(hipGraphLaunch(ex, st));
+    arena.ipsi = true;
     return P.L.model_bytes;
 }
 

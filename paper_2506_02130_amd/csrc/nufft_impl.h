@@ -1250,6 +1250,9 @@ struct Bufs {
     const double *basis_M = nullptr;  // [n_freq][K]
     double *basis_vis = nullptr;      // [n_freq][n_pairs] complex
     long long basis_np = 0;
+    // ipsi already holds this plan's tables: the last launch on this
+    // workspace had the same plan and buffers and computed them
+    bool ipsi_ready = false;
 };
 
 // Snapshot-per-XCD launches when the snapshots fill the 8 XCDs evenly enough
@@ -1296,10 +1299,11 @@ void run_pipeline(const Layout &L, const Bufs &B, int n_snap, hipStream_t st, in
     if (stages & 1) {
     if (L.total_bins)
         hipLaunchKernelGGL(k_fill_int, dim3(blocks(L.total_bins, 256)), dim3(256), 0, st, bins, L.total_bins, 0);
-    if (L.max_ipsi)
+    if (L.max_ipsi && !B.ipsi_ready) {
         launch_stage(tm, FV_STAGE_OTHER, k_ipsi<R>, dim3(blocks(L.max_ipsi, 256), n_snap), dim3(256), 0, st,
                      snaps_dev, ipsi);
-    tm->add(FV_STAGE_OTHER, L.sbytes[FV_STAGE_OTHER], 1);
+        tm->add(FV_STAGE_OTHER, L.sbytes[FV_STAGE_OTHER], 1);
+    }
     tm->begin(FV_STAGE_SORT, st);
     int sort_launches = 3;
     if (perm) {

@@ -74,6 +74,7 @@ void Arena::ensure(size_t bytes) {
     if (bytes <= cap) return;
     release();
     tables.clear();
+    ipsi = false;
     size_t want = std::max(bytes, cap + cap / 2);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, want);
