@@ -224,10 +224,11 @@ struct Dft {
 // stride LP in LDS, and the radices of the groups (1 past the last).  Group g
 // has Q_g = L / F_g butterflies per line; the workgroup's NL Q_g butterflies
 // are dealt to its threads in R_g rounds (butterfly b = thread + TPB r).
-// Row workgroups have 256 threads; column workgroups 512, so that twice the
-// columns share each row segment in global memory (64 bytes) for the same
-// work per thread.
-constexpr int kTpbRows = 256, kTpbCols = 512;
+// Workgroups have 512 threads: a column workgroup then takes twice the
+// columns of a 256-thread one for the same work per thread, so that each row
+// segment it reads and writes in global memory is 64 bytes; a row workgroup
+// twice the rows.
+constexpr int kTpbRows = 512, kTpbCols = 512;
 
 template <int L_, int NL_, int LP_, int F1, int F2, int F3, int F4, int F5, int F6, int TPB_>
 struct Plan {

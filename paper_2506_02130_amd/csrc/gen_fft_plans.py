@@ -5,10 +5,10 @@ The oversampled FFT of the type-3 path (paper section 2.2, step 2) runs, per
 line of n1 = L modes, two L-point transforms (the even and odd outputs of the
 zero-padded 2L-point transform).  A plan fixes, for one L:
 
-  NL     lines per workgroup (256 threads for rows, 512 for columns, so that
-         a column workgroup's row segments in global memory are twice as
-         long for the same work per thread); a power of two for columns, up
-         to 128, so that short columns still give a workgroup enough work;
+  NL     lines per workgroup of 512 threads (for columns, row segments in
+         global memory twice as long as with 256 threads, for the same work
+         per thread); a power of two for columns, up to 128, so that short
+         columns still give a workgroup enough work;
   LP     line stride in LDS: odd for rows; for columns 16/NL mod 16 (1 mod 16
          past 16 lines), so that the lines of 16 lanes (columns first) fall in
          distinct banks;
@@ -38,10 +38,9 @@ import math
 import os
 import sys
 
-TPB_ROWS, TPB_COLS = 256, 512
-# LDS per workgroup: 16 wavefronts per compute unit (four row workgroups, two
-# column workgroups)
-LDS_CAP_ROWS, LDS_CAP_COLS = 40 * 1024, 80 * 1024
+TPB_ROWS, TPB_COLS = 512, 512
+# LDS per workgroup: 16 wavefronts per compute unit (two workgroups)
+LDS_CAP_ROWS, LDS_CAP_COLS = 80 * 1024, 80 * 1024
 LDS_CU = 160 * 1024
 RADICES = (2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16)
 GMAX, GMAX_HARD = 4, 6

@@ -183,9 +183,8 @@ int main() {
 
     // ---- planned FFT table: every even 5-smooth length 16..2048 has a row
     // and a column plan within the LDS budget (16 wavefronts per compute unit:
-    // 40 KB per 256-thread row workgroup, 80 KB per 512-thread column
-    // workgroup); nothing else has one; column plans take a power of two of
-    // lines, up to 128
+    // 80 KB per 512-thread workgroup); nothing else has one; column plans take
+    // a power of two of lines, up to 128
     for (int L = 2; L <= 2100; ++L) {
         int nl = 0;
         size_t lds = 0;
@@ -194,7 +193,7 @@ int main() {
             const bool have = fft_reg_info(L, cols, &nl, &lds);
             CHECK(have == want);
             if (have) {
-                CHECK(nl >= 1 && lds > (size_t)8 * L && lds <= (cols ? 80 : 40) * 1024);
+                CHECK(nl >= 1 && lds > (size_t)8 * L && lds <= 80 * 1024);
                 if (cols) CHECK(nl >= 1 && nl <= 128 && (nl & (nl - 1)) == 0);  // a power of two
             }
         }
