@@ -590,26 +590,23 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
         st = bb[row + sx_lo];
         cnt = bb[row + sx_hi + 1] - st;
     }
-    int inc = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += y;
-    }
-    const int total = __shfl(inc, 63, 64);
     // per sub-bin row (wave-uniform, in scalar registers): the window position
     // of its first record, and the change from the previous row of the offset
     // from window position to record index; rows past nrows start at total,
-    // beyond every position
+    // beyond every position.  The rows' counts are read lane by lane into
+    // scalar registers and summed there (no shuffle round trips).
     int rpre[Cfg::MAXROWS], rdd[Cfg::MAXROWS];
-    int prev = 0;
+    int pre = 0, prev = 0;
 #pragma unroll
     for (int r = 0; r < Cfg::MAXROWS; ++r) {
-        rpre[r] = readlane_i(inc - cnt, r);
-        const int del = readlane_i(st - (inc - cnt), r);
+        const int c = readlane_i(cnt, r), s0 = readlane_i(st, r);
+        rpre[r] = pre;
+        const int del = s0 - pre;
         rdd[r] = del - prev;
         prev = del;
+        pre += c;
     }
+    const int total = pre;
     typename MA::T accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
     // FP32 tiles: each batch of 64 records is summed on the matrix cores from
     // zero and the batch sums are added in FP64, so the rounding error of a
