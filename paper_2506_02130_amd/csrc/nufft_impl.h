@@ -552,7 +552,7 @@ struct SpreadMfmaCfg {
 constexpr int kFarCell = 1 << 20;
 
 template <typename R, int W>
-__global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma(const SnapDev *snaps, int gx,
+__global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) __attribute__((amdgpu_waves_per_eu(7))) void k_spread_mfma(const SnapDev *snaps, int gx,
                                                                              int n_snap, const int *bins,
                                                                              const Rec<R, 2> *recs,
                                                                              const R *ipsi, cplx<R> *grid,
@@ -584,6 +584,19 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
     const int sx_lo = max(0, x0 - W + 1) / kSubBin, sx_hi = min(S.n1[0] - W, x0 + Cfg::T - 1) / kSubBin;
     const int sy_lo = max(0, y0 - W + 1) / kSubBin, sy_hi = min(S.n1[1] - W, y0 + Cfg::T - 1) / kSubBin;
     const int nrows = (sx_lo > sx_hi || sy_lo > sy_hi) ? 0 : sy_hi - sy_lo + 1;
+    // the deconvolution factors of the owned cells (1/psi2hat at the modes),
+    // loaded now so that their latency overlaps the tile's record chain
+    const R *ix_t = ipsi + S.ipsi_base;
+    const R *iy_t = ix_t + S.n1[0];
+    const int cx_ = x0 + (lane & 15);
+    const bool cx_in = cx_ < S.n1[0];
+    const R fx = cx_in ? ix_t[cx_] : (R)0;
+    R fy[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int cy_ = y0 + MfmaAcc<R>::row(lane, r);
+        fy[r] = cy_ < S.n1[1] ? iy_t[cy_] : (R)0;
+    }
     int cnt = 0, st = 0;
     if (lane < nrows) {
         const long long row = (long long)(sy_lo + lane) * S.nsb[0];
@@ -706,15 +719,12 @@ __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) void k_spread_mfma
         wave_sync();
     }
     // flush: divide by psi2hat at the modes, store each owned cell once
-    const R *ix_t = ipsi + S.ipsi_base;
-    const R *iy_t = ix_t + S.n1[0];
     cplx<R> *dst = grid + S.bufA;
-    const int cx_ = x0 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int cy_ = y0 + MA::row(lane, r);
-        if (cx_ < S.n1[0] && cy_ < S.n1[1]) {
-            const R f = ix_t[cx_] * iy_t[cy_];
+        if (cx_in && cy_ < S.n1[1]) {
+            const R f = fx * fy[r];
             if constexpr (kBlocked)
                 dst[(long long)cy_ * S.n1[0] + cx_] = cmake<R>((R)(sumr[r] * (double)f), (R)(sumi[r] * (double)f));
             else
