@@ -542,6 +542,9 @@ struct SpreadMfmaCfg {
     static constexpr int WPB = 1;           // wavefronts (tiles) per block, along x
     static constexpr int BX = T * WPB, BY = T;
     static constexpr int MAXROWS = 8;       // sub-bin rows per tile
+    // FP32 with w <= 8 (every FP32 width in use) fits 7 wavefronts per SIMD
+    // without spills; wider and FP64 kernels take what their registers allow
+    static constexpr int MIN_WAVES = std::is_same<R, float>::value && W <= 8 ? 7 : 1;
     // staged records: l0x, l0y (int), cr, ci (R), W x weights and W y weights
     // (R), each weight row followed by a zero
     static constexpr int WS = W + 1;        // weight row stride
@@ -552,7 +555,8 @@ struct SpreadMfmaCfg {
 constexpr int kFarCell = 1 << 20;
 
 template <typename R, int W>
-__global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB)) __attribute__((amdgpu_waves_per_eu(7))) void k_spread_mfma(const SnapDev *snaps, int gx,
+__global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB))
+__attribute__((amdgpu_waves_per_eu(SpreadMfmaCfg<R, W>::MIN_WAVES))) void k_spread_mfma(const SnapDev *snaps, int gx,
                                                                              int n_snap, const int *bins,
                                                                              const Rec<R, 2> *recs,
                                                                              const R *ipsi, cplx<R> *grid,
