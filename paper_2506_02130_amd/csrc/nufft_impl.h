@@ -531,9 +531,11 @@ __global__ __launch_bounds__(256) void k_spread(const SnapDev *snaps, int gx, in
 // x weights, real and imaginary parts in two accumulators).  Each lane stages
 // one record at a time in LDS with its 2 W kernel weights (evaluated once per
 // record and tile), then builds one A and one B element per step by lookup:
-// its cell's byte offset from the record's first cell, taken as unsigned and
-// capped at the row's end, where a zero sits (cells before or past the
-// footprint both land there).
+// its cell's byte offsets from the record's first cell along both axes, as the
+// two 16-bit halves of one register, taken as unsigned and capped at the zero
+// that sits between the record's y and x weights (cells before or past the
+// footprint land there; the x weights are stored in reverse, so that the same
+// cap reaches the zero from their side).
 template <typename R, int W>
 struct SpreadMfmaCfg {
     static constexpr int T = 16;            // tile edge
@@ -545,14 +547,18 @@ struct SpreadMfmaCfg {
     // FP32 with w <= 8 (every FP32 width in use) fits 7 wavefronts per SIMD
     // without spills; wider and FP64 kernels take what their registers allow
     static constexpr int MIN_WAVES = std::is_same<R, float>::value && W <= 8 ? 7 : 1;
-    // staged records: l0x, l0y (int), cr, ci (R), W x weights and W y weights
-    // (R), each weight row followed by a zero
-    static constexpr int WS = W + 1;        // weight row stride
-    static constexpr int WAVE_BYTES = 64 * (2 * (int)sizeof(int) + (2 + 2 * WS) * (int)sizeof(R));
+    // staged records: cr, ci (R); the first cell's offsets from the tile
+    // corner in bytes, x and y as the two 16-bit halves of one int; one row of
+    // 2 W + 1 weights (R): y weights 0 .. W - 1, a zero, x weights W - 1 .. 0
+    static constexpr int WS = 2 * W + 1;    // weight row stride (odd: rows start in distinct banks)
+    static constexpr int WAVE_BYTES = 64 * ((int)sizeof(int) + (2 + WS) * (int)sizeof(R));
     static_assert((T + W - 1 + kSubBin - 1) / kSubBin + 1 <= MAXROWS, "too many sub-bin rows per tile");
 };
-// first-cell offset of the staged slots past a batch's last record
-constexpr int kFarCell = 1 << 20;
+// first-cell offset, in bytes, of the staged slots past a batch's last record:
+// every lane's offset from it is negative as a 16-bit value
+constexpr int kFarBytes = 0x3000;
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 template <typename R, int W>
 __global__ __launch_bounds__((64 * SpreadMfmaCfg<R, W>::WPB))
@@ -576,10 +582,9 @@ __attribute__((amdgpu_waves_per_eu(SpreadMfmaCfg<R, W>::MIN_WAVES))) void k_spre
     using R2 = typename std::conditional<std::is_same<R, float>::value, float2, double2>::type;
     char *wbase = smem + wave * Cfg::WAVE_BYTES;
     R2 *sc = (R2 *)wbase;                 // strength (re, im) per staged record
-    int2 *sl0 = (int2 *)(sc + 64);        // first-cell offsets (x, y) per staged record
-    R *skx = (R *)(sl0 + 64), *sky = skx + 64 * Cfg::WS;  // [64][W + 1] kernel weights per staged record
-    skx[lane * Cfg::WS + W] = 0;  // the zero after each row, never overwritten
-    sky[lane * Cfg::WS + W] = 0;
+    int *sl0 = (int *)(sc + 64);          // first-cell offsets (x low, y high 16 bits) per staged record
+    R *skw = (R *)(sl0 + 64);             // [64][2 W + 1] kernel weights per staged record
+    skw[lane * Cfg::WS + W] = 0;          // the zero between the y and x weights, never overwritten
     const R beta = (R)S.beta;
     const R inv_hw = (R)(2.0 / W);
     const Rec<R, 2> *rs = recs + S.src_base;
@@ -632,6 +637,11 @@ __attribute__((amdgpu_waves_per_eu(SpreadMfmaCfg<R, W>::MIN_WAVES))) void k_spre
     double sumr[4] = {0, 0, 0, 0}, sumi[4] = {0, 0, 0, 0};
     const int li = lane & 15, lk = lane >> 4;  // A row / B column index, record slot of the 4
     const int lib = li * (int)sizeof(R);
+    // the lane's cell offset in bytes, twice, for the 16-bit differences of
+    // both axes at once; their cap is the zero weight (offsets before or past
+    // a record's footprint wrap or exceed it)
+    const s16x2 lib2 = {(short)lib, (short)lib};
+    const u16x2 span2 = {(unsigned short)(W * sizeof(R)), (unsigned short)(W * sizeof(R))};
     // record e of the tile's neighbourhood (a position in its sub-bin rows):
     // its row is the last one starting at or before e, and the row starts are
     // nondecreasing, so the changes of the rows starting at or before e add up
@@ -650,7 +660,9 @@ __attribute__((amdgpu_waves_per_eu(SpreadMfmaCfg<R, W>::MIN_WAVES))) void k_spre
         if (e < total) {
             const Rec<R, 2> r = nxt;
             // first-cell offsets from the tile corner, in bytes of R
-            sl0[lane] = make_int2((r.l0[0] - x0) * (int)sizeof(R), (r.l0[1] - y0) * (int)sizeof(R));
+            // |offset| <= (W + 2 kSubBin) cells: well inside 16 bits
+            sl0[lane] = (int)(((unsigned)((r.l0[1] - y0) * (int)sizeof(R)) << 16) |
+                              ((unsigned)((r.l0[0] - x0) * (int)sizeof(R)) & 0xffffu));
             sc[lane].x = r.cr;
             sc[lane].y = r.ci;
             R wx[W], wy[W];
@@ -674,13 +686,13 @@ __attribute__((amdgpu_waves_per_eu(SpreadMfmaCfg<R, W>::MIN_WAVES))) void k_spre
             }
 #pragma unroll
             for (int i = 0; i < W; ++i) {
-                skx[lane * Cfg::WS + i] = wx[i];
-                sky[lane * Cfg::WS + i] = wy[i];
+                skw[lane * Cfg::WS + i] = wy[i];
+                skw[lane * Cfg::WS + 2 * W - i] = wx[i];
             }
         } else {
             // past the last record: a corner no tile cell reaches, so the
             // steps below read in-bounds weights and contribute zero
-            sl0[lane] = make_int2(kFarCell * (int)sizeof(R), kFarCell * (int)sizeof(R));
+            sl0[lane] = (kFarBytes << 16) | kFarBytes;
             sc[lane].x = 0;
             sc[lane].y = 0;
         }
@@ -695,13 +707,14 @@ __attribute__((amdgpu_waves_per_eu(SpreadMfmaCfg<R, W>::MIN_WAVES))) void k_spre
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int rr = g0 + 4 * u + lk;
-                constexpr unsigned kSpan = W * sizeof(R);
-                const int2 o = sl0[rr];
+                const int o = sl0[rr];
                 const R2 c = sc[rr];
                 // bytes from the record's first cell, or the row's zero
-                const unsigned dy = min((unsigned)(lib - o.y), kSpan), dx = min((unsigned)(lib - o.x), kSpan);
-                const R k = *(const R *)((const char *)(skx + rr * Cfg::WS) + dx);
-                a[u] = *(const R *)((const char *)(sky + rr * Cfg::WS) + dy);
+                const u16x2 d = __builtin_elementwise_min(
+                    __builtin_bit_cast(u16x2, (s16x2)(lib2 - __builtin_bit_cast(s16x2, o))), span2);
+                const char *row = (const char *)(skw + rr * Cfg::WS);
+                a[u] = *(const R *)(row + (unsigned)d.y);
+                const R k = *(const R *)(row + 2 * W * sizeof(R) - (unsigned)d.x);
                 bre[u] = c.x * k;
                 bim[u] = c.y * k;
             }
