@@ -52,6 +52,7 @@ HOLD_OUT = 16  # even-phase outputs kept until the odd phase stores both
 # 2250-point y pass of the 3-D disk workload took 75 ms against 60 ms with the
 # general kernel, so the table stops at 2048.
 LMIN, LMAX = 16, 2048
+LMAX_ROWS = 4608
 
 # real operations per point of a small DFT (additions and multiplications,
 # a fused multiply-add counted once)
@@ -214,7 +215,7 @@ def plan(L: int, cols: bool, gmax: int = GMAX):
 def main(directory: str) -> None:
     for cols, name in ((False, "fft_plans_rows.inc"), (True, "fft_plans_cols.inc")):
         lines = ["// Generated by gen_fft_plans.py: FV_FFT_PLAN(L, NL, LP, F1, F2, F3, F4, F5, F6)"]
-        for L in range(LMIN, LMAX + 1, 2):
+        for L in range(LMIN, (LMAX if cols else LMAX_ROWS) + 1, 2):
             if not smooth(L):
                 continue
             p = plan(L, cols)

@@ -182,14 +182,14 @@ int main() {
             }
 
     // ---- planned FFT table: every even 5-smooth length 16..2048 has a row
-    // and a column plan within the LDS budget (16 wavefronts per compute unit:
-    // 80 KB per 512-thread workgroup); nothing else has one; column plans take
-    // a power of two of lines, up to 128
-    for (int L = 2; L <= 2100; ++L) {
+    // and a column plan, and 2050..4608 a row plan, within the LDS budget (16
+    // wavefronts per compute unit: 80 KB per 512-thread workgroup); nothing
+    // else has one; column plans take a power of two of lines, up to 128
+    for (int L = 2; L <= 4700; ++L) {
         int nl = 0;
         size_t lds = 0;
-        const bool want = L >= 16 && L <= 2048 && L % 2 == 0 && smooth5(L);
         for (bool cols : {false, true}) {
+            const bool want = L >= 16 && L <= (cols ? 2048 : 4608) && L % 2 == 0 && smooth5(L);
             const bool have = fft_reg_info(L, cols, &nl, &lds);
             CHECK(have == want);
             if (have) {
