@@ -47,11 +47,13 @@ GMAX, GMAX_HARD = 4, 6
 HOLD = 24      # points a middle group holds across its barrier
 HOLD_IN = 32   # points a thread loads before its first DFT
 HOLD_OUT = 16  # even-phase outputs kept until the odd phase stores both
-# Plans that fit the LDS cap exist up to 2430 points, but a column pass of
-# such lines holds one line per workgroup (8-byte segments per row): the
-# 2250-point y pass of the 3-D disk workload took 75 ms against 60 ms with the
-# general kernel, so the table stops at 2048.
-LMIN, LMAX = 16, 2048
+# Column plans stop at 2304 points.  With 256-thread workgroups and a 40 KB
+# cap a 2250-point column workgroup held one line (8-byte segments per row),
+# and the y pass of the 3-D disk workload took 75 ms against 60 ms with the
+# general kernel; with 512 threads and 80 KB it holds two lines, and that pass
+# takes 51 ms against 58.  Rows are contiguous, so their plans go on to 4608
+# points (one row per workgroup past 3600).
+LMIN, LMAX = 16, 2304
 LMAX_ROWS = 4608
 
 # real operations per point of a small DFT (additions and multiplications,

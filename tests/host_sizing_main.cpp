@@ -181,15 +181,15 @@ int main() {
                 CHECK(zz_work_bytes(n_ant, n_src, prec, cap) <= cap || n_ant > 1024);
             }
 
-    // ---- planned FFT table: every even 5-smooth length 16..2048 has a row
-    // and a column plan, and 2050..4608 a row plan, within the LDS budget (16
+    // ---- planned FFT table: every even 5-smooth length 16..2304 has a row
+    // and a column plan, and 2306..4608 a row plan, within the LDS budget (16
     // wavefronts per compute unit: 80 KB per 512-thread workgroup); nothing
     // else has one; column plans take a power of two of lines, up to 128
     for (int L = 2; L <= 4700; ++L) {
         int nl = 0;
         size_t lds = 0;
         for (bool cols : {false, true}) {
-            const bool want = L >= 16 && L <= (cols ? 2048 : 4608) && L % 2 == 0 && smooth5(L);
+            const bool want = L >= 16 && L <= (cols ? 2304 : 4608) && L % 2 == 0 && smooth5(L);
             const bool have = fft_reg_info(L, cols, &nl, &lds);
             CHECK(have == want);
             if (have) {

@@ -78,8 +78,8 @@ def test_small_and_3d_grids(gpu_lib, ctx, seed, n_ant, radius, three_d):
 @pytest.mark.parametrize("radius", [450.0, 600.0])
 def test_rows_longer_than_2048(gpu_lib, ctx, radius):
     """Row plans go up to 4608 points (rows are contiguous, so a workgroup of
-    one or two long rows still reads whole lines); column plans stop at 2048,
-    and longer columns take the general kernel in the same call."""
+    one or two long rows still reads whole lines), column plans up to 2304
+    (1728- and 2250-point columns here)."""
     p = synth.small_problem(55, n_ant=20, n_src=300, n_freq=1, three_d=False, radius=radius,
                             f_lo=150e6, f_hi=170e6)
     info, err = _check(gpu_lib, ctx, p, 0, 1e-6, gpu_lib.DIM_2D | gpu_lib.NO_LATTICE)
