@@ -44,6 +44,20 @@ def test_small_2d_eps_sweep(gpu_lib, ctx, eps, no_lattice):
     assert oracle.rel_l2(v, ref) <= eps
 
 
+@pytest.mark.parametrize("eps", [1e-13, 1e-14])
+def test_widest_kernels_at_the_smallest_eps(gpu_lib, ctx, eps):
+    # the smallest accepted eps: FP64 grids and the widest spreading kernels
+    # (w = 15 and 16), whose staged first-cell offsets are the largest.  The
+    # error at 1e-14 sits just under eps (9.96e-15), so the spread order is
+    # fixed (FV_DETERMINISTIC) and the result does not move between runs.
+    p = synth.small_problem(33, n_ant=40, n_src=700, n_freq=3, hex_layout=True)
+    v, rep = _run(gpu_lib, ctx, p, eps=eps, flags=gpu_lib.NO_LATTICE | gpu_lib.DETERMINISTIC)
+    assert rep["lattice"] == 0 and rep["prec_bits"] == 64 and rep["w"] >= 15
+    err = oracle.rel_l2(v, oracle.direct_problem(p))
+    print(f"eps {eps:.0e}: w={rep['w']} rel_l2={err:.2e}", flush=True)
+    assert err <= eps
+
+
 @pytest.mark.parametrize("no_lattice", [False, True])
 def test_eps_sweep_error_is_monotone(gpu_lib, ctx, no_lattice):
     p = synth.small_problem(32, n_ant=30, n_src=500, n_freq=2, hex_layout=True)
