@@ -335,10 +335,11 @@ def test_device_output_must_be_16_byte_aligned(gpu_lib, ctx):
 
 def test_repeated_type3_after_other_paths_share_the_workspace(gpu_lib, ctx):
     """A type-3 launch whose tables match the last ones uploaded to its
-    workspace skips the upload.  Between two identical calls the workspace is
-    used by the lattice path, the matrix-core direct sum and a smaller type-3
-    layout, each of which overwrites its start; the second call must upload
-    again and give the first call's result bit for bit (deterministic order)."""
+    workspace skips the upload (and the modes' deconvolution tables).  Between
+    two identical calls the workspace is used by the lattice path, the
+    matrix-core direct sum, a smaller type-3 layout and a device batch, each of
+    which overwrites its start; the next call must upload again and give the
+    first call's result bit for bit (deterministic order)."""
     fl = gpu_lib.NO_LATTICE | gpu_lib.DETERMINISTIC
     p = synth.config1()
     v0, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=fl)
@@ -349,4 +350,17 @@ def test_repeated_type3_after_other_paths_share_the_workspace(gpu_lib, ctx):
         _run(gpu_lib, ctx, other, eps=1e-6, flags=ofl)
         v2, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=fl)
         assert np.array_equal(v0, v2)
+    # a device batch of type-3 problems (its own layouts in the same workspace)
+    import torch
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda:0").contiguous()
+    items = []
+    for q in (synth.small_problem(6, n_ant=12, n_src=50, n_freq=2), small):
+        items.append(dict(ant_enu=d(q.ant_enu), src_lmn=d(q.src_lmn), freq_hz=d(q.freq_hz), flux=d(q.flux),
+                          beam=d(q.beam) if q.beam is not None else None,
+                          vis=torch.zeros(q.n_freq, q.n_pairs, 2, dtype=torch.float64, device="cuda:0"),
+                          eps=1e-6, flags=fl))
+    ctx.simulate_batch_dev(items)
+    torch.cuda.synchronize()
+    v3, _ = _run(gpu_lib, ctx, p, eps=1e-6, flags=fl)
+    assert np.array_equal(v0, v3)
     assert oracle.rel_l2(v0, oracle.direct_problem(p)) < 1e-6
